@@ -1,0 +1,433 @@
+/*
+ * DiffCloud hot-path oracle: plain, slow, obviously-correct CPU reference.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's CPU-baseline
+ * leg may load this library.  The product path (the HIP library under paper_2204_03139_amd/)
+ * never calls it, and the two share no code: no headers, no helpers, no tables.
+ *
+ * What it computes (arXiv 2204.03139):
+ *   - area-weighted face choice and barycentric point sampling   (Sec. III-B, Eq. 3)
+ *   - bidirectional Chamfer distance, Eq. 1, and the unidirectional sim->real sum, Eq. 2
+ *                                                                   (Sec. III-A)
+ *   - the chain rule to mesh vertices through Eq. 4, with the Chamfer gradient taken through
+ *     the chosen nearest neighbours                                 (Sec. III-B, III-C)
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ *   - faces are drawn i.i.d. with replacement, P(f) proportional to area, by inverse CDF
+ *     with an upper-bound search (first k with C_k > r*S); zero-area faces are never drawn;
+ *     a zero or non-finite total area is an error;
+ *   - barycentric weights follow the square-root construction of Osada et al. 2002
+ *     (u = 1 - sqrt(r1), v = sqrt(r1)(1 - r2), w = sqrt(r1) r2), so u + v + w = 1;
+ *   - the nearest neighbour is decided by the canonical single-precision squared distance
+ *     fmaf(dz,dz, fmaf(dy,dy, dx*dx)) with dx = ax - bx rounded to float, ties to the smallest
+ *     index; distances, losses and gradients are then evaluated in double;
+ *   - random words: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), counter (i, t, 0, 0),
+ *     key (seed, 0); word layout per point: w0 = low 32 bits of x0, w1 = high 32 bits of x0,
+ *     w2 = high 32 bits of x1, w3 = high 32 bits of x2.
+ *
+ * Built with -O2 -ffp-contract=off, so no expression is fused unless written as fma.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_ERR_INVALID (-1)
+#define ORC_ERR_DEGENERATE (-5)
+
+/* ---------------------------------------------------------------- Philox4x64-10 ---------- */
+/* Salmon et al. 2011, Sec. 4: round function on four 64-bit words with two multipliers,
+ * a Weyl-sequence key schedule, ten rounds. */
+static void mulhilo64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo) {
+    unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += W0; k1 += W1; }
+        uint64_t hi0, lo0, hi1, lo1;
+        mulhilo64(M0, x0, &hi0, &lo0);
+        mulhilo64(M1, x2, &hi1, &lo1);
+        uint64_t y0 = hi1 ^ x1 ^ k0;
+        uint64_t y1 = lo1;
+        uint64_t y2 = hi0 ^ x3 ^ k1;
+        uint64_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Four words per (frame t, point i) for the sampler, from (seed, t, i). */
+void orc_words_from_seed(uint64_t seed, int T, int N, uint32_t *words) {
+    for (int t = 0; t < T; ++t)
+        for (int i = 0; i < N; ++i) {
+            uint64_t c[4] = {(uint64_t)i, (uint64_t)t, 0, 0}, k[2] = {seed, 0}, o[4];
+            orc_philox4x64_10(c, k, o);
+            uint32_t *w = words + ((size_t)t * N + i) * 4;
+            w[0] = (uint32_t)o[0];
+            w[1] = (uint32_t)(o[0] >> 32);
+            w[2] = (uint32_t)(o[1] >> 32);
+            w[3] = (uint32_t)(o[2] >> 32);
+        }
+}
+
+/* ---------------------------------------------------------------- sampling (Sec. III-B) -- */
+/* Triangle area in double from float corners: A = |(p2-p1) x (p3-p1)| / 2, every product and
+ * difference rounded in double (no fused operations), the squared norm summed left to right. */
+static double tri_area(const float *p1, const float *p2, const float *p3) {
+    double e1x = (double)p2[0] - (double)p1[0];
+    double e1y = (double)p2[1] - (double)p1[1];
+    double e1z = (double)p2[2] - (double)p1[2];
+    double e2x = (double)p3[0] - (double)p1[0];
+    double e2y = (double)p3[1] - (double)p1[1];
+    double e2z = (double)p3[2] - (double)p1[2];
+    double cx = e1y * e2z - e1z * e2y;
+    double cy = e1z * e2x - e1x * e2z;
+    double cz = e1x * e2y - e1y * e2x;
+    double n2 = cx * cx + cy * cy + cz * cz;
+    return 0.5 * sqrt(n2);
+}
+
+int orc_face_areas(const float *verts, const int32_t *faces, int V, int F, double *areas) {
+    for (int f = 0; f < F; ++f) {
+        const int32_t *fv = faces + 3 * (size_t)f;
+        if (fv[0] < 0 || fv[0] >= V || fv[1] < 0 || fv[1] >= V || fv[2] < 0 || fv[2] >= V)
+            return ORC_ERR_INVALID;
+        areas[f] = tri_area(verts + 3 * (size_t)fv[0], verts + 3 * (size_t)fv[1],
+                            verts + 3 * (size_t)fv[2]);
+    }
+    return ORC_OK;
+}
+
+/* Inclusive running sum C_k = C_{k-1} + A_k, left to right, in double. */
+int orc_area_cdf(const double *areas, int F, double *cdf) {
+    double s = 0.0;
+    for (int f = 0; f < F; ++f) {
+        s = s + areas[f];
+        cdf[f] = s;
+    }
+    if (!(s > 0.0) || !isfinite(s)) return ORC_ERR_DEGENERATE;
+    return ORC_OK;
+}
+
+/* Face of one draw: r = (53 high bits of the 64-bit word) * 2^-53 in [0,1), target = r*S,
+ * answer = first k with C_k > target; if rounding leaves none, the last face of nonzero area. */
+int orc_pick_face(const double *areas, const double *cdf, int F, uint32_t w_lo, uint32_t w_hi) {
+    uint64_t w = ((uint64_t)w_hi << 32) | (uint64_t)w_lo;
+    double r = (double)(w >> 11) * 0x1p-53;
+    double S = cdf[F - 1];
+    double target = r * S;
+    for (int k = 0; k < F; ++k)
+        if (cdf[k] > target) return k;
+    for (int k = F - 1; k >= 0; --k)
+        if (areas[k] > 0.0) return k;
+    return -1;
+}
+
+/* Point on triangle (p1,p2,p3) by Eq. 3 with Osada's square-root weights:
+ * r1, r2 = (word >> 8) * 2^-24 (exact floats in [0,1)); s = sqrt(r1) correctly rounded;
+ * u = 1 - s, v = s (1 - r2), w = s r2; x = u p1 + v p2 + w p3 evaluated as
+ * fma(w, p3, fma(v, p2, u*p1)) per coordinate, in single precision. */
+void orc_barycentric(const float *p1, const float *p2, const float *p3, uint32_t w_r1,
+                     uint32_t w_r2, float *x, float *bary) {
+    float r1 = (float)(w_r1 >> 8) * 0x1p-24f;
+    float r2 = (float)(w_r2 >> 8) * 0x1p-24f;
+    float s = sqrtf(r1);
+    float u = 1.0f - s;
+    float v = s * (1.0f - r2);
+    float w = s * r2;
+    for (int c = 0; c < 3; ++c) x[c] = fmaf(w, p3[c], fmaf(v, p2[c], u * p1[c]));
+    bary[0] = u;
+    bary[1] = v;
+    bary[2] = w;
+}
+
+/* Sample N points per frame from a [T,V,3] mesh trajectory with fixed faces [F,3]. */
+int orc_sample_surface(const float *verts, const int32_t *faces, int T, int V, int F, int N,
+                       const uint32_t *words, float *points, int32_t *face_idx, float *bary,
+                       double *areas_out, double *cdf_out) {
+    if (T <= 0 || V <= 0 || F <= 0 || N <= 0) return ORC_ERR_INVALID;
+    double *A = (double *)malloc(sizeof(double) * (size_t)F);
+    double *C = (double *)malloc(sizeof(double) * (size_t)F);
+    int status = ORC_OK;
+    for (int t = 0; t < T && status == ORC_OK; ++t) {
+        const float *vt = verts + (size_t)t * V * 3;
+        int rc = orc_face_areas(vt, faces, V, F, A);
+        if (rc != ORC_OK) { status = rc; break; }
+        rc = orc_area_cdf(A, F, C);
+        if (areas_out) memcpy(areas_out + (size_t)t * F, A, sizeof(double) * F);
+        if (cdf_out) memcpy(cdf_out + (size_t)t * F, C, sizeof(double) * F);
+        if (rc != ORC_OK) { status = rc; break; }
+        for (int i = 0; i < N; ++i) {
+            const uint32_t *w = words + ((size_t)t * N + i) * 4;
+            int f = orc_pick_face(A, C, F, w[0], w[1]);
+            const int32_t *fv = faces + 3 * (size_t)f;
+            size_t o = (size_t)t * N + i;
+            face_idx[o] = f;
+            orc_barycentric(vt + 3 * (size_t)fv[0], vt + 3 * (size_t)fv[1], vt + 3 * (size_t)fv[2],
+                            w[2], w[3], points + 3 * o, bary + 3 * o);
+        }
+    }
+    free(A);
+    free(C);
+    return status;
+}
+
+/* ---------------------------------------------------------------- Chamfer (Sec. III-A) --- */
+/* Canonical single-precision squared distance (the quantity that decides the argmin). */
+static float dist_f32(const float *q, const float *p) {
+    float dx = q[0] - p[0];
+    float dy = q[1] - p[1];
+    float dz = q[2] - p[2];
+    return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
+/* The same squared distance evaluated in double from the float inputs. */
+static double dist_f64(const float *q, const float *p) {
+    double dx = (double)q[0] - (double)p[0];
+    double dy = (double)q[1] - (double)p[1];
+    double dz = (double)q[2] - (double)p[2];
+    return dx * dx + dy * dy + dz * dz;
+}
+
+/* For every query q_i: idx[i] = argmin_j of the canonical distance (smallest j on ties),
+ * d32[i] = that distance, d64[i] = the double twin at the same index.  Brute force. */
+void orc_nearest(const float *Q, int Nq, const float *P, int Np, int32_t *idx, float *d32,
+                 double *d64, int nthreads) {
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+#endif
+    for (int i = 0; i < Nq; ++i) {
+        const float *q = Q + 3 * (size_t)i;
+        float best = INFINITY;
+        int bj = -1;
+        for (int j = 0; j < Np; ++j) {
+            float d = dist_f32(q, P + 3 * (size_t)j);
+            if (bj < 0 || d < best) { best = d; bj = j; }
+        }
+        idx[i] = bj;
+        d32[i] = best;
+        d64[i] = dist_f64(q, P + 3 * (size_t)bj);
+    }
+    (void)nthreads;
+}
+
+/* Per-frame weights of the two directions: Eq. 1 averages each direction, Eq. 2 sums the
+ * sim->real direction only. */
+static void red_weights(int reduction, int Na, int Nb, double *alpha, double *beta) {
+    if (reduction == 1) { *alpha = 1.0; *beta = 0.0; }
+    else { *alpha = 1.0 / (double)Na; *beta = 1.0 / (double)Nb; }
+}
+
+/* Bidirectional nearest neighbours per frame and loss[t] = w_t (alpha sum_i d_a + beta sum_j d_b)
+ * with double-precision distances, accumulated in index order. */
+int orc_chamfer(const float *a, const float *b, int T, int Na, int Nb, int reduction,
+                const float *frame_w, int32_t *idx_a, float *d32a, double *d64a, int32_t *idx_b,
+                float *d32b, double *d64b, double *loss, int nthreads) {
+    if (T <= 0 || Na <= 0 || Nb <= 0 || (reduction != 0 && reduction != 1)) return ORC_ERR_INVALID;
+    double alpha, beta;
+    red_weights(reduction, Na, Nb, &alpha, &beta);
+    for (int t = 0; t < T; ++t) {
+        const float *at = a + (size_t)t * Na * 3, *bt = b + (size_t)t * Nb * 3;
+        size_t oa = (size_t)t * Na, ob = (size_t)t * Nb;
+        orc_nearest(at, Na, bt, Nb, idx_a + oa, d32a + oa, d64a + oa, nthreads);
+        orc_nearest(bt, Nb, at, Na, idx_b + ob, d32b + ob, d64b + ob, nthreads);
+        double sa = 0.0, sb = 0.0;
+        for (int i = 0; i < Na; ++i) sa += d64a[oa + i];
+        for (int j = 0; j < Nb; ++j) sb += d64b[ob + j];
+        double wt = frame_w ? (double)frame_w[t] : 1.0;
+        loss[t] = wt * (alpha * sa + beta * sb);
+    }
+    return ORC_OK;
+}
+
+/* Gradient of sum_t g_t * loss[t] with the nearest neighbours held fixed (a subgradient at
+ * ties).  d/da_i of alpha |a_i - b_{idx_a[i]}|^2 is 2 alpha (a_i - b_{idx_a[i]}); every b_j whose
+ * neighbour is a_i adds 2 beta (a_i - b_j).  ga_abs collects the sum of absolute contributions
+ * per component (for condition-aware tolerances).  gb (optional) is the mirror image. */
+int orc_chamfer_grad(const float *a, const float *b, const int32_t *idx_a, const int32_t *idx_b,
+                     int T, int Na, int Nb, int reduction, const float *frame_w,
+                     const double *grad_loss, double *ga, double *ga_abs, double *gb,
+                     double *gb_abs) {
+    if (T <= 0 || Na <= 0 || Nb <= 0 || (reduction != 0 && reduction != 1)) return ORC_ERR_INVALID;
+    double alpha, beta;
+    red_weights(reduction, Na, Nb, &alpha, &beta);
+    memset(ga, 0, sizeof(double) * (size_t)T * Na * 3);
+    if (ga_abs) memset(ga_abs, 0, sizeof(double) * (size_t)T * Na * 3);
+    if (gb) memset(gb, 0, sizeof(double) * (size_t)T * Nb * 3);
+    if (gb_abs) memset(gb_abs, 0, sizeof(double) * (size_t)T * Nb * 3);
+    for (int t = 0; t < T; ++t) {
+        double s = (grad_loss ? grad_loss[t] : 1.0) * (frame_w ? (double)frame_w[t] : 1.0);
+        const float *at = a + (size_t)t * Na * 3, *bt = b + (size_t)t * Nb * 3;
+        double *gat = ga + (size_t)t * Na * 3;
+        double *gaa = ga_abs ? ga_abs + (size_t)t * Na * 3 : NULL;
+        double *gbt = gb ? gb + (size_t)t * Nb * 3 : NULL;
+        double *gba = gb_abs ? gb_abs + (size_t)t * Nb * 3 : NULL;
+        for (int i = 0; i < Na; ++i) {
+            int j = idx_a[(size_t)t * Na + i];
+            for (int c = 0; c < 3; ++c) {
+                double diff = (double)at[3 * (size_t)i + c] - (double)bt[3 * (size_t)j + c];
+                double g = 2.0 * alpha * s * diff;
+                gat[3 * (size_t)i + c] += g;
+                if (gaa) gaa[3 * (size_t)i + c] += fabs(g);
+                if (gbt) gbt[3 * (size_t)j + c] -= g;
+                if (gba) gba[3 * (size_t)j + c] += fabs(g);
+            }
+        }
+        if (beta != 0.0)
+            for (int j = 0; j < Nb; ++j) {
+                int i = idx_b[(size_t)t * Nb + j];
+                for (int c = 0; c < 3; ++c) {
+                    double diff = (double)at[3 * (size_t)i + c] - (double)bt[3 * (size_t)j + c];
+                    double g = 2.0 * beta * s * diff;
+                    gat[3 * (size_t)i + c] += g;
+                    if (gaa) gaa[3 * (size_t)i + c] += fabs(g);
+                    if (gbt) gbt[3 * (size_t)j + c] -= g;
+                    if (gba) gba[3 * (size_t)j + c] += fabs(g);
+                }
+            }
+    }
+    return ORC_OK;
+}
+
+/* Eq. 4: dx_i/dp_{i,c} = bary_c(i) * I, so vertex v collects bary_c(i) * g_i over every sampled
+ * point i whose face has v as corner c.  No gradient flows through the face choice or areas. */
+int orc_sample_grad(const double *gpoints, const double *gpoints_abs, const int32_t *faces,
+                    const int32_t *face_idx, const float *bary, int T, int V, int F, int N,
+                    double *gverts, double *gverts_abs) {
+    if (T <= 0 || V <= 0 || F <= 0 || N <= 0) return ORC_ERR_INVALID;
+    memset(gverts, 0, sizeof(double) * (size_t)T * V * 3);
+    if (gverts_abs) memset(gverts_abs, 0, sizeof(double) * (size_t)T * V * 3);
+    for (int t = 0; t < T; ++t)
+        for (int i = 0; i < N; ++i) {
+            size_t o = (size_t)t * N + i;
+            int f = face_idx[o];
+            if (f < 0 || f >= F) return ORC_ERR_INVALID;
+            for (int c = 0; c < 3; ++c) {
+                int v = faces[3 * (size_t)f + c];
+                double wc = (double)bary[3 * o + c];
+                for (int k = 0; k < 3; ++k) {
+                    double g = wc * gpoints[3 * o + k];
+                    gverts[((size_t)t * V + v) * 3 + k] += g;
+                    if (gverts_abs) {
+                        double ga = gpoints_abs ? gpoints_abs[3 * o + k] : fabs(gpoints[3 * o + k]);
+                        gverts_abs[((size_t)t * V + v) * 3 + k] += fabs(wc) * ga;
+                    }
+                }
+            }
+        }
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------------- finite differences ----- */
+/* Points of Eq. 3 in double from double vertices, with face choice and weights held fixed. */
+void orc_points_f64(const double *verts, const int32_t *faces, const int32_t *face_idx,
+                    const float *bary, int T, int V, int N, double *out) {
+    for (int t = 0; t < T; ++t)
+        for (int i = 0; i < N; ++i) {
+            size_t o = (size_t)t * N + i;
+            const int32_t *fv = faces + 3 * (size_t)face_idx[o];
+            for (int k = 0; k < 3; ++k) {
+                double x = 0.0;
+                for (int c = 0; c < 3; ++c)
+                    x += (double)bary[3 * o + c] * verts[((size_t)t * V + fv[c]) * 3 + k];
+                out[3 * o + k] = x;
+            }
+        }
+}
+
+/* Loss of Eq. 1/2 summed over frames, all in double, neighbours searched in double.
+ * If idx_a / idx_b are given they are used instead of searching (frozen neighbours). */
+double orc_loss_f64(const double *a, const float *b, int T, int Na, int Nb, int reduction,
+                    const float *frame_w, const int32_t *idx_a, const int32_t *idx_b,
+                    int32_t *idx_a_out, int32_t *idx_b_out, int nthreads) {
+    double alpha, beta;
+    red_weights(reduction, Na, Nb, &alpha, &beta);
+    double total = 0.0;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#endif
+    double *da = (double *)malloc(sizeof(double) * (size_t)Na);
+    double *db = (double *)malloc(sizeof(double) * (size_t)Nb);
+    for (int t = 0; t < T; ++t) {
+        const double *at = a + (size_t)t * Na * 3;
+        const float *bt = b + (size_t)t * Nb * 3;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+#endif
+        for (int i = 0; i < Na; ++i) {
+            double best = INFINITY;
+            int bj = -1;
+            if (idx_a) {
+                bj = idx_a[(size_t)t * Na + i];
+                double dx = at[3 * (size_t)i] - bt[3 * (size_t)bj];
+                double dy = at[3 * (size_t)i + 1] - bt[3 * (size_t)bj + 1];
+                double dz = at[3 * (size_t)i + 2] - bt[3 * (size_t)bj + 2];
+                best = dx * dx + dy * dy + dz * dz;
+            } else {
+                for (int j = 0; j < Nb; ++j) {
+                    double dx = at[3 * (size_t)i] - bt[3 * (size_t)j];
+                    double dy = at[3 * (size_t)i + 1] - bt[3 * (size_t)j + 1];
+                    double dz = at[3 * (size_t)i + 2] - bt[3 * (size_t)j + 2];
+                    double d = dx * dx + dy * dy + dz * dz;
+                    if (bj < 0 || d < best) { best = d; bj = j; }
+                }
+            }
+            da[i] = best;
+            if (idx_a_out) idx_a_out[(size_t)t * Na + i] = bj;
+        }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+#endif
+        for (int j = 0; j < Nb; ++j) {
+            double best = INFINITY;
+            int bi = -1;
+            if (beta == 0.0 && !idx_b_out) { db[j] = 0.0; continue; }
+            if (idx_b) {
+                bi = idx_b[(size_t)t * Nb + j];
+                double dx = at[3 * (size_t)bi] - bt[3 * (size_t)j];
+                double dy = at[3 * (size_t)bi + 1] - bt[3 * (size_t)j + 1];
+                double dz = at[3 * (size_t)bi + 2] - bt[3 * (size_t)j + 2];
+                best = dx * dx + dy * dy + dz * dz;
+            } else {
+                for (int i = 0; i < Na; ++i) {
+                    double dx = at[3 * (size_t)i] - bt[3 * (size_t)j];
+                    double dy = at[3 * (size_t)i + 1] - bt[3 * (size_t)j + 1];
+                    double dz = at[3 * (size_t)i + 2] - bt[3 * (size_t)j + 2];
+                    double d = dx * dx + dy * dy + dz * dz;
+                    if (bi < 0 || d < best) { best = d; bi = i; }
+                }
+            }
+            db[j] = best;
+            if (idx_b_out) idx_b_out[(size_t)t * Nb + j] = bi;
+        }
+        double sa = 0.0, sb = 0.0;
+        for (int i = 0; i < Na; ++i) sa += da[i];
+        if (beta != 0.0)
+            for (int j = 0; j < Nb; ++j) sb += db[j];
+        total += (frame_w ? (double)frame_w[t] : 1.0) * (alpha * sa + beta * sb);
+    }
+    free(da);
+    free(db);
+    (void)nthreads;
+    return total;
+}
+
+int orc_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
