@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Benchmark of the DiffCloud hot path on one MI355X.
+
+One step = the whole path over one batch of synthetic input, inputs resident in HBM:
+  sample_surface (areas, FP64 CDF, face choice, points)  ->  chamfer_fwd (both directions + loss)
+  ->  chamfer_bwd (through the saved neighbours)  ->  sample_surface_bwd (Eq. 4, to vertices)
+for every frame of the 100-frame, 100x100-grid, 65,536 x 65,536-point trajectory workload.
+value = sum over frames of Na*Nb point pairs / seconds per step (whole job, one GPU).
+
+Prints ONE JSON line.  The roofline object refers to the all-pairs kernel (its device time is
+measured with HIP events on the stream it runs on, inside the timed region); the cpu_baseline
+object times the CPU oracle on a bounded sample of the same workload on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "fwd+bwd Chamfer point-pairs/s; p50/p99 request latency; BF16-MFMA vs FP32"
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published fp32 vector peak
+FLOPS_PER_PAIR = 8                # 3 sub, 3 mul, 2 add: one squared distance
+
+
+def _args():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=4, choices=[1, 2, 4])
+    ap.add_argument("--precision", choices=["fp32", "bf16", "both"], default="both")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle baseline sample (0 disables it)")
+    ap.add_argument("--frames", type=int, default=None, help="override the frame count")
+    return ap.parse_args()
+
+
+def run_path(p, torch, w, precision, steps, warmup):
+    """Time `steps` full steps of one precision path; returns (ms_per_step, kernel_times)."""
+    ctx = p.default_context(0)
+    T, V, Na, Nb = w["T"], w["V"], w["Na"], w["Nb"]
+    dev = torch.device("cuda", 0)
+    verts = torch.from_numpy(w["verts"]).to(dev)
+    faces = torch.from_numpy(w["faces"]).to(dev)
+    obs = torch.from_numpy(w["observed"]).to(dev)
+    ones = torch.ones(T, dtype=torch.float64, device=dev)
+    pts = torch.empty((T, Na, 3), dtype=torch.float32, device=dev)
+    fi = torch.empty((T, Na), dtype=torch.int32, device=dev)
+    ba = torch.empty((T, Na, 3), dtype=torch.float32, device=dev)
+    fwd = dict(dist_a=torch.empty((T, Na), device=dev), idx_a=torch.empty((T, Na), dtype=torch.int32,
+                                                                          device=dev),
+               dist_b=torch.empty((T, Nb), device=dev), idx_b=torch.empty((T, Nb), dtype=torch.int32,
+                                                                          device=dev),
+               loss=torch.empty(T, dtype=torch.float64, device=dev))
+    ga = torch.empty((T, Na, 3), dtype=torch.float32, device=dev)
+    gv = torch.empty((T, V, 3), dtype=torch.float32, device=dev)
+
+    def step():
+        p.sample_surface(verts, faces, Na, seed=w["seed"], out=(pts, fi, ba), ctx=ctx)
+        p.chamfer_fwd(pts, obs, precision=precision, out=fwd, ctx=ctx)
+        p.chamfer_bwd(ones, pts, obs, fwd["idx_a"], fwd["idx_b"], out=(ga, None), ctx=ctx)
+        p.sample_surface_bwd(ga, faces, fi, ba, V, out=gv, ctx=ctx)
+
+    for _ in range(warmup):
+        step()
+    ctx.sync()
+    ctx.kernel_times(reset=True)
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.profile(False)
+    ms = e0.elapsed_time(e1) / steps
+    kt = ctx.kernel_times(reset=True)
+    ctx.sync()
+    stats = ctx.stats()
+    loss = fwd["loss"].sum().item()
+    return ms, kt, stats, loss
+
+
+def cpu_baseline(w, seconds):
+    """Time the oracle (as it stands) on a bounded sample of frame 0: its sampling, nearest
+    neighbours for a subset of queries in both directions against the full clouds, and the
+    gradient formulas; report point pairs per second."""
+    import oracle
+    threads = oracle.max_threads()
+    verts, faces, obs = w["verts"][:1], w["faces"], w["observed"][0]
+    Na, Nb = w["Na"], w["Nb"]
+    t0 = time.perf_counter()
+    pts, fi, ba = oracle.sample_surface(verts, faces, Na, seed=w["seed"])
+    t_sample = time.perf_counter() - t0
+    # calibrate on a small slice, then size the sample to the requested time
+    q = 256
+    t0 = time.perf_counter()
+    oracle.nearest(pts[0][:q], obs)
+    rate = q * Nb / max(time.perf_counter() - t0, 1e-6)
+    nq = int(min(Na, max(q, rate * seconds / 2 / Nb)))
+    t0 = time.perf_counter()
+    ia, _, _ = oracle.nearest(pts[0][:nq], obs)
+    ib, _, _ = oracle.nearest(obs[:nq], pts[0])
+    t_nn = time.perf_counter() - t0
+    pairs = nq * Nb + nq * Na
+    return dict(value=pairs / (t_nn + t_sample), unit="point-pairs/s", cores=threads,
+                kind="oracle",
+                sample=f"frame 0 of the workload: its sampling ({Na} points) plus {nq} queries "
+                       f"per direction searched exhaustively against the full {Nb}/{Na}-point "
+                       f"clouds ({pairs:.3e} pairs, {t_nn + t_sample:.1f} s on {threads} threads)")
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2204_03139_amd as p
+    from workloads import gen
+    p.load()
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(2)
+    w = gen.workload(a.workload, T=a.frames)
+    T, Na, Nb = w["T"], w["Na"], w["Nb"]
+    pairs = float(T) * Na * Nb
+    paths = {}
+    todo = {"fp32": [0], "bf16": [1], "both": [0, 1]}[a.precision]
+    for prec in todo:
+        name = "fp32" if prec == 0 else "bf16_refine"
+        try:
+            ms, kt, stats, loss = run_path(p, torch, w, prec, a.steps, a.warmup)
+        except p.DCError as e:
+            paths[name] = dict(error=str(e))
+            continue
+        nn_ms, nn_n = kt["all_pairs"]
+        per_launch_pairs = pairs  # one launch handles one direction over every frame
+        avg = nn_ms / max(nn_n, 1)
+        paths[name] = dict(pairs_per_s=pairs / (ms * 1e-3), ms_per_step=ms,
+                           kernel_ms={k: v[0] / a.steps for k, v in kt.items()},
+                           kernel_launches={k: v[1] // a.steps for k, v in kt.items()},
+                           all_pairs_avg_launch_ms=avg,
+                           all_pairs_pairs_per_s=per_launch_pairs / (avg * 1e-3) if avg else None,
+                           loss_sum=loss, screen_stats=stats)
+    ok = {k: v for k, v in paths.items() if "error" not in v}
+    if not ok:
+        print(json.dumps(dict(metric=METRIC, error=paths)))
+        sys.exit(1)
+    best = max(ok, key=lambda k: ok[k]["pairs_per_s"])
+    bp = ok[best]
+    achieved = FLOPS_PER_PAIR * bp["all_pairs_pairs_per_s"] / 1e12
+    line = dict(
+        metric=METRIC, value=bp["pairs_per_s"], unit="point-pairs/s", n_gpus=1, steps=a.steps,
+        warmup=a.warmup, ms_per_step=bp["ms_per_step"], higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f32" if best == "fp32" else "bf16+f32", data="synthetic",
+        config=dict(workload=w["name"], frames=T, n_sim=Na, n_obs=Nb, grid=gen.CONFIGS[a.workload]
+                    .get("n"), faces=w["F"], precision=best, reduction="Eq. 1 (bidirectional mean)",
+                    pairs_per_step=pairs),
+        roofline=dict(bound="alu", achieved=achieved, peak=FP32_VECTOR_PEAK_TFLOPS,
+                      unit="TFLOP/s", frac=achieved / FP32_VECTOR_PEAK_TFLOPS, traffic=None,
+                      kernel="all-pairs nearest-neighbour kernel, one direction over all frames",
+                      flops_per_pair=FLOPS_PER_PAIR),
+        paths=paths,
+    )
+    if a.cpu_seconds > 0:
+        line["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * diffcloud.h - C ABI of the MI355X (gfx950) DiffCloud hot-path library, libdiffcloud.so.
+ *
+ * The library computes, on one GPU, the data-parallel part of the DiffCloud gradient pipeline
+ * (arXiv 2204.03139): area-weighted point sampling from triangle-mesh trajectories
+ * (Sec. III-B, Eq. 3), the bidirectional or unidirectional Chamfer distance to an observed cloud
+ * (Sec. III-A, Eq. 1 and Eq. 2), and the backward pass to per-vertex gradients through Eq. 4,
+ * for every frame of a trajectory (Sec. III-C).
+ *
+ * Conventions shared by every entry point
+ *  - All arrays are dense, row-major, little-endian.  Coordinates are float32 triples (x, y, z).
+ *    [T,N,3] means frame-major: element (t, i, k) sits at ((t*N)+i)*3+k.
+ *  - Pointers marked "device" must be device memory of the context's GPU (for example a torch
+ *    tensor's data_ptr()).  The caller owns them; the library never frees or keeps them past the
+ *    call's stream work.  Pointers marked "host" are ordinary host memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Direct calls are
+ *    asynchronous: they validate their arguments on the host, enqueue kernels on `stream` and
+ *    return.  Calls that share one context must be ordered on one stream (or otherwise not overlap
+ *    in time), since they share the context's scratch memory.
+ *  - Every entry point returns a status code.  No exception crosses the ABI.  Argument errors are
+ *    reported immediately.  Errors that only the device can see (a face index outside [0, V), a
+ *    frame whose total area is zero or not finite) set a sticky status word in the context, and
+ *    dc_sync() reports and clears it.  The text of the last error of the calling thread is
+ *    available from dc_last_error().
+ *  - Limits: 1 <= T <= 65535; 1 <= N, Na, Nb, V, F <= 2^24.  NaN or infinite coordinates are not
+ *    validated; they propagate and the neighbour indices they produce are unspecified.
+ */
+#ifndef DIFFCLOUD_H
+#define DIFFCLOUD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status codes */
+#define DC_OK 0
+#define DC_PENDING 1           /* dc_poll: the request is queued or running */
+#define DC_ERR_INVALID (-1)    /* bad argument (null pointer, size out of range, bad enum) */
+#define DC_ERR_NOMEM (-2)      /* a device allocation failed */
+#define DC_ERR_BUDGET (-3)     /* the work can never fit the context's HBM budget */
+#define DC_ERR_HIP (-4)        /* a HIP runtime call failed; see dc_last_error() */
+#define DC_ERR_DEGENERATE (-5) /* a frame's total surface area is zero or not finite */
+#define DC_ERR_UNSUPPORTED (-6)/* valid request this build does not support */
+
+/* precision of the all-pairs nearest-neighbour search (both give the same indices) */
+#define DC_PREC_FP32 0        /* exact single-precision search on the vector ALUs */
+#define DC_PREC_BF16_REFINE 1 /* bf16 matrix-core screen, certified, exact fp32 re-evaluation */
+
+/* reduction of the two directions into the per-frame loss */
+#define DC_RED_BIDIR_MEAN 0   /* Eq. 1: mean over a of min_b + mean over b of min_a */
+#define DC_RED_SIM2REAL_SUM 1 /* Eq. 2: sum over a (simulated) of min over b (observed) */
+
+typedef struct dc_ctx dc_ctx;
+
+/* ------------------------------------------------------------------ context */
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device memory the context
+ * may hold at once (scratch of direct calls plus resident requests of the serving loop);
+ * 0 means 64 GiB.  max_slots caps the requests the serving loop keeps in flight (0 means 64).
+ * On success *out receives the context.  Errors: DC_ERR_INVALID, DC_ERR_HIP, DC_ERR_NOMEM. */
+int dc_create(dc_ctx **out, int device, size_t hbm_budget_bytes, int max_slots);
+
+/* Wait for the serving loop to drain, free everything the context owns, destroy it. */
+int dc_destroy(dc_ctx *ctx);
+
+/* Text of the calling thread's last error ("" if none); valid until the thread's next call. */
+const char *dc_last_error(void);
+
+/* Wait for `stream`, then report and clear device-detected errors of earlier direct calls:
+ * DC_OK, DC_ERR_DEGENERATE (a frame with zero or non-finite total area; its points are NaN and
+ * its face indices -1) or DC_ERR_INVALID (a face index outside [0, V)). */
+int dc_sync(dc_ctx *ctx, void *stream);
+
+/* ------------------------------------------------------------------ sampling, Sec. III-B */
+/* Draw N points per frame on the surface of the mesh (verts[t], faces), Eq. 3.
+ *   verts    device float [T,V,3]   vertex positions per frame
+ *   faces    device int32 [F,3]     corner vertex indices, the same for every frame
+ *   seed     key of the counter-based generator, used when uniforms is NULL
+ *   uniforms device uint32 [T,N,4] or NULL: four random words per (frame, point)
+ *   points   device float [T,N,3]   out: sampled points
+ *   face_idx device int32 [T,N]     out: face of each point
+ *   bary     device float [T,N,3]   out: (u, v, w) of each point
+ * Arithmetic, per frame t:
+ *   A_f  = |(p2-p1) x (p3-p1)| / 2 in double from the float corners (no fused operations);
+ *   C_k  = C_{k-1} + A_k in double, left to right; S = C_{F-1};
+ *   face = first k with C_k > r*S, r = (53 high bits of words 0,1) * 2^-53 (word 1 is the high
+ *          half); if none, the last face with A_k > 0; zero-area faces are never drawn;
+ *   r1, r2 = (word >> 8) * 2^-24 of words 2 and 3; s = correctly rounded sqrt(r1);
+ *   u = 1-s, v = s(1-r2), w = s r2 (the square-root construction of Osada et al. 2002);
+ *   x = fma(w, p3, fma(v, p2, u*p1)) per coordinate, in float.
+ * With uniforms == NULL the words come from Philox4x64-10 (Salmon et al., SC'11) with counter
+ * (i, t, 0, 0) and key (seed, 0): words 0,1 = low, high half of output 0; word 2 = high half of
+ * output 1; word 3 = high half of output 2.
+ * Errors: DC_ERR_INVALID (argument), DC_ERR_HIP; zero or non-finite total area and bad face
+ * indices are reported by dc_sync(). */
+int dc_sample_surface(dc_ctx *ctx, const float *verts, const int32_t *faces, int T, int V, int F,
+                      int N, uint64_t seed, const uint32_t *uniforms, float *points,
+                      int32_t *face_idx, float *bary, void *stream);
+
+/* Backward of dc_sample_surface through Eq. 4 (dx_i/dp_{i,c} = bary_c(i) I):
+ *   grad_verts[t,v] = sum over points i of frame t and corners c with faces[face_idx[t,i]][c]==v
+ *                     of bary[t,i,c] * grad_points[t,i].
+ * No gradient flows through the face choice or the areas.  Sums run in a fixed order (by vertex
+ * incidence, then by point index), so the result is bitwise reproducible; no atomics are used.
+ *   grad_points device float [T,N,3]; faces, face_idx, bary as produced by dc_sample_surface;
+ *   grad_verts  device float [T,V,3], overwritten.
+ * Points whose face_idx is -1 (degenerate frame) contribute nothing.
+ * Errors: DC_ERR_INVALID, DC_ERR_HIP, DC_ERR_NOMEM, DC_ERR_BUDGET (scratch over budget). */
+int dc_sample_surface_bwd(dc_ctx *ctx, const float *grad_points, const int32_t *faces,
+                          const int32_t *face_idx, const float *bary, int T, int V, int F, int N,
+                          float *grad_verts, void *stream);
+
+/* ------------------------------------------------------------------ Chamfer, Sec. III-A */
+/* Nearest neighbours in both directions and the per-frame loss, Eq. 1 or Eq. 2.
+ *   a, b      device float [T,Na,3], [T,Nb,3]   simulated (a) and observed (b) clouds
+ *   precision DC_PREC_FP32 or DC_PREC_BF16_REFINE (same results; different speed)
+ *   reduction DC_RED_BIDIR_MEAN (Eq. 1) or DC_RED_SIM2REAL_SUM (Eq. 2)
+ *   frame_w   device float [T] or NULL (all ones): weight w_t of frame t
+ *   dist_a, idx_a  device float/int32 [T,Na] out: min over b, and its index
+ *   dist_b, idx_b  device float/int32 [T,Nb] out: min over a, and its index
+ *   loss      device double [T] out: loss[t] = w_t (alpha sum_i dist_a + beta sum_j dist_b),
+ *             alpha = 1/Na, beta = 1/Nb for Eq. 1; alpha = 1, beta = 0 for Eq. 2.
+ * The neighbour of a point is decided by the canonical float squared distance
+ *   d = fma(dz, dz, fma(dy, dy, dx*dx)), dx = ax - bx rounded to float,
+ * ties going to the smallest index; dist_* hold that float d.  Both directions are always
+ * computed (the backward of Eq. 1 needs idx_b); the loss sums the float distances in double.
+ * Errors: DC_ERR_INVALID, DC_ERR_HIP, DC_ERR_NOMEM, DC_ERR_BUDGET. */
+int dc_chamfer_fwd(dc_ctx *ctx, const float *a, const float *b, int T, int Na, int Nb,
+                   int precision, int reduction, const float *frame_w, float *dist_a,
+                   int32_t *idx_a, float *dist_b, int32_t *idx_b, double *loss, void *stream);
+
+/* Backward of dc_chamfer_fwd with the neighbours of the forward held fixed (a subgradient at
+ * ties), for the upstream gradient g_t = grad_loss[t] of loss[t]:
+ *   grad_a[t,i] = g_t w_t ( 2 alpha (a_i - b_{idx_a[i]}) + 2 beta sum_{j: idx_b[j]=i} (a_i - b_j) )
+ *   grad_b[t,j] = g_t w_t ( 2 beta (b_j - a_{idx_b[j]}) + 2 alpha sum_{i: idx_a[i]=j} (b_j - a_i) )
+ * The sums over j (resp. i) run in increasing index order after a stable, atomic-free sort by
+ * neighbour index, so results are bitwise reproducible.
+ *   grad_loss device double [T]; a, b, idx_a, idx_b, frame_w as in dc_chamfer_fwd;
+ *   grad_a device float [T,Na,3] out (overwritten); grad_b device float [T,Nb,3] or NULL.
+ * Errors: DC_ERR_INVALID, DC_ERR_HIP, DC_ERR_NOMEM, DC_ERR_BUDGET. */
+int dc_chamfer_bwd(dc_ctx *ctx, const double *grad_loss, const float *a, const float *b,
+                   const int32_t *idx_a, const int32_t *idx_b, int T, int Na, int Nb,
+                   int reduction, const float *frame_w, float *grad_a, float *grad_b,
+                   void *stream);
+
+/* Counters of the bf16 screen since the context was created (read after dc_sync):
+ *   queries    nearest-neighbour queries answered by the screened search
+ *   candidates candidate groups re-evaluated exactly
+ *   fallbacks  queries whose certificate failed and that were searched exhaustively */
+typedef struct dc_stats {
+    uint64_t queries;
+    uint64_t candidates;
+    uint64_t fallbacks;
+} dc_stats;
+int dc_get_stats(dc_ctx *ctx, dc_stats *out);
+
+/* ------------------------------------------------------------------ kernel timing */
+/* With profiling on, the direct calls bracket their kernels with HIP events on the caller's
+ * stream and accumulate the elapsed device time per category:
+ *   [0] the all-pairs nearest-neighbour kernel (exact fp32 search, or the bf16 screen)
+ *   [1] the exact re-evaluation of screened candidates
+ *   [2] sampling (areas, CDF, face choice, points)
+ *   [3] the backward kernels (Chamfer and sampling backward, their sorts)
+ * dc_get_kernel_times waits for the recorded events, returns the sums and launch counts, and
+ * resets them when `reset` is nonzero.  Profiling costs two event records per launch. */
+typedef struct dc_kernel_times {
+    double ms[4];
+    uint64_t launches[4];
+} dc_kernel_times;
+int dc_profile(dc_ctx *ctx, int enable);
+int dc_get_kernel_times(dc_ctx *ctx, dc_kernel_times *out, int reset);
+
+/* ------------------------------------------------------------------ serving loop */
+/* One calibration query: a mesh trajectory, an observed cloud sequence, and how to compare
+ * them.  All pointers are host memory, copied into context-owned device memory at admission;
+ * the caller may reuse them as soon as dc_submit returns. */
+typedef struct dc_request {
+    const float *verts;    /* host float [T,V,3] */
+    const int32_t *faces;  /* host int32 [F,3] */
+    int T, V, F;
+    int n_sim;             /* points sampled per frame (Na) */
+    const float *observed; /* host float [T,n_obs,3] */
+    int n_obs;             /* observed points per frame (Nb) */
+    uint64_t seed;         /* sampler key (the uniforms come from the counter-based generator) */
+    int precision;         /* DC_PREC_* */
+    int reduction;         /* DC_RED_* */
+    const float *frame_w;  /* host float [T] or NULL */
+} dc_request;
+
+/* Result of a request, written by the library; the caller owns it and must keep it alive until
+ * dc_poll() returns something other than DC_PENDING for its ticket. */
+typedef struct dc_result {
+    double *loss;       /* host double [T], caller-allocated; out: loss[t] */
+    float *grad_verts;  /* host float [T,V,3] caller-allocated, or NULL; out: d(sum_t loss[t])/dV */
+    double t_submit;    /* seconds (steady clock) when dc_submit accepted the request */
+    double t_admit;     /* when its device memory was granted and its work enqueued */
+    double t_done;      /* when its results were on the host */
+    int status;         /* DC_OK or an error code once done */
+} dc_result;
+
+/* Queue a request.  It is admitted once its device memory fits under the budget and a slot is
+ * free; admitted requests are batched with whatever else is waiting and run on the device
+ * alongside requests already in flight.  A request whose memory alone exceeds the budget fails
+ * with DC_ERR_BUDGET at once.  *ticket identifies it for dc_poll().  Thread-safe. */
+int dc_submit(dc_ctx *ctx, const dc_request *req, dc_result *out, uint64_t *ticket);
+
+/* DC_PENDING while queued or running; then the request's final status (DC_OK or an error),
+ * after which the ticket is forgotten (a second poll gives DC_ERR_INVALID).  Thread-safe. */
+int dc_poll(dc_ctx *ctx, uint64_t ticket);
+
+/* Test hook: make the context's next n device allocations fail with DC_ERR_NOMEM, so that
+ * failure handling can be exercised without exhausting the device. */
+int dc_debug_fail_allocs(dc_ctx *ctx, int n);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int dc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIFFCLOUD_H */

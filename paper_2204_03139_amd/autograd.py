@@ -1,0 +1,52 @@
+"""torch.autograd.Function over the C ABI: sampling (Eq. 3) + Chamfer (Eq. 1/2) forward, and the
+backward through the saved neighbours and Eq. 4 to the mesh vertices.
+
+The forward saves the face choice, barycentric weights, sampled points and both neighbour index
+arrays; the backward never recomputes them.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib
+
+
+class DiffCloudChamfer(torch.autograd.Function):
+    """loss[t] for a mesh trajectory verts [T,V,3] against an observed cloud [T,Nb,3].
+
+    apply(verts, faces, observed, n_sim, seed, precision, reduction, frame_w, uniforms)
+    returns the per-frame loss [T] (float64).  Gradients flow to verts (and to observed when it
+    requires grad)."""
+
+    @staticmethod
+    def forward(ctx, verts, faces, observed, n_sim, seed=0, precision=_lib.DC_PREC_FP32,
+                reduction=_lib.DC_RED_BIDIR_MEAN, frame_w=None, uniforms=None):
+        v = verts.detach().contiguous()
+        obs = observed.detach().contiguous()
+        points, face_idx, bary = _lib.sample_surface(v, faces, n_sim, seed=seed, uniforms=uniforms)
+        out = _lib.chamfer_fwd(points, obs, precision=precision, reduction=reduction,
+                               frame_w=frame_w)
+        ctx.save_for_backward(faces, obs, points, face_idx, bary, out["idx_a"], out["idx_b"],
+                              frame_w if frame_w is not None else torch.empty(0))
+        ctx.V = v.shape[1]
+        ctx.reduction = reduction
+        ctx.has_w = frame_w is not None
+        ctx.mark_non_differentiable(out["idx_a"])
+        return out["loss"]
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        faces, obs, points, face_idx, bary, idx_a, idx_b, fw = ctx.saved_tensors
+        fw = fw if ctx.has_w else None
+        want_b = ctx.needs_input_grad[2]
+        ga, gb = _lib.chamfer_bwd(grad_loss.detach().to(torch.float64).contiguous(), points, obs,
+                                  idx_a, idx_b, reduction=ctx.reduction, frame_w=fw, want_b=want_b)
+        gv = _lib.sample_surface_bwd(ga, faces, face_idx, bary, ctx.V)
+        return gv, None, gb, None, None, None, None, None, None
+
+
+def diffcloud_loss(verts, faces, observed, n_sim, seed=0, precision=_lib.DC_PREC_FP32,
+                   reduction=_lib.DC_RED_BIDIR_MEAN, frame_w=None, uniforms=None):
+    """Sum over frames of the per-frame loss (a scalar, float64)."""
+    return DiffCloudChamfer.apply(verts, faces, observed, n_sim, seed, precision, reduction,
+                                  frame_w, uniforms).sum()

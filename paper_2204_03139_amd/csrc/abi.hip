@@ -1,0 +1,413 @@
+// C ABI entry points of libdiffcloud: argument validation, scratch management under the HBM
+// budget, and the launch sequence of each call.  Every kernel runs on the caller's stream.
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "dc_internal.h"
+#include "scheduler.h"
+
+namespace dc {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+void clear_error() { g_err.clear(); }
+
+int hip_fail(hipError_t e, const char *what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return DC_ERR_HIP;
+}
+
+int budget_take(dc_ctx *ctx, size_t bytes) {
+    std::lock_guard<std::mutex> g(ctx->budget_mu);
+    if (ctx->held + bytes > ctx->budget) {
+        set_error("HBM budget exceeded: need " + std::to_string(bytes) + " bytes, " +
+                  std::to_string(ctx->budget - ctx->held) + " free");
+        return DC_ERR_BUDGET;
+    }
+    ctx->held += bytes;
+    return DC_OK;
+}
+
+void budget_give(dc_ctx *ctx, size_t bytes) {
+    std::lock_guard<std::mutex> g(ctx->budget_mu);
+    ctx->held -= bytes;
+}
+
+int dev_alloc(dc_ctx *ctx, void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) return DC_OK;
+    int rc = budget_take(ctx, bytes);
+    if (rc != DC_OK) return rc;
+    bool forced = false;
+    {
+        std::lock_guard<std::mutex> g(ctx->budget_mu);
+        if (ctx->fail_next_alloc > 0) {
+            --ctx->fail_next_alloc;
+            forced = true;
+        }
+    }
+    hipError_t e = forced ? hipErrorOutOfMemory : hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        budget_give(ctx, bytes);
+        *p = nullptr;
+        set_error("device allocation of " + std::to_string(bytes) + " bytes failed");
+        return DC_ERR_NOMEM;
+    }
+    return DC_OK;
+}
+
+void dev_free(dc_ctx *ctx, void *p, size_t bytes) {
+    if (!p) return;
+    (void)hipFree(p);
+    budget_give(ctx, bytes);
+}
+
+int arena_reserve(dc_ctx *ctx, size_t bytes) {
+    Arena &a = ctx->arena;
+    a.reset();
+    if (bytes <= a.cap) return DC_OK;
+    // the old buffer may still be read by queued work: wait for the device before freeing it
+    DC_HIP(hipDeviceSynchronize());
+    dev_free(ctx, a.base, a.cap);
+    a.base = nullptr;
+    a.cap = 0;
+    const size_t want = (bytes + (size_t(1) << 20) - 1) & ~((size_t(1) << 20) - 1);
+    void *p = nullptr;
+    int rc = dev_alloc(ctx, &p, want);
+    if (rc != DC_OK) return rc;
+    a.base = static_cast<char *>(p);
+    a.cap = want;
+    return DC_OK;
+}
+
+static int check_dims(int T, std::initializer_list<long> sizes) {
+    if (T < 1 || T > 65535) {
+        set_error("T must be in [1, 65535]");
+        return DC_ERR_INVALID;
+    }
+    for (long n : sizes)
+        if (n < 1 || n > (1L << 24)) {
+            set_error("sizes must be in [1, 2^24]");
+            return DC_ERR_INVALID;
+        }
+    return DC_OK;
+}
+
+static int launched(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, what);
+    return DC_OK;
+}
+
+// Shared by the direct calls and the serving loop: sampling with its scratch carved from `ar`.
+ProfScope::ProfScope(dc_ctx *c, int category, hipStream_t st) : ctx(c), cat(category), s(st) {
+    if (!ctx || !ctx->prof || hipEventCreate(&a) != hipSuccess) {
+        ctx = nullptr;
+        return;
+    }
+    (void)hipEventRecord(a, s);
+}
+
+ProfScope::~ProfScope() {
+    if (!ctx) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+    }
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> g(ctx->prof_mu);
+    ctx->prof_pending.push_back({cat, a, b});
+}
+
+int enqueue_sample(dc_ctx *prof, const float *verts, const int32_t *faces, int T, int V, int F,
+                   int N, uint64_t seed, const uint32_t *uniforms, float *points,
+                   int32_t *face_idx, float *bary, Arena &ar, unsigned *status, hipStream_t s) {
+    double *cdf = ar.take<double>((size_t)T * F);
+    int32_t *lastpos = ar.take<int32_t>((size_t)T);
+    ProfScope ps(prof, 2, s);
+    launch_sample(verts, faces, T, V, F, N, seed, uniforms, points, face_idx, bary, cdf, lastpos,
+                  status, s);
+    return launched("sample_surface launch");
+}
+
+size_t chamfer_fwd_scratch_bytes(int T, int Na, int Nb, int precision) {
+    if (precision == DC_PREC_BF16_REFINE)
+        return std::max(screen_scratch_bytes(T, Na, Nb), screen_scratch_bytes(T, Nb, Na));
+    return std::max(nn_exact_scratch_bytes(T, Na, Nb), nn_exact_scratch_bytes(T, Nb, Na));
+}
+
+int enqueue_chamfer_fwd(dc_ctx *prof, const float *a, const float *b, int T, int Na, int Nb,
+                        int precision, int reduction, const float *frame_w, float *dist_a,
+                        int32_t *idx_a, float *dist_b, int32_t *idx_b, double *loss,
+                        char *scratch, unsigned long long *stats, hipStream_t s) {
+    if (precision == DC_PREC_BF16_REFINE) {
+        launch_nn_screened(a, Na, b, Nb, T, idx_a, dist_a, scratch, stats, prof, s);
+        launch_nn_screened(b, Nb, a, Na, T, idx_b, dist_b, scratch, stats, prof, s);
+    } else {
+        {
+            ProfScope ps(prof, 0, s);
+            launch_nn_exact_ws(a, Na, b, Nb, T, idx_a, dist_a, scratch, s);
+        }
+        {
+            ProfScope ps(prof, 0, s);
+            launch_nn_exact_ws(b, Nb, a, Na, T, idx_b, dist_b, scratch, s);
+        }
+    }
+    launch_loss(dist_a, dist_b, T, Na, Nb, reduction, frame_w, loss, s);
+    return launched("chamfer_fwd launch");
+}
+
+}  // namespace dc
+
+using namespace dc;
+
+extern "C" {
+
+int dc_version(void) { return 100; }
+
+const char *dc_last_error(void) { return g_err.c_str(); }
+
+int dc_create(dc_ctx **out, int device, size_t hbm_budget_bytes, int max_slots) {
+    clear_error();
+    if (!out) {
+        set_error("out is NULL");
+        return DC_ERR_INVALID;
+    }
+    *out = nullptr;
+    int n = 0;
+    DC_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) {
+        set_error("device index out of range");
+        return DC_ERR_INVALID;
+    }
+    if (max_slots < 0) {
+        set_error("max_slots must be >= 0");
+        return DC_ERR_INVALID;
+    }
+    DC_HIP(hipSetDevice(device));
+    dc_ctx *c = new (std::nothrow) dc_ctx();
+    if (!c) return DC_ERR_NOMEM;
+    c->device = device;
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t(64) << 30);
+    c->max_slots = max_slots ? max_slots : 64;
+    hipError_t e = hipMalloc(&c->d_status, sizeof(unsigned) * 4);
+    if (e == hipSuccess) e = hipMalloc(&c->d_stats, sizeof(unsigned long long) * 4);
+    if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(unsigned) * 4);
+    if (e == hipSuccess) e = hipMemset(c->d_stats, 0, sizeof(unsigned long long) * 4);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipFree(c->d_status);
+        (void)hipFree(c->d_stats);
+        delete c;
+        return hip_fail(e, "dc_create");
+    }
+    *out = c;
+    return DC_OK;
+}
+
+int dc_destroy(dc_ctx *ctx) {
+    clear_error();
+    if (!ctx) return DC_ERR_INVALID;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->sched) {
+        sched_destroy(ctx);
+        ctx->sched = nullptr;
+    }
+    (void)hipDeviceSynchronize();
+    dev_free(ctx, ctx->arena.base, ctx->arena.cap);
+    (void)hipFree(ctx->d_status);
+    (void)hipFree(ctx->d_stats);
+    delete ctx;
+    return DC_OK;
+}
+
+int dc_sync(dc_ctx *ctx, void *stream) {
+    clear_error();
+    if (!ctx) return DC_ERR_INVALID;
+    DC_HIP(hipSetDevice(ctx->device));
+    DC_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    unsigned st = 0;
+    DC_HIP(hipMemcpy(&st, ctx->d_status, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (st) DC_HIP(hipMemset(ctx->d_status, 0, sizeof(unsigned)));
+    if (st & ST_BAD_FACE) {
+        set_error("a face index lies outside [0, V)");
+        return DC_ERR_INVALID;
+    }
+    if (st & ST_DEGENERATE) {
+        set_error("a frame has zero or non-finite total surface area");
+        return DC_ERR_DEGENERATE;
+    }
+    return DC_OK;
+}
+
+int dc_get_stats(dc_ctx *ctx, dc_stats *out) {
+    clear_error();
+    if (!ctx || !out) return DC_ERR_INVALID;
+    DC_HIP(hipSetDevice(ctx->device));
+    unsigned long long v[4] = {0, 0, 0, 0};
+    DC_HIP(hipMemcpy(v, ctx->d_stats, sizeof(v), hipMemcpyDeviceToHost));
+    out->queries = v[0];
+    out->candidates = v[1];
+    out->fallbacks = v[2];
+    return DC_OK;
+}
+
+int dc_profile(dc_ctx *ctx, int enable) {
+    clear_error();
+    if (!ctx) return DC_ERR_INVALID;
+    ctx->prof = enable != 0;
+    return DC_OK;
+}
+
+int dc_get_kernel_times(dc_ctx *ctx, dc_kernel_times *out, int reset) {
+    clear_error();
+    if (!ctx || !out) return DC_ERR_INVALID;
+    DC_HIP(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> g(ctx->prof_mu);
+    for (auto &r : ctx->prof_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) == hipSuccess &&
+            hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            ctx->prof_ms[r.cat] += ms;
+            ctx->prof_n[r.cat] += 1;
+        }
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    ctx->prof_pending.clear();
+    for (int k = 0; k < 4; ++k) {
+        out->ms[k] = ctx->prof_ms[k];
+        out->launches[k] = ctx->prof_n[k];
+        if (reset) {
+            ctx->prof_ms[k] = 0;
+            ctx->prof_n[k] = 0;
+        }
+    }
+    return DC_OK;
+}
+
+int dc_debug_fail_allocs(dc_ctx *ctx, int n) {
+    if (!ctx || n < 0) return DC_ERR_INVALID;
+    std::lock_guard<std::mutex> g(ctx->budget_mu);
+    ctx->fail_next_alloc = n;
+    return DC_OK;
+}
+
+int dc_sample_surface(dc_ctx *ctx, const float *verts, const int32_t *faces, int T, int V, int F,
+                      int N, uint64_t seed, const uint32_t *uniforms, float *points,
+                      int32_t *face_idx, float *bary, void *stream) {
+    clear_error();
+    if (!ctx || !verts || !faces || !points || !face_idx || !bary) {
+        set_error("dc_sample_surface: NULL argument");
+        return DC_ERR_INVALID;
+    }
+    int rc = check_dims(T, {V, F, N});
+    if (rc) return rc;
+    DC_HIP(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> g(ctx->mu);
+    rc = arena_reserve(ctx, sample_scratch_bytes(T, F));
+    if (rc) return rc;
+    return enqueue_sample(ctx, verts, faces, T, V, F, N, seed, uniforms, points, face_idx, bary,
+                          ctx->arena, ctx->d_status, static_cast<hipStream_t>(stream));
+}
+
+int dc_sample_surface_bwd(dc_ctx *ctx, const float *grad_points, const int32_t *faces,
+                          const int32_t *face_idx, const float *bary, int T, int V, int F, int N,
+                          float *grad_verts, void *stream) {
+    clear_error();
+    if (!ctx || !grad_points || !faces || !face_idx || !bary || !grad_verts) {
+        set_error("dc_sample_surface_bwd: NULL argument");
+        return DC_ERR_INVALID;
+    }
+    int rc = check_dims(T, {V, F, N, 3L * F});
+    if (rc) return rc;
+    DC_HIP(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> g(ctx->mu);
+    const size_t need = sample_bwd_scratch_bytes(T, V, F, N);
+    rc = arena_reserve(ctx, need);
+    if (rc) return rc;
+    ProfScope ps(ctx, 3, static_cast<hipStream_t>(stream));
+    launch_sample_bwd(grad_points, faces, face_idx, bary, T, V, F, N, grad_verts,
+                      ctx->arena.take<char>(need), static_cast<hipStream_t>(stream));
+    return launched("sample_surface_bwd launch");
+}
+
+int dc_chamfer_fwd(dc_ctx *ctx, const float *a, const float *b, int T, int Na, int Nb,
+                   int precision, int reduction, const float *frame_w, float *dist_a,
+                   int32_t *idx_a, float *dist_b, int32_t *idx_b, double *loss, void *stream) {
+    clear_error();
+    if (!ctx || !a || !b || !dist_a || !idx_a || !dist_b || !idx_b || !loss) {
+        set_error("dc_chamfer_fwd: NULL argument");
+        return DC_ERR_INVALID;
+    }
+    if (precision != DC_PREC_FP32 && precision != DC_PREC_BF16_REFINE) {
+        set_error("unknown precision");
+        return DC_ERR_INVALID;
+    }
+    if (reduction != DC_RED_BIDIR_MEAN && reduction != DC_RED_SIM2REAL_SUM) {
+        set_error("unknown reduction");
+        return DC_ERR_INVALID;
+    }
+    int rc = check_dims(T, {Na, Nb});
+    if (rc) return rc;
+    if (precision == DC_PREC_BF16_REFINE && !screen_available()) {
+        set_error("the bf16 screen is not available in this build");
+        return DC_ERR_UNSUPPORTED;
+    }
+    DC_HIP(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> g(ctx->mu);
+    const size_t need = chamfer_fwd_scratch_bytes(T, Na, Nb, precision);
+    rc = arena_reserve(ctx, need);
+    if (rc) return rc;
+    return enqueue_chamfer_fwd(ctx, a, b, T, Na, Nb, precision, reduction, frame_w, dist_a, idx_a,
+                               dist_b, idx_b, loss, ctx->arena.take<char>(need), ctx->d_stats,
+                               static_cast<hipStream_t>(stream));
+}
+
+int dc_chamfer_bwd(dc_ctx *ctx, const double *grad_loss, const float *a, const float *b,
+                   const int32_t *idx_a, const int32_t *idx_b, int T, int Na, int Nb,
+                   int reduction, const float *frame_w, float *grad_a, float *grad_b,
+                   void *stream) {
+    clear_error();
+    if (!ctx || !grad_loss || !a || !b || !idx_a || !idx_b || !grad_a) {
+        set_error("dc_chamfer_bwd: NULL argument");
+        return DC_ERR_INVALID;
+    }
+    if (reduction != DC_RED_BIDIR_MEAN && reduction != DC_RED_SIM2REAL_SUM) {
+        set_error("unknown reduction");
+        return DC_ERR_INVALID;
+    }
+    int rc = check_dims(T, {Na, Nb});
+    if (rc) return rc;
+    DC_HIP(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> g(ctx->mu);
+    const size_t need = chamfer_bwd_scratch_bytes(T, Na, Nb, grad_b != nullptr);
+    rc = arena_reserve(ctx, need);
+    if (rc) return rc;
+    ProfScope ps(ctx, 3, static_cast<hipStream_t>(stream));
+    launch_chamfer_bwd(grad_loss, a, b, idx_a, idx_b, T, Na, Nb, reduction, frame_w, grad_a,
+                       grad_b, ctx->arena.take<char>(need), static_cast<hipStream_t>(stream));
+    return launched("chamfer_bwd launch");
+}
+
+int dc_submit(dc_ctx *ctx, const dc_request *req, dc_result *out, uint64_t *ticket) {
+    clear_error();
+    if (!ctx || !req || !out || !ticket) {
+        set_error("dc_submit: NULL argument");
+        return DC_ERR_INVALID;
+    }
+    return sched_submit(ctx, req, out, ticket);
+}
+
+int dc_poll(dc_ctx *ctx, uint64_t ticket) {
+    clear_error();
+    if (!ctx) return DC_ERR_INVALID;
+    return sched_poll(ctx, ticket);
+}
+
+}  // extern "C"

@@ -1,0 +1,179 @@
+// Backward passes: the Chamfer gradient through the saved neighbours (Sec. III-A, Eq. 1/2) and
+// the sampling gradient through Eq. 4 (Sec. III-B).  Both are gathers over segments built by the
+// stable atomic-free sort, summed in increasing index order, so every result is bitwise
+// reproducible and independent of scheduling.
+#include "dc_internal.h"
+
+namespace dc {
+namespace {
+
+constexpr int BW_THREADS = 256;
+
+// first position p in sorted[0..n) with sorted[p] >= key
+__device__ __forceinline__ int lower_bound(const int32_t *sorted, int n, int key) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sorted[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// g_x[t,i] = g_t w_t ( cs * (x_i - y_{nn_x[i]}) + cm * sum_{j: nn_y[j]=i} (x_i - y_j) )
+// for x = a (cs = 2 alpha, cm = 2 beta) or x = b (cs = 2 beta, cm = 2 alpha).
+__global__ __launch_bounds__(BW_THREADS) void k_chamfer_bwd(
+    const double *__restrict__ grad_loss, const float *__restrict__ X, const float *__restrict__ Y,
+    const int32_t *__restrict__ nn_x, const int32_t *__restrict__ ykeys_sorted,
+    const int32_t *__restrict__ yvals_sorted, int Nx, int Ny, double cself, double cmutual,
+    const float *__restrict__ frame_w, float *__restrict__ gX) {
+    const int t = blockIdx.y;
+    const int i = blockIdx.x * BW_THREADS + threadIdx.x;
+    if (i >= Nx) return;
+    const double g = grad_loss[t] * (frame_w ? (double)frame_w[t] : 1.0);
+    const float cs = (float)(cself * g);
+    const float cm = (float)(cmutual * g);
+    const float *xt = X + (size_t)t * Nx * 3;
+    const float *yt = Y + (size_t)t * Ny * 3;
+    const float x0 = xt[3 * (size_t)i], x1 = xt[3 * (size_t)i + 1], x2 = xt[3 * (size_t)i + 2];
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+    const int jn = nn_x[(size_t)t * Nx + i];
+    if (cs != 0.f && (unsigned)jn < (unsigned)Ny) {  // indices outside [0, Ny) contribute nothing
+        const int j = jn;
+        g0 = cs * (x0 - yt[3 * (size_t)j]);
+        g1 = cs * (x1 - yt[3 * (size_t)j + 1]);
+        g2 = cs * (x2 - yt[3 * (size_t)j + 2]);
+    }
+    if (cm != 0.f) {
+        const int32_t *ks = ykeys_sorted + (size_t)t * Ny;
+        const int32_t *vs = yvals_sorted + (size_t)t * Ny;
+        const int lo = lower_bound(ks, Ny, i);
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+        for (int p = lo; p < Ny && ks[p] == i; ++p) {
+            const int j = vs[p];
+            s0 += x0 - yt[3 * (size_t)j];
+            s1 += x1 - yt[3 * (size_t)j + 1];
+            s2 += x2 - yt[3 * (size_t)j + 2];
+        }
+        g0 = __builtin_fmaf(cm, s0, g0);
+        g1 = __builtin_fmaf(cm, s1, g1);
+        g2 = __builtin_fmaf(cm, s2, g2);
+    }
+    float *o = gX + ((size_t)t * Nx + i) * 3;
+    o[0] = g0;
+    o[1] = g1;
+    o[2] = g2;
+}
+
+// face_start[t][f] = first sorted position whose face is >= f, for f in [0, F]
+__global__ void k_bounds(const int32_t *__restrict__ sorted, int N, int K,
+                         int32_t *__restrict__ start) {
+    const int t = blockIdx.y;
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f > K) return;
+    start[(size_t)t * (K + 1) + f] = lower_bound(sorted + (size_t)t * N, N, f);
+}
+
+// grad_verts[t,v] = sum over incident (face f, corner c) in increasing (f, c), then over the
+// points i of face f in increasing i, of bary[t,i,c] * g[t,i]
+__global__ __launch_bounds__(BW_THREADS) void k_sample_bwd(
+    const float *__restrict__ gpts, const float *__restrict__ bary,
+    const int32_t *__restrict__ pts_by_face, const int32_t *__restrict__ face_start,
+    const int32_t *__restrict__ corners_by_vertex, const int32_t *__restrict__ vert_start, int V,
+    int F, int N, float *__restrict__ gverts) {
+    const int t = blockIdx.y;
+    const int v = blockIdx.x * BW_THREADS + threadIdx.x;
+    if (v >= V) return;
+    const int32_t *fs = face_start + (size_t)t * (F + 1);
+    const int32_t *pf = pts_by_face + (size_t)t * N;
+    const float *gt = gpts + (size_t)t * N * 3;
+    const float *bt = bary + (size_t)t * N * 3;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    for (int q = vert_start[v]; q < vert_start[v + 1]; ++q) {
+        const int fc = corners_by_vertex[q];
+        const int f = fc / 3, c = fc - 3 * (fc / 3);
+        for (int p = fs[f]; p < fs[f + 1]; ++p) {
+            const int i = pf[p];
+            const float w = bt[3 * (size_t)i + c];
+            a0 = __builtin_fmaf(w, gt[3 * (size_t)i], a0);
+            a1 = __builtin_fmaf(w, gt[3 * (size_t)i + 1], a1);
+            a2 = __builtin_fmaf(w, gt[3 * (size_t)i + 2], a2);
+        }
+    }
+    float *o = gverts + ((size_t)t * V + v) * 3;
+    o[0] = a0;
+    o[1] = a1;
+    o[2] = a2;
+}
+
+}  // namespace
+
+size_t chamfer_bwd_scratch_bytes(int T, int Na, int Nb, bool want_b) {
+    size_t s = 2 * Arena::need((size_t)T * Nb, 4) + segsort_scratch_bytes(T, Nb);
+    if (want_b) s += 2 * Arena::need((size_t)T * Na, 4) + segsort_scratch_bytes(T, Na);
+    return s;
+}
+
+void launch_chamfer_bwd(const double *grad_loss, const float *a, const float *b,
+                        const int32_t *idx_a, const int32_t *idx_b, int T, int Na, int Nb,
+                        int reduction, const float *frame_w, float *grad_a, float *grad_b,
+                        char *scratch, hipStream_t s) {
+    const bool eq2 = reduction == DC_RED_SIM2REAL_SUM;
+    const double alpha = eq2 ? 1.0 : 1.0 / (double)Na;
+    const double beta = eq2 ? 0.0 : 1.0 / (double)Nb;
+    Arena ar;
+    ar.base = scratch;
+    ar.cap = chamfer_bwd_scratch_bytes(T, Na, Nb, grad_b != nullptr);
+    // segments of b grouped by their neighbour in a (needed when beta != 0)
+    int32_t *kb = ar.take<int32_t>((size_t)T * Nb);
+    int32_t *vb = ar.take<int32_t>((size_t)T * Nb);
+    char *ssb = ar.take<char>(segsort_scratch_bytes(T, Nb));
+    if (beta != 0.0) launch_segsort(idx_b, T, Nb, Na, kb, vb, ssb, s);
+    hipLaunchKernelGGL(k_chamfer_bwd, dim3((Na + BW_THREADS - 1) / BW_THREADS, T),
+                       dim3(BW_THREADS), 0, s, grad_loss, a, b, idx_a, kb, vb, Na, Nb, 2.0 * alpha,
+                       2.0 * beta, frame_w, grad_a);
+    if (grad_b) {
+        int32_t *ka = ar.take<int32_t>((size_t)T * Na);
+        int32_t *va = ar.take<int32_t>((size_t)T * Na);
+        char *ssa = ar.take<char>(segsort_scratch_bytes(T, Na));
+        launch_segsort(idx_a, T, Na, Nb, ka, va, ssa, s);
+        hipLaunchKernelGGL(k_chamfer_bwd, dim3((Nb + BW_THREADS - 1) / BW_THREADS, T),
+                           dim3(BW_THREADS), 0, s, grad_loss, b, a, idx_b, ka, va, Nb, Na,
+                           2.0 * beta, 2.0 * alpha, frame_w, grad_b);
+    }
+}
+
+size_t sample_bwd_scratch_bytes(int T, int V, int F, int N) {
+    return 2 * Arena::need((size_t)T * N, 4) + segsort_scratch_bytes(T, N) +
+           Arena::need((size_t)T * (F + 1), 4) + 2 * Arena::need((size_t)3 * F, 4) +
+           segsort_scratch_bytes(1, 3 * F) + Arena::need((size_t)V + 1, 4);
+}
+
+void launch_sample_bwd(const float *grad_points, const int32_t *faces, const int32_t *face_idx,
+                       const float *bary, int T, int V, int F, int N, float *grad_verts,
+                       char *scratch, hipStream_t s) {
+    Arena ar;
+    ar.base = scratch;
+    ar.cap = sample_bwd_scratch_bytes(T, V, F, N);
+    int32_t *fk = ar.take<int32_t>((size_t)T * N);
+    int32_t *fv = ar.take<int32_t>((size_t)T * N);
+    char *ss1 = ar.take<char>(segsort_scratch_bytes(T, N));
+    int32_t *fstart = ar.take<int32_t>((size_t)T * (F + 1));
+    int32_t *ck = ar.take<int32_t>((size_t)3 * F);
+    int32_t *cv = ar.take<int32_t>((size_t)3 * F);
+    char *ss2 = ar.take<char>(segsort_scratch_bytes(1, 3 * F));
+    int32_t *vstart = ar.take<int32_t>((size_t)V + 1);
+    // points grouped by face (face -1 of a degenerate frame sorts last, as key F, and is unused)
+    launch_segsort(face_idx, T, N, F, fk, fv, ss1, s);
+    hipLaunchKernelGGL(k_bounds, dim3((F + 1 + 255) / 256, T), dim3(256), 0, s, fk, N, F, fstart);
+    // (face, corner) slots grouped by vertex: the vertex-incidence CSR of the topology
+    launch_segsort(faces, 1, 3 * F, V, ck, cv, ss2, s);
+    hipLaunchKernelGGL(k_bounds, dim3((V + 1 + 255) / 256, 1), dim3(256), 0, s, ck, 3 * F, V,
+                       vstart);
+    hipLaunchKernelGGL(k_sample_bwd, dim3((V + BW_THREADS - 1) / BW_THREADS, T), dim3(BW_THREADS),
+                       0, s, grad_points, bary, fv, fstart, cv, vstart, V, F, N, grad_verts);
+}
+
+}  // namespace dc

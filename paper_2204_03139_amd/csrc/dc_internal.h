@@ -1,0 +1,153 @@
+// Internal declarations of libdiffcloud: context, scratch arena, error state, kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/diffcloud.h"
+
+namespace dc {
+
+// ---------------------------------------------------------------- error state
+void set_error(const std::string &msg);
+void clear_error();
+int hip_fail(hipError_t e, const char *what);  // records the message, returns DC_ERR_HIP
+
+#define DC_HIP(call)                                      \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return ::dc::hip_fail(e_, #call); \
+    } while (0)
+
+// bits of the sticky device status word
+enum : unsigned { ST_DEGENERATE = 1u, ST_BAD_FACE = 2u };
+
+// ---------------------------------------------------------------- scratch arena
+// A grow-only device buffer carved into 256-byte aligned pieces per call.  Growing frees the old
+// buffer only after the device is idle, so work still in flight never loses its memory.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0;
+    size_t off = 0;
+    void reset() { off = 0; }
+    template <class T>
+    T *take(size_t count) {
+        size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+        T *p = reinterpret_cast<T *>(base + off);
+        off += bytes;
+        return p;
+    }
+    static size_t need(size_t count, size_t elem) { return (count * elem + 255) & ~size_t(255); }
+};
+
+struct Scheduler;
+
+// events bracketing profiled launches: (category, start, stop)
+struct ProfRecord {
+    int cat;
+    hipEvent_t a, b;
+};
+
+}  // namespace dc
+
+struct dc_ctx {
+    int device = 0;
+    size_t budget = 0;
+    int max_slots = 64;
+    std::mutex mu;                // serialises direct calls (they share the arena)
+    std::mutex budget_mu;         // guards budget accounting
+    size_t held = 0;              // bytes of device memory held against the budget
+    dc::Arena arena;              // scratch of direct calls
+    unsigned *d_status = nullptr;           // sticky device status word
+    unsigned long long *d_stats = nullptr;  // [3] screen counters
+    dc::Scheduler *sched = nullptr;
+    int fail_next_alloc = 0;      // test hook: make the next N allocations fail
+    bool prof = false;            // record events around profiled launches
+    std::mutex prof_mu;
+    std::vector<dc::ProfRecord> prof_pending;
+    double prof_ms[4] = {0, 0, 0, 0};
+    uint64_t prof_n[4] = {0, 0, 0, 0};
+};
+
+namespace dc {
+
+// reserve `bytes` of the budget; DC_ERR_BUDGET if it cannot fit
+int budget_take(dc_ctx *ctx, size_t bytes);
+void budget_give(dc_ctx *ctx, size_t bytes);
+// device allocation counted against the budget
+int dev_alloc(dc_ctx *ctx, void **p, size_t bytes);
+void dev_free(dc_ctx *ctx, void *p, size_t bytes);
+// make sure the direct-call arena holds at least `bytes`; resets its offset
+int arena_reserve(dc_ctx *ctx, size_t bytes);
+
+// start / stop an event pair around the launches of category `cat` (no-op unless profiling)
+struct ProfScope {
+    dc_ctx *ctx;
+    int cat;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    ProfScope(dc_ctx *c, int category, hipStream_t st);
+    ~ProfScope();
+};
+
+// ---------------------------------------------------------------- launchers (async, on `s`)
+// sampling
+size_t sample_scratch_bytes(int T, int F);
+void launch_sample(const float *verts, const int32_t *faces, int T, int V, int F, int N,
+                   uint64_t seed, const uint32_t *uniforms, float *points, int32_t *face_idx,
+                   float *bary, double *cdf_scratch, int32_t *lastpos_scratch, unsigned *status,
+                   hipStream_t s);
+
+// exact fp32 nearest neighbours: for each query of Q[t] the index of its nearest point in P[t]
+size_t nn_exact_scratch_bytes(int T, int Nq, int Np);
+void launch_nn_exact_ws(const float *Q, int Nq, const float *P, int Np, int T, int32_t *idx,
+                        float *dist, char *scratch, hipStream_t st);
+
+// bf16 matrix-core screen + certified exact refine (same outputs as launch_nn_exact)
+bool screen_available();
+size_t screen_scratch_bytes(int T, int Nq, int Np);
+void launch_nn_screened(const float *Q, int Nq, const float *P, int Np, int T, int32_t *idx,
+                        float *dist, char *scratch, unsigned long long *stats, dc_ctx *prof,
+                        hipStream_t s);
+
+// per-frame loss from the float distances, accumulated in double
+void launch_loss(const float *dist_a, const float *dist_b, int T, int Na, int Nb, int reduction,
+                 const float *frame_w, double *loss, hipStream_t s);
+
+// stable, atomic-free sort of per-frame keys in [0, key_limit]: out_keys/out_vals get the keys
+// and the original positions in (key, position) order.
+size_t segsort_scratch_bytes(int T, int N);
+void launch_segsort(const int32_t *keys, int T, int N, int key_limit, int32_t *out_keys,
+                    int32_t *out_vals, char *scratch, hipStream_t s);
+
+// Chamfer backward
+size_t chamfer_bwd_scratch_bytes(int T, int Na, int Nb, bool want_b);
+void launch_chamfer_bwd(const double *grad_loss, const float *a, const float *b,
+                        const int32_t *idx_a, const int32_t *idx_b, int T, int Na, int Nb,
+                        int reduction, const float *frame_w, float *grad_a, float *grad_b,
+                        char *scratch, hipStream_t s);
+
+// sampling backward
+size_t sample_bwd_scratch_bytes(int T, int V, int F, int N);
+void launch_sample_bwd(const float *grad_points, const int32_t *faces, const int32_t *face_idx,
+                       const float *bary, int T, int V, int F, int N, float *grad_verts,
+                       char *scratch, hipStream_t s);
+
+// composite enqueues shared by the direct calls and the serving loop
+// `prof` is the context whose profiling records the launches, or NULL
+int enqueue_sample(dc_ctx *prof, const float *verts, const int32_t *faces, int T, int V, int F,
+                   int N, uint64_t seed, const uint32_t *uniforms, float *points,
+                   int32_t *face_idx, float *bary, Arena &ar, unsigned *status, hipStream_t s);
+size_t chamfer_fwd_scratch_bytes(int T, int Na, int Nb, int precision);
+int enqueue_chamfer_fwd(dc_ctx *prof, const float *a, const float *b, int T, int Na, int Nb,
+                        int precision,
+                        int reduction, const float *frame_w, float *dist_a, int32_t *idx_a,
+                        float *dist_b, int32_t *idx_b, double *loss, char *scratch,
+                        unsigned long long *stats, hipStream_t s);
+
+}  // namespace dc

@@ -1,0 +1,231 @@
+// Exact single-precision nearest neighbours (the plain fp32 path of Sec. III-A, Eq. 1/2) and the
+// per-frame loss reduction.
+//
+// k_nn_exact: each lane owns QPT queries held in registers; the workgroup streams the target
+// cloud through LDS in tiles of NN_TILE points (one 16-byte broadcast read per target per lane).
+// Per pair the lane evaluates the canonical distance fma(dz,dz,fma(dy,dy,dx*dx)) and keeps only a
+// running minimum over a sub-tile of NN_SUB targets (one v_min per pair); the first sub-tile with
+// a strictly smaller minimum is remembered.  At the end the lane rescans that one sub-tile from
+// global memory for the first index whose distance equals the minimum, which is the smallest
+// index among the exact ties, so the result is the exact argmin with the smallest-index rule.
+// Large frames split the target range over grid.z slices; a merge kernel combines the slices in
+// slice order with the same strict-less rule.
+#include "dc_internal.h"
+
+namespace dc {
+namespace {
+
+constexpr int NN_THREADS = 256;
+constexpr int NN_TILE = 1024;
+constexpr int NN_SUB = 64;
+
+__device__ __forceinline__ float canon_d2(float qx, float qy, float qz, float px, float py,
+                                          float pz) {
+    const float dx = qx - px;
+    const float dy = qy - py;
+    const float dz = qz - pz;
+    return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+}
+
+template <int QPT>
+__global__ __launch_bounds__(NN_THREADS) void k_nn_exact(const float *__restrict__ Q, int Nq,
+                                                         const float *__restrict__ P, int Np,
+                                                         int slice_len, int32_t *__restrict__ idx,
+                                                         float *__restrict__ dist,
+                                                         size_t slice_stride) {
+    __shared__ float4 tile[NN_TILE];
+    const int t = blockIdx.y;
+    const int z = blockIdx.z;
+    const float *Qt = Q + (size_t)t * Nq * 3;
+    const float *Pt = P + (size_t)t * Np * 3;
+    const int j_begin = z * slice_len;
+    const int j_end = min(Np, j_begin + slice_len);
+    const int q0 = blockIdx.x * NN_THREADS * QPT + threadIdx.x;
+
+    float qx[QPT], qy[QPT], qz[QPT], best[QPT];
+    int bsub[QPT];
+#pragma unroll
+    for (int k = 0; k < QPT; ++k) {
+        const int qi = q0 + k * NN_THREADS;
+        const bool ok = qi < Nq;
+        qx[k] = ok ? Qt[3 * (size_t)qi] : 0.f;
+        qy[k] = ok ? Qt[3 * (size_t)qi + 1] : 0.f;
+        qz[k] = ok ? Qt[3 * (size_t)qi + 2] : 0.f;
+        best[k] = __builtin_inff();
+        bsub[k] = j_begin;
+    }
+
+    for (int base = j_begin; base < j_end; base += NN_TILE) {
+        const int n = min(NN_TILE, j_end - base);
+        __syncthreads();
+        for (int j = threadIdx.x; j < n; j += NN_THREADS) {
+            const float *p = Pt + 3 * (size_t)(base + j);
+            tile[j] = make_float4(p[0], p[1], p[2], 0.f);
+        }
+        __syncthreads();
+        int s0 = 0;
+        for (; s0 + NN_SUB <= n; s0 += NN_SUB) {
+            float m[QPT];
+#pragma unroll
+            for (int k = 0; k < QPT; ++k) m[k] = __builtin_inff();
+#pragma unroll 8
+            for (int j = s0; j < s0 + NN_SUB; ++j) {
+                const float4 p = tile[j];
+#pragma unroll
+                for (int k = 0; k < QPT; ++k)
+                    m[k] = __builtin_fminf(m[k], canon_d2(qx[k], qy[k], qz[k], p.x, p.y, p.z));
+            }
+#pragma unroll
+            for (int k = 0; k < QPT; ++k)
+                if (m[k] < best[k]) {
+                    best[k] = m[k];
+                    bsub[k] = base + s0;
+                }
+        }
+        if (s0 < n) {  // ragged tail of the slice
+            float m[QPT];
+#pragma unroll
+            for (int k = 0; k < QPT; ++k) m[k] = __builtin_inff();
+            for (int j = s0; j < n; ++j) {
+                const float4 p = tile[j];
+#pragma unroll
+                for (int k = 0; k < QPT; ++k)
+                    m[k] = __builtin_fminf(m[k], canon_d2(qx[k], qy[k], qz[k], p.x, p.y, p.z));
+            }
+#pragma unroll
+            for (int k = 0; k < QPT; ++k)
+                if (m[k] < best[k]) {
+                    best[k] = m[k];
+                    bsub[k] = base + s0;
+                }
+        }
+    }
+
+    // rescan the winning sub-tile for the first exact match
+#pragma unroll
+    for (int k = 0; k < QPT; ++k) {
+        const int qi = q0 + k * NN_THREADS;
+        if (qi >= Nq) continue;
+        const int js = bsub[k];
+        const int je = min(js + NN_SUB, j_end);
+        int found = js;
+        for (int j = js; j < je; ++j) {
+            const float *p = Pt + 3 * (size_t)j;
+            if (canon_d2(qx[k], qy[k], qz[k], p[0], p[1], p[2]) == best[k]) {
+                found = j;
+                break;
+            }
+        }
+        const size_t o = (size_t)z * slice_stride + (size_t)t * Nq + qi;
+        idx[o] = found;
+        dist[o] = best[k];
+    }
+}
+
+// combine per-slice winners; slices hold increasing index ranges, so strict-less keeps the
+// smallest index among equal distances
+__global__ void k_nn_merge(const int32_t *__restrict__ pidx, const float *__restrict__ pdist,
+                           int slices, size_t slice_stride, size_t total, int32_t *__restrict__ idx,
+                           float *__restrict__ dist) {
+    const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= total) return;
+    float b = pdist[o];
+    int bi = pidx[o];
+    for (int z = 1; z < slices; ++z) {
+        const float d = pdist[z * slice_stride + o];
+        if (d < b) {
+            b = d;
+            bi = pidx[z * slice_stride + o];
+        }
+    }
+    idx[o] = bi;
+    dist[o] = b;
+}
+
+constexpr int LOSS_THREADS = 256;
+
+// loss[t] = w_t (alpha sum_i dist_a + beta sum_j dist_b), in double, in a fixed order
+__global__ __launch_bounds__(LOSS_THREADS) void k_loss(const float *__restrict__ da,
+                                                       const float *__restrict__ db, int Na,
+                                                       int Nb, double alpha, double beta,
+                                                       const float *__restrict__ frame_w,
+                                                       double *__restrict__ loss) {
+    __shared__ double sa[LOSS_THREADS], sb[LOSS_THREADS];
+    const int t = blockIdx.x;
+    double xa = 0.0, xb = 0.0;
+    for (int i = threadIdx.x; i < Na; i += LOSS_THREADS) xa += (double)da[(size_t)t * Na + i];
+    if (beta != 0.0)
+        for (int j = threadIdx.x; j < Nb; j += LOSS_THREADS) xb += (double)db[(size_t)t * Nb + j];
+    sa[threadIdx.x] = xa;
+    sb[threadIdx.x] = xb;
+    __syncthreads();
+    for (int h = LOSS_THREADS / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sa[threadIdx.x] += sa[threadIdx.x + h];
+            sb[threadIdx.x] += sb[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double w = frame_w ? (double)frame_w[t] : 1.0;
+        loss[t] = w * (alpha * sa[0] + beta * sb[0]);
+    }
+}
+
+}  // namespace
+
+// scratch for the slice partials (0 when no slicing is needed)
+static int nn_slices(int Nq, int Np, int T, int qpt) {
+    const long qblocks = (Nq + NN_THREADS * qpt - 1) / (NN_THREADS * qpt);
+    const long blocks = qblocks * T;
+    int s = 1;
+    while (blocks * s < 2048 && (long)Np / (s * 2) >= 2 * NN_TILE) s *= 2;
+    return s;
+}
+
+static int nn_qpt(int Nq) { return Nq >= 16384 ? 8 : (Nq >= 4096 ? 4 : 1); }
+
+size_t nn_exact_scratch_bytes(int T, int Nq, int Np) {
+    const int s = nn_slices(Nq, Np, T, nn_qpt(Nq));
+    if (s == 1) return 0;
+    return Arena::need((size_t)s * T * Nq, 4) * 2;
+}
+
+void launch_nn_exact_ws(const float *Q, int Nq, const float *P, int Np, int T, int32_t *idx,
+                        float *dist, char *scratch, hipStream_t st) {
+    const int qpt = nn_qpt(Nq);
+    const int s = nn_slices(Nq, Np, T, qpt);
+    const int slice_len = (Np + s - 1) / s;
+    const size_t stride = (size_t)T * Nq;
+    int32_t *pidx = idx;
+    float *pdist = dist;
+    if (s > 1) {
+        pidx = reinterpret_cast<int32_t *>(scratch);
+        pdist = reinterpret_cast<float *>(scratch + Arena::need((size_t)s * T * Nq, 4));
+    }
+    const dim3 grid((Nq + NN_THREADS * qpt - 1) / (NN_THREADS * qpt), T, s);
+    if (qpt == 8)
+        hipLaunchKernelGGL(k_nn_exact<8>, grid, dim3(NN_THREADS), 0, st, Q, Nq, P, Np, slice_len,
+                           pidx, pdist, stride);
+    else if (qpt == 4)
+        hipLaunchKernelGGL(k_nn_exact<4>, grid, dim3(NN_THREADS), 0, st, Q, Nq, P, Np, slice_len,
+                           pidx, pdist, stride);
+    else
+        hipLaunchKernelGGL(k_nn_exact<1>, grid, dim3(NN_THREADS), 0, st, Q, Nq, P, Np, slice_len,
+                           pidx, pdist, stride);
+    if (s > 1) {
+        const size_t total = (size_t)T * Nq;
+        hipLaunchKernelGGL(k_nn_merge, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                           pidx, pdist, s, stride, total, idx, dist);
+    }
+}
+
+void launch_loss(const float *dist_a, const float *dist_b, int T, int Na, int Nb, int reduction,
+                 const float *frame_w, double *loss, hipStream_t s) {
+    const double alpha = reduction == DC_RED_SIM2REAL_SUM ? 1.0 : 1.0 / (double)Na;
+    const double beta = reduction == DC_RED_SIM2REAL_SUM ? 0.0 : 1.0 / (double)Nb;
+    hipLaunchKernelGGL(k_loss, dim3(T), dim3(LOSS_THREADS), 0, s, dist_a, dist_b, Na, Nb, alpha,
+                       beta, frame_w, loss);
+}
+
+}  // namespace dc

@@ -1,0 +1,199 @@
+// Area-weighted surface sampling (arXiv 2204.03139, Sec. III-B, Eq. 3).
+//
+// Two kernels per call:
+//   k_area_cdf   one workgroup per frame: face areas in double (all lanes), then the running sum
+//                C_k = C_{k-1} + A_k in double by one lane, in face order, so the CDF is the exact
+//                left-to-right sum (index stability needs the same rounding as a sequential sum).
+//   k_sample     one lane per point: random words (given, or Philox4x64-10), inverse-CDF face
+//                choice by an upper-bound binary search, barycentric point in float.
+// Built with -ffp-contract=off: only the fma calls written out below are fused.
+#include "dc_internal.h"
+
+namespace dc {
+namespace {
+
+constexpr int AC_THREADS = 256;
+constexpr int AC_CHUNK = 4096;  // faces staged in LDS per step (32 KiB of doubles)
+
+__device__ __forceinline__ bool face_ok(const int32_t *fv, int V) {
+    return fv[0] >= 0 && fv[0] < V && fv[1] >= 0 && fv[1] < V && fv[2] >= 0 && fv[2] < V;
+}
+
+// |(p2-p1) x (p3-p1)| / 2 with every product and difference rounded in double.
+__device__ __forceinline__ double tri_area_f64(const float *p1, const float *p2, const float *p3) {
+    const double ax = (double)p2[0] - (double)p1[0];
+    const double ay = (double)p2[1] - (double)p1[1];
+    const double az = (double)p2[2] - (double)p1[2];
+    const double bx = (double)p3[0] - (double)p1[0];
+    const double by = (double)p3[1] - (double)p1[1];
+    const double bz = (double)p3[2] - (double)p1[2];
+    const double nx = ay * bz - az * by;
+    const double ny = az * bx - ax * bz;
+    const double nz = ax * by - ay * bx;
+    const double sq = nx * nx + ny * ny + nz * nz;
+    return 0.5 * __builtin_sqrt(sq);
+}
+
+__global__ __launch_bounds__(AC_THREADS) void k_area_cdf(const float *__restrict__ verts,
+                                                         const int32_t *__restrict__ faces, int V,
+                                                         int F, double *__restrict__ cdf,
+                                                         int32_t *__restrict__ lastpos,
+                                                         unsigned *__restrict__ status) {
+    __shared__ double area[AC_CHUNK];
+    __shared__ int bad;
+    const int t = blockIdx.x;
+    const float *vt = verts + (size_t)t * V * 3;
+    double *ct = cdf + (size_t)t * F;
+    if (threadIdx.x == 0) bad = 0;
+    double run = 0.0;  // meaningful in lane 0 only
+    int last = -1;
+    for (int base = 0; base < F; base += AC_CHUNK) {
+        const int n = min(AC_CHUNK, F - base);
+        __syncthreads();
+        for (int k = threadIdx.x; k < n; k += AC_THREADS) {
+            const int32_t *fv = faces + 3 * (size_t)(base + k);
+            double a = 0.0;
+            if (face_ok(fv, V))
+                a = tri_area_f64(vt + 3 * (size_t)fv[0], vt + 3 * (size_t)fv[1],
+                                 vt + 3 * (size_t)fv[2]);
+            else
+                bad = 1;
+            area[k] = a;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+#pragma unroll 8
+            for (int k = 0; k < n; ++k) {
+                const double a = area[k];
+                run = run + a;
+                ct[base + k] = run;
+                last = (a > 0.0) ? base + k : last;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const bool degenerate = !(run > 0.0) || !__builtin_isfinite(run);
+        lastpos[t] = (degenerate || bad) ? -1 : last;
+        if (bad) atomicOr(status, (unsigned)ST_BAD_FACE);
+        if (degenerate) atomicOr(status, (unsigned)ST_DEGENERATE);
+    }
+}
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 64x64->128 products
+// with a Weyl key schedule.
+struct Words4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Words4 philox_words(uint64_t seed, uint32_t t, uint32_t i) {
+    uint64_t c0 = i, c1 = t, c2 = 0, c3 = 0;
+    uint64_t k0 = seed, k1 = 0;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t m0 = 0xD2E7470EE14C6C93ull, m1 = 0xCA5A826395121157ull;
+        const uint64_t p0hi = __umul64hi(m0, c0), p0lo = m0 * c0;
+        const uint64_t p1hi = __umul64hi(m1, c2), p1lo = m1 * c2;
+        const uint64_t n0 = p1hi ^ c1 ^ k0;
+        const uint64_t n2 = p0hi ^ c3 ^ k1;
+        c0 = n0;
+        c1 = p1lo;
+        c2 = n2;
+        c3 = p0lo;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+    Words4 w;
+    w.w0 = (uint32_t)c0;
+    w.w1 = (uint32_t)(c0 >> 32);
+    w.w2 = (uint32_t)(c1 >> 32);
+    w.w3 = (uint32_t)(c2 >> 32);
+    return w;
+}
+
+constexpr int SP_THREADS = 256;
+
+__global__ __launch_bounds__(SP_THREADS) void k_sample(
+    const float *__restrict__ verts, const int32_t *__restrict__ faces, int V, int F, int N,
+    uint64_t seed, const uint32_t *__restrict__ uniforms, const double *__restrict__ cdf,
+    const int32_t *__restrict__ lastpos, float *__restrict__ points, int32_t *__restrict__ face_idx,
+    float *__restrict__ bary) {
+    const int t = blockIdx.y;
+    const int i = blockIdx.x * SP_THREADS + threadIdx.x;
+    if (i >= N) return;
+    const size_t o = (size_t)t * N + i;
+    const int lp = lastpos[t];
+    if (lp < 0) {  // degenerate frame or bad faces: reported through the status word
+        const float nan = __builtin_nanf("");
+        points[3 * o] = nan;
+        points[3 * o + 1] = nan;
+        points[3 * o + 2] = nan;
+        bary[3 * o] = 0.f;
+        bary[3 * o + 1] = 0.f;
+        bary[3 * o + 2] = 0.f;
+        face_idx[o] = -1;
+        return;
+    }
+    Words4 w;
+    if (uniforms) {
+        const uint4 u = reinterpret_cast<const uint4 *>(uniforms)[o];
+        w.w0 = u.x;
+        w.w1 = u.y;
+        w.w2 = u.z;
+        w.w3 = u.w;
+    } else {
+        w = philox_words(seed, (uint32_t)t, (uint32_t)i);
+    }
+    // inverse CDF: first k with C_k > r * S
+    const double *ct = cdf + (size_t)t * F;
+    const uint64_t bits = (((uint64_t)w.w1 << 32) | (uint64_t)w.w0) >> 11;
+    const double r = (double)bits * 0x1p-53;
+    const double target = r * ct[F - 1];
+    int lo = 0, hi = F;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ct[mid] > target)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    const int f = (lo < F) ? lo : lp;
+    // barycentric point, Eq. 3, with the square-root weights
+    const float r1 = (float)(w.w2 >> 8) * 0x1p-24f;
+    const float r2 = (float)(w.w3 >> 8) * 0x1p-24f;
+    const float s = __builtin_sqrtf(r1);
+    const float bu = 1.0f - s;
+    const float bv = s * (1.0f - r2);
+    const float bw = s * r2;
+    const int32_t *fv = faces + 3 * (size_t)f;
+    const float *vt = verts + (size_t)t * V * 3;
+    const float *p1 = vt + 3 * (size_t)fv[0];
+    const float *p2 = vt + 3 * (size_t)fv[1];
+    const float *p3 = vt + 3 * (size_t)fv[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        points[3 * o + k] = __builtin_fmaf(bw, p3[k], __builtin_fmaf(bv, p2[k], bu * p1[k]));
+    bary[3 * o] = bu;
+    bary[3 * o + 1] = bv;
+    bary[3 * o + 2] = bw;
+    face_idx[o] = f;
+}
+
+}  // namespace
+
+size_t sample_scratch_bytes(int T, int F) {
+    return Arena::need((size_t)T * F, sizeof(double)) + Arena::need((size_t)T, sizeof(int32_t));
+}
+
+void launch_sample(const float *verts, const int32_t *faces, int T, int V, int F, int N,
+                   uint64_t seed, const uint32_t *uniforms, float *points, int32_t *face_idx,
+                   float *bary, double *cdf_scratch, int32_t *lastpos_scratch, unsigned *status,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_area_cdf, dim3(T), dim3(AC_THREADS), 0, s, verts, faces, V, F,
+                       cdf_scratch, lastpos_scratch, status);
+    dim3 grid((N + SP_THREADS - 1) / SP_THREADS, T);
+    hipLaunchKernelGGL(k_sample, grid, dim3(SP_THREADS), 0, s, verts, faces, V, F, N, seed,
+                       uniforms, cdf_scratch, lastpos_scratch, points, face_idx, bary);
+}
+
+}  // namespace dc

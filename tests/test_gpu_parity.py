@@ -1,0 +1,279 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on the same seeded
+inputs.  Indices and sampled points must match bit for bit; distances, losses and gradients to
+the tolerances stated in each test (1e-5 relative in float32)."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import gen
+
+from gpu_helpers import assert_grad, assert_rel, dev, gpu, host, say, torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample_both(p, verts, faces, N, words=None, seed=None):
+    """GPU and oracle sampling of the same trajectory."""
+    vt, ft = dev(verts), dev(faces)
+    if words is not None:
+        g = p.sample_surface(vt, ft, N, uniforms=dev(words.view(np.int32)))
+        o = oracle.sample_surface(verts, faces, N, words=words)
+    else:
+        g = p.sample_surface(vt, ft, N, seed=seed)
+        o = oracle.sample_surface(verts, faces, N, seed=seed)
+    torch.cuda.synchronize()
+    return [host(x) for x in g], o
+
+
+@pytest.mark.parametrize("case", ["cfg1-words", "cfg1-philox", "cfg2-3frames", "ragged"])
+def test_sample_parity(case):
+    p = gpu()
+    say(f"[sample] {case}")
+    if case.startswith("cfg1"):
+        w = gen.workload(1)
+        verts, faces, N = w["verts"], w["faces"], w["Na"]
+        words = w["words"] if case.endswith("words") else None
+        seed = None if words is not None else w["seed"]
+    elif case == "cfg2-3frames":
+        w = gen.workload(2, T=3)
+        verts, faces, N, words, seed = w["verts"], w["faces"], w["Na"], w["words"], None
+    else:  # tiny mesh, ragged point count
+        verts, faces = gen.trajectory(3, 2, 9)
+        N, words, seed = 37, None, 123456789012345
+    (gp, gf, gb), (op, of, ob) = _sample_both(p, verts, faces, N, words, seed)
+    assert np.array_equal(gf, of)
+    assert np.array_equal(gp.view(np.uint32), op.view(np.uint32))
+    assert np.array_equal(gb.view(np.uint32), ob.view(np.uint32))
+
+
+def test_sqrt_all_levels():
+    """Every one of the 2^24 values of r1 goes through a correctly rounded square root: with
+    r2 = 0 the weight v equals s = sqrt(r1) exactly, compared with the host's IEEE sqrt."""
+    p = gpu()
+    say("[sample] sqrt over 2^24 levels")
+    n = 1 << 24
+    verts = np.array([[[0, 0, 0], [1, 0, 0], [0, 1, 0]]], np.float32)
+    faces = np.array([[0, 1, 2]], np.int32)
+    words = np.zeros((1, n, 4), np.uint32)
+    words[0, :, 2] = np.arange(n, dtype=np.uint32) << 8
+    _, _, b = p.sample_surface(dev(verts), dev(faces), n, uniforms=dev(words.view(np.int32)))
+    s_gpu = host(b)[0, :, 1]
+    r1 = (np.arange(n, dtype=np.float64) * 2.0**-24).astype(np.float32)
+    s_host = np.sqrt(r1)
+    assert np.array_equal(s_gpu.view(np.uint32), s_host.view(np.uint32))
+
+
+def test_sample_degenerate_and_bad_faces():
+    p = gpu()
+    say("[sample] degenerate / bad faces")
+    ctx = p.Context(0)
+    verts = np.zeros((2, 3, 3), np.float32)
+    verts[1] = [[0, 0, 0], [1, 0, 0], [0, 1, 0]]  # frame 1 fine, frame 0 zero area
+    faces = np.array([[0, 1, 2]], np.int32)
+    pts, fi, ba = p.sample_surface(dev(verts), dev(faces), 5, seed=1, ctx=ctx)
+    with pytest.raises(p.DCError) as e:
+        ctx.sync()
+    assert e.value.code == -5
+    fi = host(fi)
+    assert np.all(fi[0] == -1) and np.all(fi[1] == 0)
+    assert np.all(np.isnan(host(pts)[0]))
+    ctx.sync()  # the status is cleared after being reported
+    bad = np.array([[0, 1, 7]], np.int32)
+    p.sample_surface(dev(verts[1:]), dev(bad), 5, seed=1, ctx=ctx)
+    with pytest.raises(p.DCError) as e:
+        ctx.sync()
+    assert e.value.code == -1
+    ctx.close()
+
+
+def test_invalid_arguments():
+    p = gpu()
+    a = torch.zeros((1, 4, 3), device="cuda")
+    with pytest.raises(p.DCError) as e:
+        p.chamfer_fwd(a, a, precision=7)
+    assert e.value.code == -1
+    with pytest.raises(p.DCError):
+        p.chamfer_fwd(a, a, reduction=3)
+    z = torch.zeros((1, 0, 3), device="cuda")
+    with pytest.raises(p.DCError):
+        p.chamfer_fwd(z, a)
+    with pytest.raises(ValueError):
+        p.chamfer_fwd(a[:, ::2], a)
+
+
+def _chamfer_both(p, A, B, reduction=0, frame_w=None, precision=0):
+    g = p.chamfer_fwd(dev(A), dev(B), precision=precision, reduction=reduction,
+                      frame_w=None if frame_w is None else dev(frame_w))
+    torch.cuda.synchronize()
+    g = {k: host(v) for k, v in g.items()}
+    o = oracle.chamfer(A, B, reduction, frame_w)
+    return g, o
+
+
+def _check_chamfer(g, o):
+    assert np.array_equal(g["idx_a"], o["idx_a"])
+    assert np.array_equal(g["idx_b"], o["idx_b"])
+    assert np.array_equal(g["dist_a"].view(np.uint32), o["d32a"].view(np.uint32))
+    assert np.array_equal(g["dist_b"].view(np.uint32), o["d32b"].view(np.uint32))
+    nz = o["d64a"] > 0
+    assert_rel(g["dist_a"][nz], o["d64a"][nz], 1e-5, "dist_a vs double")
+    assert_rel(g["loss"], o["loss"], 1e-5, "loss")
+
+
+CHAMFER_CASES = {
+    "cfg1": lambda: (lambda w: (oracle.sample_surface(w["verts"], w["faces"], w["Na"],
+                                                      words=w["words"])[0], w["observed"]))(
+        gen.workload(1)),
+    "cfg2-3frames": lambda: (lambda w: (oracle.sample_surface(w["verts"], w["faces"], w["Na"],
+                                                              words=w["words"])[0],
+                                        w["observed"]))(gen.workload(2, T=3)),
+    "ragged-1x1": lambda: (np.random.default_rng(1).uniform(-.5, .5, (2, 1, 3)).astype(np.float32),
+                           np.random.default_rng(2).uniform(-.5, .5, (2, 1, 3)).astype(np.float32)),
+    "ragged-1000x4097": lambda: (
+        np.random.default_rng(3).uniform(-.5, .5, (2, 1000, 3)).astype(np.float32),
+        np.random.default_rng(4).uniform(-.5, .5, (2, 4097, 3)).astype(np.float32)),
+    "ragged-1025x3": lambda: (
+        np.random.default_rng(5).uniform(-.5, .5, (1, 1025, 3)).astype(np.float32),
+        np.random.default_rng(6).uniform(-.5, .5, (1, 3, 3)).astype(np.float32)),
+    "slices-2x20000": lambda: (
+        np.random.default_rng(7).uniform(-.5, .5, (1, 20000, 3)).astype(np.float32),
+        np.random.default_rng(8).uniform(-.5, .5, (1, 20000, 3)).astype(np.float32)),
+}
+
+
+@pytest.mark.parametrize("case", list(CHAMFER_CASES))
+@pytest.mark.parametrize("precision", [0])
+def test_chamfer_parity(case, precision):
+    p = gpu()
+    say(f"[chamfer] {case} precision={precision}")
+    A, B = CHAMFER_CASES[case]()
+    g, o = _chamfer_both(p, A, B, precision=precision)
+    _check_chamfer(g, o)
+
+
+@pytest.mark.parametrize("precision", [0])
+def test_chamfer_ties_and_identity(precision):
+    p = gpu()
+    say(f"[chamfer] ties precision={precision}")
+    r = np.random.default_rng(21)
+    A = r.uniform(-.5, .5, (1, 3000, 3)).astype(np.float32)
+    g, o = _chamfer_both(p, A, A.copy(), precision=precision)
+    _check_chamfer(g, o)
+    assert np.array_equal(g["idx_a"][0], np.arange(3000)) and g["loss"][0] == 0.0
+    # exact duplicates in the target: ties must go to the smallest index
+    B = np.concatenate([A[:, :1500], A[:, :1500], A[:, 1500:]], axis=1)
+    g, o = _chamfer_both(p, A, B, precision=precision)
+    _check_chamfer(g, o)
+    # a grid with many equidistant neighbours
+    x = np.arange(16, dtype=np.float32) / 16
+    G = np.stack(np.meshgrid(x, x, x, indexing="ij"), -1).reshape(1, -1, 3)
+    Q = (G[:, ::7] + np.float32(1 / 32)).astype(np.float32)
+    g, o = _chamfer_both(p, Q, G, precision=precision)
+    _check_chamfer(g, o)
+
+
+@pytest.mark.parametrize("reduction", [0, 1])
+def test_loss_reductions_and_weights(reduction):
+    p = gpu()
+    r = np.random.default_rng(31)
+    A = r.uniform(-.5, .5, (3, 500, 3)).astype(np.float32)
+    B = r.uniform(-.5, .5, (3, 700, 3)).astype(np.float32)
+    w = np.array([0.5, 0.0, 2.0], np.float32)
+    g, o = _chamfer_both(p, A, B, reduction=reduction, frame_w=w)
+    _check_chamfer(g, o)
+
+
+@pytest.mark.parametrize("cfg,T", [(1, None), (3, None), (2, 2)])
+@pytest.mark.parametrize("reduction", [0, 1])
+def test_backward_parity(cfg, T, reduction):
+    """Chamfer backward and sampling backward against the oracle's double gradients."""
+    p = gpu()
+    say(f"[backward] cfg{cfg} reduction={reduction}")
+    w = gen.workload(cfg, T=T)
+    verts, faces, obs, words = w["verts"], w["faces"], w["observed"], w["words"]
+    Tn = verts.shape[0]
+    fw = np.linspace(0.5, 1.5, Tn).astype(np.float32)
+    gl = np.linspace(1.0, -0.5, Tn)
+    pts, fi, ba = oracle.sample_surface(verts, faces, w["Na"], words=words)
+    och = oracle.chamfer(pts, obs, reduction, fw)
+    og = oracle.chamfer_grad(pts, obs, och["idx_a"], och["idx_b"], reduction, fw, gl,
+                             want_b=True)
+    ogv, ogva = oracle.sample_grad(og["ga"], faces, fi, ba, w["V"], og["ga_abs"])
+    # GPU pipeline on the same inputs
+    gpts, gfi, gba = p.sample_surface(dev(verts), dev(faces), w["Na"],
+                                      uniforms=dev(words.view(np.int32)))
+    fwd = p.chamfer_fwd(gpts, dev(obs), reduction=reduction, frame_w=dev(fw))
+    ga, gb = p.chamfer_bwd(dev(gl), gpts, dev(obs), fwd["idx_a"], fwd["idx_b"],
+                           reduction=reduction, frame_w=dev(fw), want_b=True)
+    gv = p.sample_surface_bwd(ga, dev(faces), gfi, gba, w["V"])
+    torch.cuda.synchronize()
+    assert np.array_equal(host(fwd["idx_a"]), och["idx_a"])
+    assert_grad(host(ga), og["ga"], og["ga_abs"], what="grad_a")
+    assert_grad(host(gb), og["gb"], og["gb_abs"], what="grad_b")
+    assert_grad(host(gv), ogv, ogva, what="grad_verts")
+
+
+def test_determinism():
+    p = gpu()
+    w = gen.workload(3)
+    verts, faces, obs = dev(w["verts"]), dev(w["faces"]), dev(w["observed"])
+    outs = []
+    for _ in range(2):
+        pts, fi, ba = p.sample_surface(verts, faces, w["Na"], seed=5)
+        f = p.chamfer_fwd(pts, obs)
+        ga, gb = p.chamfer_bwd(torch.ones(w["T"], dtype=torch.float64, device="cuda"), pts, obs,
+                               f["idx_a"], f["idx_b"], want_b=True)
+        gv = p.sample_surface_bwd(ga, faces, fi, ba, w["V"])
+        outs.append([host(x).copy() for x in (pts, f["idx_a"], f["idx_b"], f["loss"], ga, gb, gv)])
+    for x, y in zip(*outs):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+
+
+@pytest.mark.parametrize("precision", [0])
+def test_full_size_sampled(precision):
+    """The 100-frame, 65,536 x 65,536 workload in the benchmark's launch configuration: sampled
+    points checked bit-exactly on a few whole frames, nearest neighbours checked exactly on
+    sampled queries (the oracle searches the full frame for each), and properties of the whole
+    gradient that hold at any size."""
+    p = gpu()
+    say(f"[full-size] precision={precision}")
+    w = gen.workload(4)
+    verts, faces, obs = w["verts"], w["faces"], w["observed"]
+    T, Na, Nb = w["T"], w["Na"], w["Nb"]
+    pts, fi, ba = p.sample_surface(dev(verts), dev(faces), Na, seed=w["seed"])
+    f = p.chamfer_fwd(pts, dev(obs), precision=precision)
+    ga, gb = p.chamfer_bwd(torch.ones(T, dtype=torch.float64, device="cuda"), pts, dev(obs),
+                           f["idx_a"], f["idx_b"], want_b=True)
+    gv = p.sample_surface_bwd(ga, dev(faces), fi, ba, w["V"])
+    torch.cuda.synchronize()
+    hp, hfi, ia, ib = host(pts), host(fi), host(f["idx_a"]), host(f["idx_b"])
+    r = np.random.default_rng(44)
+    frames = sorted(r.choice(T, 3, replace=False))
+    for t in frames:
+        op, ofi, _ = oracle.sample_surface(verts[t:t + 1], faces, Na,
+                                           words=_words_frame(w["seed"], t, Na))
+        assert np.array_equal(hfi[t], ofi[0])
+        assert np.array_equal(hp[t].view(np.uint32), op[0].view(np.uint32))
+        qa = r.choice(Na, 48, replace=False)
+        oi, od, _ = oracle.nearest(op[0][qa], obs[t])
+        assert np.array_equal(ia[t][qa], oi)
+        qb = r.choice(Nb, 48, replace=False)
+        oi, od, _ = oracle.nearest(obs[t][qb], op[0])
+        assert np.array_equal(ib[t][qb], oi)
+    # whole-gradient properties: translation invariance makes every frame's a- and b-gradients
+    # sum to zero; Eq. 4 weights sum to one, so vertex gradients sum to the point gradients
+    sa = host(ga).astype(np.float64).sum(1)
+    sb = host(gb).astype(np.float64).sum(1)
+    scale = np.abs(host(ga)).astype(np.float64).sum(1) + 1e-30
+    assert np.all(np.abs(sa + sb) <= 1e-4 * scale)
+    sv = host(gv).astype(np.float64).sum(1)
+    assert np.all(np.abs(sv - sa) <= 1e-4 * scale)
+
+
+def _words_frame(seed, t, N):
+    """Philox words of one frame t (the generator is keyed by frame, so a frame can be drawn
+    alone)."""
+    full = np.zeros((1, N, 4), np.uint32)
+    c = oracle.words_from_seed(seed, t + 1, N)
+    full[0] = c[t]
+    return full
