@@ -107,6 +107,11 @@ void launch_sample(const float *verts, const int32_t *faces, int T, int V, int F
 size_t nn_exact_scratch_bytes(int T, int Nq, int Np);
 void launch_nn_exact_ws(const float *Q, int Nq, const float *P, int Np, int T, int32_t *idx,
                         float *dist, char *scratch, hipStream_t st);
+// the same search restricted, per frame t, to the rows qlist[t*Nq + k], k < qcount[t]
+size_t nn_exact_list_scratch_bytes(int T, int Nq, int Np);
+void launch_nn_exact_list(const float *Q, int Nq, const float *P, int Np, int T,
+                          const int32_t *qlist, const int32_t *qcount, int32_t *idx, float *dist,
+                          char *scratch, hipStream_t st);
 
 // bf16 matrix-core screen + certified exact refine (same outputs as launch_nn_exact)
 bool screen_available();

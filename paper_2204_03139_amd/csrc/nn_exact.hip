@@ -27,15 +27,21 @@ __device__ __forceinline__ float canon_d2(float qx, float qy, float qz, float px
     return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
 }
 
+// qlist/qcount (optional): per frame, only the queries qlist[t*Nq + k], k < qcount[t], are
+// searched; slice partials are then indexed by k and the merge maps them back to the rows.
 template <int QPT>
 __global__ __launch_bounds__(NN_THREADS) void k_nn_exact(const float *__restrict__ Q, int Nq,
                                                          const float *__restrict__ P, int Np,
                                                          int slice_len, int32_t *__restrict__ idx,
                                                          float *__restrict__ dist,
-                                                         size_t slice_stride) {
+                                                         size_t slice_stride,
+                                                         const int32_t *__restrict__ qlist,
+                                                         const int32_t *__restrict__ qcount) {
     __shared__ float4 tile[NN_TILE];
     const int t = blockIdx.y;
     const int z = blockIdx.z;
+    const int nq_live = qlist ? qcount[t] : Nq;
+    if ((int)(blockIdx.x * NN_THREADS * QPT) >= nq_live) return;  // uniform per block
     const float *Qt = Q + (size_t)t * Nq * 3;
     const float *Pt = P + (size_t)t * Np * 3;
     const int j_begin = z * slice_len;
@@ -46,8 +52,9 @@ __global__ __launch_bounds__(NN_THREADS) void k_nn_exact(const float *__restrict
     int bsub[QPT];
 #pragma unroll
     for (int k = 0; k < QPT; ++k) {
-        const int qi = q0 + k * NN_THREADS;
-        const bool ok = qi < Nq;
+        const int qk = q0 + k * NN_THREADS;
+        const bool ok = qk < nq_live;
+        const int qi = ok ? (qlist ? qlist[(size_t)t * Nq + qk] : qk) : 0;
         qx[k] = ok ? Qt[3 * (size_t)qi] : 0.f;
         qy[k] = ok ? Qt[3 * (size_t)qi + 1] : 0.f;
         qz[k] = ok ? Qt[3 * (size_t)qi + 2] : 0.f;
@@ -104,8 +111,9 @@ __global__ __launch_bounds__(NN_THREADS) void k_nn_exact(const float *__restrict
     // rescan the winning sub-tile for the first exact match
 #pragma unroll
     for (int k = 0; k < QPT; ++k) {
-        const int qi = q0 + k * NN_THREADS;
-        if (qi >= Nq) continue;
+        const int qk = q0 + k * NN_THREADS;
+        if (qk >= nq_live) continue;
+        const int qi = (qlist && slice_stride == 0) ? qlist[(size_t)t * Nq + qk] : qk;
         const int js = bsub[k];
         const int je = min(js + NN_SUB, j_end);
         int found = js;
@@ -123,12 +131,17 @@ __global__ __launch_bounds__(NN_THREADS) void k_nn_exact(const float *__restrict
 }
 
 // combine per-slice winners; slices hold increasing index ranges, so strict-less keeps the
-// smallest index among equal distances
+// smallest index among equal distances.  With a query list, position k of frame t goes back to
+// row qlist[t*Nq + k].
 __global__ void k_nn_merge(const int32_t *__restrict__ pidx, const float *__restrict__ pdist,
-                           int slices, size_t slice_stride, size_t total, int32_t *__restrict__ idx,
-                           float *__restrict__ dist) {
+                           int slices, size_t slice_stride, int Nq, int T,
+                           int32_t *__restrict__ idx, float *__restrict__ dist,
+                           const int32_t *__restrict__ qlist, const int32_t *__restrict__ qcount) {
     const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= total) return;
+    if (o >= (size_t)T * Nq) return;
+    const int t = (int)(o / Nq);
+    const int k = (int)(o - (size_t)t * Nq);
+    if (qlist && k >= qcount[t]) return;
     float b = pdist[o];
     int bi = pidx[o];
     for (int z = 1; z < slices; ++z) {
@@ -138,8 +151,9 @@ __global__ void k_nn_merge(const int32_t *__restrict__ pidx, const float *__rest
             bi = pidx[z * slice_stride + o];
         }
     }
-    idx[o] = bi;
-    dist[o] = b;
+    const size_t out = qlist ? (size_t)t * Nq + qlist[o] : o;
+    idx[out] = bi;
+    dist[out] = b;
 }
 
 constexpr int LOSS_THREADS = 256;
@@ -191,10 +205,9 @@ size_t nn_exact_scratch_bytes(int T, int Nq, int Np) {
     return Arena::need((size_t)s * T * Nq, 4) * 2;
 }
 
-void launch_nn_exact_ws(const float *Q, int Nq, const float *P, int Np, int T, int32_t *idx,
-                        float *dist, char *scratch, hipStream_t st) {
-    const int qpt = nn_qpt(Nq);
-    const int s = nn_slices(Nq, Np, T, qpt);
+static void launch_nn_exact_impl(const float *Q, int Nq, const float *P, int Np, int T,
+                                 int32_t *idx, float *dist, char *scratch, int qpt, int s,
+                                 const int32_t *qlist, const int32_t *qcount, hipStream_t st) {
     const int slice_len = (Np + s - 1) / s;
     const size_t stride = (size_t)T * Nq;
     int32_t *pidx = idx;
@@ -203,21 +216,51 @@ void launch_nn_exact_ws(const float *Q, int Nq, const float *P, int Np, int T, i
         pidx = reinterpret_cast<int32_t *>(scratch);
         pdist = reinterpret_cast<float *>(scratch + Arena::need((size_t)s * T * Nq, 4));
     }
+    // without slices the kernel writes final rows itself (slice_stride 0 marks that case)
+    const size_t kstride = s > 1 ? stride : 0;
     const dim3 grid((Nq + NN_THREADS * qpt - 1) / (NN_THREADS * qpt), T, s);
     if (qpt == 8)
         hipLaunchKernelGGL(k_nn_exact<8>, grid, dim3(NN_THREADS), 0, st, Q, Nq, P, Np, slice_len,
-                           pidx, pdist, stride);
+                           pidx, pdist, kstride, qlist, qcount);
     else if (qpt == 4)
         hipLaunchKernelGGL(k_nn_exact<4>, grid, dim3(NN_THREADS), 0, st, Q, Nq, P, Np, slice_len,
-                           pidx, pdist, stride);
+                           pidx, pdist, kstride, qlist, qcount);
     else
         hipLaunchKernelGGL(k_nn_exact<1>, grid, dim3(NN_THREADS), 0, st, Q, Nq, P, Np, slice_len,
-                           pidx, pdist, stride);
+                           pidx, pdist, kstride, qlist, qcount);
     if (s > 1) {
         const size_t total = (size_t)T * Nq;
         hipLaunchKernelGGL(k_nn_merge, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                           pidx, pdist, s, stride, total, idx, dist);
+                           pidx, pdist, s, stride, Nq, T, idx, dist, qlist, qcount);
     }
+}
+
+void launch_nn_exact_ws(const float *Q, int Nq, const float *P, int Np, int T, int32_t *idx,
+                        float *dist, char *scratch, hipStream_t st) {
+    const int qpt = nn_qpt(Nq);
+    launch_nn_exact_impl(Q, Nq, P, Np, T, idx, dist, scratch, qpt, nn_slices(Nq, Np, T, qpt),
+                         nullptr, nullptr, st);
+}
+
+// slices for a list of unknown length: split the targets so that a short list still spreads
+// over several workgroups
+static int list_slices(int Np) {
+    int s = 1;
+    while (s < 16 && (long)Np / (s * 2) >= 4096) s *= 2;
+    return s;
+}
+
+size_t nn_exact_list_scratch_bytes(int T, int Nq, int Np) {
+    const int s = list_slices(Np);
+    if (s == 1) return 0;
+    return Arena::need((size_t)s * T * Nq, 4) * 2;
+}
+
+void launch_nn_exact_list(const float *Q, int Nq, const float *P, int Np, int T,
+                          const int32_t *qlist, const int32_t *qcount, int32_t *idx, float *dist,
+                          char *scratch, hipStream_t st) {
+    launch_nn_exact_impl(Q, Nq, P, Np, T, idx, dist, scratch, 1, list_slices(Np), qlist, qcount,
+                         st);
 }
 
 void launch_loss(const float *dist_a, const float *dist_b, int T, int Na, int Nb, int reduction,

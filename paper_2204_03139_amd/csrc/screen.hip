@@ -1,13 +1,412 @@
-// bf16 matrix-core screen with certified exact refine: not built yet in this revision.
+// bf16 matrix-core screen + certified exact refine for the all-pairs nearest neighbour
+// (Sec. III-A, Eq. 1/2): the same indices as the exact single-precision search, found faster.
+//
+// Screen (k_screen): the squared distance is expanded as s_ij = |q_i|^2 + |p_j|^2 - 2 q_i.p_j and
+// evaluated as one K=32 dot product per pair on v_mfma_f32_16x16x32_bf16 with fp32 accumulation.
+// Each float coordinate is split exactly into three bf16 parts (x = h + m + l), and the six
+// products hH, hM, mH, hL, lH, mM per coordinate (18 K-slots) plus the two norms, each split in
+// three (6 K-slots), fill 24 of the 32 K-slots; the matrix unit does the whole distance, the vector
+// unit only keeps minimums (one v_min3 per two pairs).  Query rows stay in registers (64 per wave,
+// four 16-row tiles); targets stream through LDS in groups of 256, their bf16 operand built while
+// staging.  Targets are laid out so that, inside each chunk of 1024, result column c of the 64
+// tiles holds the 64 consecutive targets [64c, 64c+64): a (column, chunk) "slot group" is one
+// contiguous run.  For every (lane, row) the kernel keeps the minimum of each of its slot groups,
+// and the two best groups and the third-best value.
+// Certificate: with a rigorous bound e_ij <= C (|q_i|^2 + |p_j|^2) on |s_ij - d_ij| (bf16 splits
+// exact, products exact, at most 24 roundings of the fp32 accumulator at 2^-23), every index whose
+// canonical float distance can equal the minimum has s_ij <= m_i + Delta_i, where m_i is the
+// row's screened minimum and Delta_i bounds the error at the screened winner and at the canonical
+// winner (both lie within sqrt(m_i + e) of q_i, which bounds their norms).  Slot groups whose
+// minimum passes that test are candidates.  A row is "heavy" (searched exhaustively by the exact
+// kernel) if a slot has three passing groups, if it has more than MAXC candidates, or if its
+// minimum is not finite; heavy rows are appended to a per-frame list.
+// Refine (k_refine): one lane per light query evaluates the canonical distance
+// fma(dz,dz,fma(dy,dy,dx*dx)) over its candidate groups and keeps the lexicographic
+// (distance, index) minimum, which is exactly the argmin of the exhaustive search with the
+// smallest-index rule.
 #include "dc_internal.h"
 
 namespace dc {
+namespace {
 
-bool screen_available() { return false; }
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-size_t screen_scratch_bytes(int, int, int) { return 0; }
+constexpr int SC_WAVES = 4;
+constexpr int SC_THREADS = 64 * SC_WAVES;
+constexpr int SC_ATILES = 4;                            // 16-row tiles per wave
+constexpr int SC_ROWS = SC_WAVES * SC_ATILES * 16;       // 256 query rows per workgroup
+constexpr int SC_STAGE = 256;                            // targets staged in LDS per step
+constexpr int SC_CHUNK = 1024;                           // targets per tracking chunk
+constexpr int SC_TILES_PER_CHUNK = SC_CHUNK / 16;        // 64 targets per slot per chunk
+constexpr int MAXC = 14;                                 // candidate slot groups per row
+constexpr int REC_INTS = 2 + MAXC;                       // n, spare, entries
 
-void launch_nn_screened(const float *, int, const float *, int, int, int32_t *, float *, char *,
-                        unsigned long long *, dc_ctx *, hipStream_t) {}
+// bound constant C of the screen error: 24 accumulations at 2^-23 relative on a sum of absolute
+// products <= 2.02 (|q|^2 + |p|^2), plus the dropped split products and the float norms
+constexpr float SCREEN_C = 6.5e-6f;
+constexpr float SCREEN_TAU = 1e-30f;       // absolute slack (denormal flushing of tiny products)
+constexpr float CANON_U13 = 13.0f * 5.9604645e-8f;  // 13 u, u = 2^-24
+
+struct Split3 {
+    __bf16 h, m, l;
+};
+
+// exact three-way split of a float into bf16 parts (round to nearest even at each step)
+__device__ __forceinline__ Split3 split3(float x) {
+    Split3 s;
+    s.h = (__bf16)x;
+    const float r1 = x - (float)s.h;
+    s.m = (__bf16)r1;
+    s.l = (__bf16)(r1 - (float)s.m);
+    return s;
+}
+
+__device__ __forceinline__ float norm2(float x, float y, float z) {
+    return __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x));
+}
+
+// K-slot vectors.  Query side: per coordinate [h,h,m,h,l,m], then |q|^2 parts, then ones.
+// Target side (of -2p): per coordinate [h,m,h,l,h,m], then ones, then |p|^2 parts.
+__device__ __forceinline__ void query_vector(float x, float y, float z, __bf16 (&v)[32]) {
+    const float c[3] = {x, y, z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const Split3 s = split3(c[k]);
+        v[6 * k + 0] = s.h;
+        v[6 * k + 1] = s.h;
+        v[6 * k + 2] = s.m;
+        v[6 * k + 3] = s.h;
+        v[6 * k + 4] = s.l;
+        v[6 * k + 5] = s.m;
+    }
+    const Split3 n = split3(norm2(x, y, z));
+    v[18] = n.h;
+    v[19] = n.m;
+    v[20] = n.l;
+    v[21] = (__bf16)1.0f;
+    v[22] = (__bf16)1.0f;
+    v[23] = (__bf16)1.0f;
+#pragma unroll
+    for (int k = 24; k < 32; ++k) v[k] = (__bf16)0.0f;
+}
+
+__device__ __forceinline__ void target_vector(float x, float y, float z, bool valid,
+                                              __bf16 (&v)[32]) {
+    const float c[3] = {-2.0f * x, -2.0f * y, -2.0f * z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const Split3 s = split3(valid ? c[k] : 0.0f);
+        v[6 * k + 0] = s.h;
+        v[6 * k + 1] = s.m;
+        v[6 * k + 2] = s.h;
+        v[6 * k + 3] = s.l;
+        v[6 * k + 4] = s.h;
+        v[6 * k + 5] = s.m;
+    }
+    v[18] = (__bf16)1.0f;
+    v[19] = (__bf16)1.0f;
+    v[20] = (__bf16)1.0f;
+    const Split3 n = split3(valid ? norm2(x, y, z) : 1e30f);  // padding: a huge distance
+    v[21] = n.h;
+    v[22] = n.m;
+    v[23] = n.l;
+#pragma unroll
+    for (int k = 24; k < 32; ++k) v[k] = (__bf16)0.0f;
+}
+
+__device__ __forceinline__ bf16x8 pick8(const __bf16 (&v)[32], int g) {
+    bf16x8 r;
+    if (g == 0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) r[e] = v[e];
+    } else if (g == 1) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) r[e] = v[8 + e];
+    } else if (g == 2) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) r[e] = v[16 + e];
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) r[e] = v[24 + e];
+    }
+    return r;
+}
+
+// largest squared norm of each frame's targets (for the certificate)
+__global__ __launch_bounds__(256) void k_norm_max(const float *__restrict__ P, int Np,
+                                                  float *__restrict__ out,
+                                                  int32_t *__restrict__ heavy_cnt) {
+    __shared__ float red[256];
+    const int t = blockIdx.x;
+    if (threadIdx.x == 0) heavy_cnt[t] = 0;
+    const float *pt = P + (size_t)t * Np * 3;
+    float m = 0.f;
+    for (int j = threadIdx.x; j < Np; j += 256)
+        m = fmaxf(m, norm2(pt[3 * (size_t)j], pt[3 * (size_t)j + 1], pt[3 * (size_t)j + 2]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[t] = red[0];
+}
+
+__global__ __launch_bounds__(SC_THREADS) void k_screen(const float *__restrict__ Q, int Nq,
+                                                       const float *__restrict__ P, int Np,
+                                                       const float *__restrict__ npmax,
+                                                       int32_t *__restrict__ rec,
+                                                       int32_t *__restrict__ heavy_cnt,
+                                                       int32_t *__restrict__ heavy_list) {
+    __shared__ bf16x8 stage[4][SC_STAGE];  // [K-chunk][target] -> 16 bytes, conflict-free reads
+    const int t = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;   // K-chunk of the operands; row group of the result
+    const int col = lane & 15; // row of the A operand; column (slot) of the result
+    const float *Qt = Q + (size_t)t * Nq * 3;
+    const float *Pt = P + (size_t)t * Np * 3;
+    const int row0 = blockIdx.x * SC_ROWS + wave * (SC_ATILES * 16);
+
+    // query operands, held for the whole sweep
+    bf16x8 A[SC_ATILES];
+#pragma unroll
+    for (int a = 0; a < SC_ATILES; ++a) {
+        const int r = row0 + 16 * a + col;
+        __bf16 v[32];
+        if (r < Nq)
+            query_vector(Qt[3 * (size_t)r], Qt[3 * (size_t)r + 1], Qt[3 * (size_t)r + 2], v);
+        else
+            query_vector(0.f, 0.f, 0.f, v);
+        A[a] = pick8(v, g);
+    }
+
+    const float inf = __builtin_inff();
+    float m[SC_ATILES][4], b1[SC_ATILES][4], b2[SC_ATILES][4], b3[SC_ATILES][4];
+    int c1[SC_ATILES][4], c2[SC_ATILES][4];
+#pragma unroll
+    for (int a = 0; a < SC_ATILES; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            m[a][r] = inf;
+            b1[a][r] = inf;
+            b2[a][r] = inf;
+            b3[a][r] = inf;
+            c1[a][r] = -1;
+            c2[a][r] = -1;
+        }
+    const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+    const int nstage = ((Np + SC_CHUNK - 1) / SC_CHUNK) * (SC_CHUNK / SC_STAGE);
+    for (int st = 0; st < nstage; ++st) {
+        const int base = st * SC_STAGE;
+        __syncthreads();
+        {
+            // tile-local position (btl, c) of this stage holds target 64c + 16*(stage in chunk)
+            // + btl of the chunk, so column c of a chunk is a contiguous run of 64 targets
+            const int c = threadIdx.x >> 4, btl = threadIdx.x & 15;
+            const int chunk_base = (base / SC_CHUNK) * SC_CHUNK;
+            const int j = chunk_base + 64 * c + 16 * ((base % SC_CHUNK) / SC_STAGE) + btl;
+            const bool valid = j < Np;
+            const float x = valid ? Pt[3 * (size_t)j] : 0.f;
+            const float y = valid ? Pt[3 * (size_t)j + 1] : 0.f;
+            const float z = valid ? Pt[3 * (size_t)j + 2] : 0.f;
+            __bf16 v[32];
+            target_vector(x, y, z, valid, v);
+            const int pos = btl * 16 + c;
+            stage[0][pos] = pick8(v, 0);
+            stage[1][pos] = pick8(v, 1);
+            stage[2][pos] = pick8(v, 2);
+            stage[3][pos] = pick8(v, 3);
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int bt = 0; bt < SC_STAGE / 16; bt += 2) {
+            const bf16x8 B0 = stage[g][bt * 16 + col];
+            const bf16x8 B1 = stage[g][bt * 16 + 16 + col];
+#pragma unroll
+            for (int a = 0; a < SC_ATILES; ++a) {
+                const floatx4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B0, zero, 0, 0, 0);
+                const floatx4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B1, zero, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) m[a][r] = fminf(m[a][r], fminf(d0[r], d1[r]));
+            }
+        }
+        const bool chunk_end = ((base + SC_STAGE) % SC_CHUNK == 0) || (st == nstage - 1);
+        if (chunk_end) {
+            const int k = base / SC_CHUNK;
+#pragma unroll
+            for (int a = 0; a < SC_ATILES; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float x = m[a][r];
+                    const bool t1 = x < b1[a][r];
+                    const bool t2 = x < b2[a][r];
+                    b3[a][r] = __builtin_amdgcn_fmed3f(x, b2[a][r], b3[a][r]);
+                    b2[a][r] = __builtin_amdgcn_fmed3f(x, b1[a][r], b2[a][r]);
+                    b1[a][r] = fminf(x, b1[a][r]);
+                    c2[a][r] = t1 ? c1[a][r] : (t2 ? k : c2[a][r]);
+                    c1[a][r] = t1 ? k : c1[a][r];
+                    m[a][r] = inf;
+                }
+        }
+    }
+
+    // certificate and candidate records; the 16 lanes of a group share one row per (a, r)
+    const float npm = npmax[t];
+    const unsigned long long gmask = 0xFFFFull << (16 * g);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int a = 0; a < SC_ATILES; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = row0 + 16 * a + 4 * g + r;
+            float mi = b1[a][r];
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) mi = fminf(mi, __shfl_xor(mi, off, 64));
+            float nq = 0.f;
+            if (row < Nq)
+                nq = norm2(Qt[3 * (size_t)row], Qt[3 * (size_t)row + 1], Qt[3 * (size_t)row + 2]);
+            // Delta: error bound at the screened winner (E1) and at the canonical winner (E2);
+            // each winner lies within sqrt(distance) of q, which bounds its squared norm
+            const float up = 1.0001f;
+            const float qn = __builtin_sqrtf(nq) * up;
+            const float mp = fmaxf(mi, 0.f);
+            const float e0 = (SCREEN_C * (nq + npm) + SCREEN_TAU) * up;
+            const float r0 = qn + __builtin_sqrtf(mp + e0) * up;
+            const float e1 = (SCREEN_C * (nq + r0 * r0) + SCREEN_TAU) * up;
+            const float d1 = (mp + e1) * (1.0f + CANON_U13) * up;
+            const float r1 = qn + __builtin_sqrtf(d1) * up;
+            const float e2 = (SCREEN_C * (nq + r1 * r1) + SCREEN_TAU) * up;
+            const float theta = (mi + e1 + e2 + CANON_U13 * (mp + e1)) * up + SCREEN_TAU;
+            const bool finite = __builtin_isfinite(mi) && __builtin_isfinite(theta) &&
+                                __builtin_isfinite(npm);
+            const bool k1 = finite && c1[a][r] >= 0 && b1[a][r] <= theta;
+            const bool k2 = finite && c2[a][r] >= 0 && b2[a][r] <= theta;
+            const bool over = finite && b3[a][r] <= theta;
+            const unsigned long long m1 = __ballot(k1) & gmask;
+            const unsigned long long m2 = __ballot(k2) & gmask;
+            const unsigned long long mo = __ballot(over) & gmask;
+            const int n = __popcll(m1) + __popcll(m2);
+            const bool heavy = !finite || n > MAXC || mo != 0ull;
+            if (row < Nq) {
+                int32_t *rr = rec + ((size_t)t * Nq + row) * REC_INTS;
+                if (col == 0) {
+                    rr[0] = heavy ? -1 : n;
+                    if (heavy) {
+                        const int pos = atomicAdd(&heavy_cnt[t], 1);
+                        heavy_list[(size_t)t * Nq + pos] = row;
+                    }
+                }
+                if (!heavy) {
+                    const int off = __popcll(m1 & below) + __popcll(m2 & below);
+                    if (k1) rr[2 + off] = (c1[a][r] << 4) | col;
+                    if (k2) rr[2 + off + (k1 ? 1 : 0)] = (c2[a][r] << 4) | col;
+                }
+            }
+        }
+}
+
+__device__ __forceinline__ float canon_d2(float qx, float qy, float qz, const float *p) {
+    const float dx = qx - p[0];
+    const float dy = qy - p[1];
+    const float dz = qz - p[2];
+    return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+}
+
+constexpr int RF_THREADS = 256;
+
+// exact re-evaluation of the candidate groups of light rows (heavy rows are left to the exact
+// kernel and skipped here)
+__global__ __launch_bounds__(RF_THREADS) void k_refine(const float *__restrict__ Q, int Nq,
+                                                       const float *__restrict__ P, int Np,
+                                                       const int32_t *__restrict__ rec,
+                                                       int32_t *__restrict__ idx,
+                                                       float *__restrict__ dist,
+                                                       unsigned long long *__restrict__ stats) {
+    __shared__ unsigned cnt[2];
+    if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int t = blockIdx.y;
+    const int i = blockIdx.x * RF_THREADS + threadIdx.x;
+    unsigned ncand = 0, nheavy = 0;
+    if (i < Nq) {
+        const int32_t *rr = rec + ((size_t)t * Nq + i) * REC_INTS;
+        const int n = rr[0];
+        if (n < 0) {
+            nheavy = 1;
+        } else {
+            const float *Pt = P + (size_t)t * Np * 3;
+            const float *q = Q + ((size_t)t * Nq + i) * 3;
+            const float qx = q[0], qy = q[1], qz = q[2];
+            float best = __builtin_inff();
+            int bj = Np;
+            for (int e = 0; e < n; ++e) {
+                const int code = rr[2 + e];
+                const int j0 = (code >> 4) * SC_CHUNK + 64 * (code & 15);
+                const int j1 = min(Np, j0 + 64);
+                for (int j = j0; j < j1; ++j) {
+                    const float d = canon_d2(qx, qy, qz, Pt + 3 * (size_t)j);
+                    if (bj == Np || d < best || (d == best && j < bj)) {
+                        best = d;
+                        bj = j;
+                    }
+                }
+            }
+            if (bj == Np) {  // no candidate survived (non-finite data): first index
+                bj = 0;
+                best = canon_d2(qx, qy, qz, Pt);
+            }
+            idx[(size_t)t * Nq + i] = bj;
+            dist[(size_t)t * Nq + i] = best;
+            ncand = (unsigned)n;
+        }
+    }
+    if (stats) {
+        atomicAdd(&cnt[0], ncand);
+        atomicAdd(&cnt[1], nheavy);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int live = min(RF_THREADS, Nq - (int)blockIdx.x * RF_THREADS);
+            atomicAdd(&stats[0], (unsigned long long)live);
+            atomicAdd(&stats[1], (unsigned long long)cnt[0]);
+            atomicAdd(&stats[2], (unsigned long long)cnt[1]);
+        }
+    }
+}
+
+}  // namespace
+
+bool screen_available() { return true; }
+
+size_t screen_scratch_bytes(int T, int Nq, int Np) {
+    return Arena::need((size_t)T, 4) * 2 + Arena::need((size_t)T * Nq, 4) +
+           Arena::need((size_t)T * Nq * REC_INTS, 4) + nn_exact_list_scratch_bytes(T, Nq, Np);
+}
+
+void launch_nn_screened(const float *Q, int Nq, const float *P, int Np, int T, int32_t *idx,
+                        float *dist, char *scratch, unsigned long long *stats, dc_ctx *prof,
+                        hipStream_t s) {
+    Arena ar;
+    ar.base = scratch;
+    ar.cap = screen_scratch_bytes(T, Nq, Np);
+    float *npmax = ar.take<float>((size_t)T);
+    int32_t *heavy_cnt = ar.take<int32_t>((size_t)T);
+    int32_t *heavy_list = ar.take<int32_t>((size_t)T * Nq);
+    int32_t *rec = ar.take<int32_t>((size_t)T * Nq * REC_INTS);
+    char *exact_scratch = ar.take<char>(nn_exact_list_scratch_bytes(T, Nq, Np));
+    hipLaunchKernelGGL(k_norm_max, dim3(T), dim3(256), 0, s, P, Np, npmax, heavy_cnt);
+    {
+        ProfScope ps(prof, 0, s);
+        hipLaunchKernelGGL(k_screen, dim3((Nq + SC_ROWS - 1) / SC_ROWS, T), dim3(SC_THREADS), 0,
+                           s, Q, Nq, P, Np, npmax, rec, heavy_cnt, heavy_list);
+    }
+    {
+        ProfScope ps(prof, 1, s);
+        hipLaunchKernelGGL(k_refine, dim3((Nq + RF_THREADS - 1) / RF_THREADS, T),
+                           dim3(RF_THREADS), 0, s, Q, Nq, P, Np, rec, idx, dist, stats);
+        launch_nn_exact_list(Q, Nq, P, Np, T, heavy_list, heavy_cnt, idx, dist, exact_scratch, s);
+    }
+}
 
 }  // namespace dc

@@ -142,7 +142,7 @@ CHAMFER_CASES = {
 
 
 @pytest.mark.parametrize("case", list(CHAMFER_CASES))
-@pytest.mark.parametrize("precision", [0])
+@pytest.mark.parametrize("precision", [0, 1])
 def test_chamfer_parity(case, precision):
     p = gpu()
     say(f"[chamfer] {case} precision={precision}")
@@ -151,7 +151,7 @@ def test_chamfer_parity(case, precision):
     _check_chamfer(g, o)
 
 
-@pytest.mark.parametrize("precision", [0])
+@pytest.mark.parametrize("precision", [0, 1])
 def test_chamfer_ties_and_identity(precision):
     p = gpu()
     say(f"[chamfer] ties precision={precision}")
@@ -173,14 +173,35 @@ def test_chamfer_ties_and_identity(precision):
 
 
 @pytest.mark.parametrize("reduction", [0, 1])
-def test_loss_reductions_and_weights(reduction):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_loss_reductions_and_weights(reduction, precision):
     p = gpu()
     r = np.random.default_rng(31)
     A = r.uniform(-.5, .5, (3, 500, 3)).astype(np.float32)
     B = r.uniform(-.5, .5, (3, 700, 3)).astype(np.float32)
     w = np.array([0.5, 0.0, 2.0], np.float32)
-    g, o = _chamfer_both(p, A, B, reduction=reduction, frame_w=w)
+    g, o = _chamfer_both(p, A, B, reduction=reduction, frame_w=w, precision=precision)
     _check_chamfer(g, o)
+
+
+def test_screen_candidates_are_few():
+    """The bf16 screen's certificate must leave only a handful of candidate groups per query and
+    rarely fall back to an exhaustive search (otherwise the screen would be pointless)."""
+    p = gpu()
+    say("[screen] candidate statistics, 100x100 grid, 2 frames of 65536 x 65536")
+    w = gen.workload(4, T=2)
+    ctx = p.Context(0)
+    pts, _, _ = p.sample_surface(dev(w["verts"]), dev(w["faces"]), w["Na"], seed=w["seed"],
+                                 ctx=ctx)
+    p.chamfer_fwd(pts, dev(w["observed"]), precision=1, ctx=ctx)
+    ctx.sync()
+    st = ctx.stats()
+    say(f"[screen] {st}")
+    q = st["queries"]
+    assert q == 2 * 2 * 65536
+    assert st["candidates"] / q < 8
+    assert st["fallbacks"] / q < 0.05
+    ctx.close()
 
 
 @pytest.mark.parametrize("cfg,T", [(1, None), (3, None), (2, 2)])
@@ -229,7 +250,7 @@ def test_determinism():
         assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
 
 
-@pytest.mark.parametrize("precision", [0])
+@pytest.mark.parametrize("precision", [0, 1])
 def test_full_size_sampled(precision):
     """The 100-frame, 65,536 x 65,536 workload in the benchmark's launch configuration: sampled
     points checked bit-exactly on a few whole frames, nearest neighbours checked exactly on
