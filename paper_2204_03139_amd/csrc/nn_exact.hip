@@ -41,12 +41,14 @@ __global__ __launch_bounds__(NN_THREADS) void k_nn_exact(const float *__restrict
     const int t = blockIdx.y;
     const int z = blockIdx.z;
     const int nq_live = qlist ? qcount[t] : Nq;
-    if ((int)(blockIdx.x * NN_THREADS * QPT) >= nq_live) return;  // uniform per block
     const float *Qt = Q + (size_t)t * Nq * 3;
     const float *Pt = P + (size_t)t * Np * 3;
     const int j_begin = z * slice_len;
     const int j_end = min(Np, j_begin + slice_len);
-    const int q0 = blockIdx.x * NN_THREADS * QPT + threadIdx.x;
+    // the list of a frame is short and its length only known on the device: each workgroup
+    // walks query blocks blockIdx.x, blockIdx.x + gridDim.x, ... (one step without a list)
+    for (int qb = blockIdx.x; qb * NN_THREADS * QPT < nq_live; qb += gridDim.x) {
+    const int q0 = qb * NN_THREADS * QPT + threadIdx.x;
 
     float qx[QPT], qy[QPT], qz[QPT], best[QPT];
     int bsub[QPT];
@@ -127,6 +129,8 @@ __global__ __launch_bounds__(NN_THREADS) void k_nn_exact(const float *__restrict
         const size_t o = (size_t)z * slice_stride + (size_t)t * Nq + qi;
         idx[o] = found;
         dist[o] = best[k];
+    }
+    __syncthreads();  // the next query block restages the tiles
     }
 }
 
@@ -218,7 +222,8 @@ static void launch_nn_exact_impl(const float *Q, int Nq, const float *P, int Np,
     }
     // without slices the kernel writes final rows itself (slice_stride 0 marks that case)
     const size_t kstride = s > 1 ? stride : 0;
-    const dim3 grid((Nq + NN_THREADS * qpt - 1) / (NN_THREADS * qpt), T, s);
+    const int qblocks = (Nq + NN_THREADS * qpt - 1) / (NN_THREADS * qpt);
+    const dim3 grid(qlist ? 1 : qblocks, T, s);
     if (qpt == 8)
         hipLaunchKernelGGL(k_nn_exact<8>, grid, dim3(NN_THREADS), 0, st, Q, Nq, P, Np, slice_len,
                            pidx, pdist, kstride, qlist, qcount);

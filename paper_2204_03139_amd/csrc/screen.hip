@@ -38,7 +38,6 @@ constexpr int SC_ATILES = 4;                            // 16-row tiles per wave
 constexpr int SC_ROWS = SC_WAVES * SC_ATILES * 16;       // 256 query rows per workgroup
 constexpr int SC_STAGE = 256;                            // targets staged in LDS per step
 constexpr int SC_CHUNK = 1024;                           // targets per tracking chunk
-constexpr int SC_TILES_PER_CHUNK = SC_CHUNK / 16;        // 64 targets per slot per chunk
 constexpr int MAXC = 14;                                 // candidate slot groups per row
 constexpr int REC_INTS = 2 + MAXC;                       // n, spare, entries
 
@@ -159,7 +158,10 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(const float *__restrict__
                                                        int32_t *__restrict__ rec,
                                                        int32_t *__restrict__ heavy_cnt,
                                                        int32_t *__restrict__ heavy_list) {
-    __shared__ bf16x8 stage[4][SC_STAGE];  // [K-chunk][target] -> 16 bytes, conflict-free reads
+    // [K-chunk][entry] -> 16 bytes.  Entry 16*bt + (c ^ bt) holds tile bt, result column c, so
+    // both the staging stores (8 lanes of one column) and the operand reads (16 columns of one
+    // tile) hit distinct banks.  K-chunk 3 is all zeros on the query side and is not stored.
+    __shared__ bf16x8 stage[2][3][SC_STAGE];
     const int t = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -198,43 +200,61 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(const float *__restrict__
         }
     const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
     const int nstage = ((Np + SC_CHUNK - 1) / SC_CHUNK) * (SC_CHUNK / SC_STAGE);
+    // staging position of this thread: tile-local position (btl, c) of a stage holds target
+    // 64c + 16*(stage in chunk) + btl of the chunk, so result column c of a chunk is the
+    // contiguous run [64c, 64c+64)
+    const int sc = threadIdx.x >> 4, sbtl = threadIdx.x & 15;
+    const int spos = sbtl * 16 + (sc ^ sbtl);
+    auto target_of = [&](int st) {
+        return (st / (SC_CHUNK / SC_STAGE)) * SC_CHUNK + 64 * sc + 16 * (st % (SC_CHUNK / SC_STAGE)) +
+               sbtl;
+    };
+    // register prefetch of the next stage's target, double-buffered LDS: one barrier per stage
+    float px = 0.f, py = 0.f, pz = 0.f;
+    bool pvalid;
+    {
+        const int j = target_of(0);
+        pvalid = j < Np;
+        if (pvalid) {
+            px = Pt[3 * (size_t)j];
+            py = Pt[3 * (size_t)j + 1];
+            pz = Pt[3 * (size_t)j + 2];
+        }
+    }
+    const int gk = (g == 3) ? 0 : g;
     for (int st = 0; st < nstage; ++st) {
-        const int base = st * SC_STAGE;
-        __syncthreads();
+        const int buf = st & 1;
         {
-            // tile-local position (btl, c) of this stage holds target 64c + 16*(stage in chunk)
-            // + btl of the chunk, so column c of a chunk is a contiguous run of 64 targets
-            const int c = threadIdx.x >> 4, btl = threadIdx.x & 15;
-            const int chunk_base = (base / SC_CHUNK) * SC_CHUNK;
-            const int j = chunk_base + 64 * c + 16 * ((base % SC_CHUNK) / SC_STAGE) + btl;
-            const bool valid = j < Np;
-            const float x = valid ? Pt[3 * (size_t)j] : 0.f;
-            const float y = valid ? Pt[3 * (size_t)j + 1] : 0.f;
-            const float z = valid ? Pt[3 * (size_t)j + 2] : 0.f;
             __bf16 v[32];
-            target_vector(x, y, z, valid, v);
-            const int pos = btl * 16 + c;
-            stage[0][pos] = pick8(v, 0);
-            stage[1][pos] = pick8(v, 1);
-            stage[2][pos] = pick8(v, 2);
-            stage[3][pos] = pick8(v, 3);
+            target_vector(px, py, pz, pvalid, v);
+            stage[buf][0][spos] = pick8(v, 0);
+            stage[buf][1][spos] = pick8(v, 1);
+            stage[buf][2][spos] = pick8(v, 2);
+        }
+        if (st + 1 < nstage) {
+            const int j = target_of(st + 1);
+            pvalid = j < Np;
+            px = pvalid ? Pt[3 * (size_t)j] : 0.f;
+            py = pvalid ? Pt[3 * (size_t)j + 1] : 0.f;
+            pz = pvalid ? Pt[3 * (size_t)j + 2] : 0.f;
         }
         __syncthreads();
+        // lanes of K-group 3 hold an all-zero query operand, so any finite staged operand gives
+        // them zero products: they read K-chunk 0 instead of a stored zero chunk
 #pragma unroll 2
         for (int bt = 0; bt < SC_STAGE / 16; bt += 2) {
-            const bf16x8 B0 = stage[g][bt * 16 + col];
-            const bf16x8 B1 = stage[g][bt * 16 + 16 + col];
+            const bf16x8 B0 = stage[buf][gk][bt * 16 + (col ^ bt)];
+            const bf16x8 B1 = stage[buf][gk][bt * 16 + 16 + (col ^ (bt + 1))];
 #pragma unroll
             for (int a = 0; a < SC_ATILES; ++a) {
                 const floatx4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B0, zero, 0, 0, 0);
                 const floatx4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B1, zero, 0, 0, 0);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) m[a][r] = fminf(m[a][r], fminf(d0[r], d1[r]));
+                for (int r = 0; r < 4; ++r) m[a][r] = fminf(fminf(m[a][r], d0[r]), d1[r]);
             }
         }
-        const bool chunk_end = ((base + SC_STAGE) % SC_CHUNK == 0) || (st == nstage - 1);
-        if (chunk_end) {
-            const int k = base / SC_CHUNK;
+        if ((st + 1) % (SC_CHUNK / SC_STAGE) == 0) {  // end of a tracking chunk
+            const int k = st / (SC_CHUNK / SC_STAGE);
 #pragma unroll
             for (int a = 0; a < SC_ATILES; ++a)
 #pragma unroll
