@@ -36,6 +36,9 @@ def _args():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample (0 disables it)")
     ap.add_argument("--frames", type=int, default=None, help="override the frame count")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run one plain device-to-device copy of MIB mebibytes (to scale "
+                         "hardware byte counters) and exit")
     return ap.parse_args()
 
 
@@ -127,6 +130,16 @@ def main():
               "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if a.calibrate_copy:
+        n = a.calibrate_copy << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_bytes=n)))
+        return
 
     import paper_2204_03139_amd as p
     from workloads import gen
