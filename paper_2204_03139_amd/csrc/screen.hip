@@ -38,6 +38,7 @@ constexpr int SC_ATILES = 4;                            // 16-row tiles per wave
 constexpr int SC_ROWS = SC_WAVES * SC_ATILES * 16;       // 256 query rows per workgroup
 constexpr int SC_STAGE = 256;                            // targets staged in LDS per step
 constexpr int SC_CHUNK = 1024;                           // targets per tracking chunk
+constexpr int SC_ROWPAD = 17;                            // LDS entries per staged tile
 constexpr int MAXC = 14;                                 // candidate slot groups per row
 constexpr int REC_INTS = 2 + MAXC;                       // n, spare, entries
 
@@ -132,6 +133,23 @@ __device__ __forceinline__ bf16x8 pick8(const __bf16 (&v)[32], int g) {
     return r;
 }
 
+// Target operands of every frame, packed once: target j's three non-zero K-chunks (48 bytes).
+// Padding targets up to a whole chunk get a huge norm so they never win a minimum.
+__global__ __launch_bounds__(256) void k_pack_targets(const float *__restrict__ P, int Np,
+                                                      int Np_pad, bf16x8 *__restrict__ packed) {
+    const int t = blockIdx.y;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= Np_pad) return;
+    const bool valid = j < Np;
+    const float *p = P + ((size_t)t * Np + (valid ? j : 0)) * 3;
+    __bf16 v[32];
+    target_vector(valid ? p[0] : 0.f, valid ? p[1] : 0.f, valid ? p[2] : 0.f, valid, v);
+    bf16x8 *o = packed + ((size_t)t * Np_pad + j) * 3;
+    o[0] = pick8(v, 0);
+    o[1] = pick8(v, 1);
+    o[2] = pick8(v, 2);
+}
+
 // largest squared norm of each frame's targets (for the certificate)
 __global__ __launch_bounds__(256) void k_norm_max(const float *__restrict__ P, int Np,
                                                   float *__restrict__ out,
@@ -153,22 +171,24 @@ __global__ __launch_bounds__(256) void k_norm_max(const float *__restrict__ P, i
 }
 
 __global__ __launch_bounds__(SC_THREADS) void k_screen(const float *__restrict__ Q, int Nq,
-                                                       const float *__restrict__ P, int Np,
+                                                       const bf16x8 *__restrict__ packed,
+                                                       int Np, int Np_pad,
                                                        const float *__restrict__ npmax,
                                                        int32_t *__restrict__ rec,
                                                        int32_t *__restrict__ heavy_cnt,
                                                        int32_t *__restrict__ heavy_list) {
-    // [K-chunk][entry] -> 16 bytes.  Entry 16*bt + (c ^ bt) holds tile bt, result column c, so
-    // both the staging stores (8 lanes of one column) and the operand reads (16 columns of one
-    // tile) hit distinct banks.  K-chunk 3 is all zeros on the query side and is not stored.
-    __shared__ bf16x8 stage[2][3][SC_STAGE];
+    // [buffer][K-chunk][entry] -> 16 bytes.  Entry 17*bt + c holds tile bt, result column c: the
+    // operand reads (16 columns of one tile) are consecutive and the staging stores (8 tiles of
+    // one column, 272 bytes apart) fall in distinct banks; the read address is a per-lane base
+    // plus a compile-time offset.  K-chunk 3 is all zeros on the query side and is not stored.
+    __shared__ bf16x8 stage[2][3][SC_ROWPAD * 16];
     const int t = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4;   // K-chunk of the operands; row group of the result
     const int col = lane & 15; // row of the A operand; column (slot) of the result
     const float *Qt = Q + (size_t)t * Nq * 3;
-    const float *Pt = P + (size_t)t * Np * 3;
+    const bf16x8 *Bt = packed + (size_t)t * Np_pad * 3;
     const int row0 = blockIdx.x * SC_ROWS + wave * (SC_ATILES * 16);
 
     // query operands, held for the whole sweep
@@ -199,52 +219,44 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(const float *__restrict__
             c2[a][r] = -1;
         }
     const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
-    const int nstage = ((Np + SC_CHUNK - 1) / SC_CHUNK) * (SC_CHUNK / SC_STAGE);
+    const int nstage = Np_pad / SC_STAGE;
     // staging position of this thread: tile-local position (btl, c) of a stage holds target
     // 64c + 16*(stage in chunk) + btl of the chunk, so result column c of a chunk is the
     // contiguous run [64c, 64c+64)
     const int sc = threadIdx.x >> 4, sbtl = threadIdx.x & 15;
-    const int spos = sbtl * 16 + (sc ^ sbtl);
+    const int spos = sbtl * SC_ROWPAD + sc;
     auto target_of = [&](int st) {
         return (st / (SC_CHUNK / SC_STAGE)) * SC_CHUNK + 64 * sc + 16 * (st % (SC_CHUNK / SC_STAGE)) +
                sbtl;
     };
-    // register prefetch of the next stage's target, double-buffered LDS: one barrier per stage
-    float px = 0.f, py = 0.f, pz = 0.f;
-    bool pvalid;
+    // register prefetch of the next stage's operands, double-buffered LDS: one barrier per stage
+    bf16x8 q0, q1, q2;
     {
-        const int j = target_of(0);
-        pvalid = j < Np;
-        if (pvalid) {
-            px = Pt[3 * (size_t)j];
-            py = Pt[3 * (size_t)j + 1];
-            pz = Pt[3 * (size_t)j + 2];
-        }
+        const bf16x8 *src = Bt + (size_t)target_of(0) * 3;
+        q0 = src[0];
+        q1 = src[1];
+        q2 = src[2];
     }
     const int gk = (g == 3) ? 0 : g;
     for (int st = 0; st < nstage; ++st) {
         const int buf = st & 1;
-        {
-            __bf16 v[32];
-            target_vector(px, py, pz, pvalid, v);
-            stage[buf][0][spos] = pick8(v, 0);
-            stage[buf][1][spos] = pick8(v, 1);
-            stage[buf][2][spos] = pick8(v, 2);
-        }
+        stage[buf][0][spos] = q0;
+        stage[buf][1][spos] = q1;
+        stage[buf][2][spos] = q2;
         if (st + 1 < nstage) {
-            const int j = target_of(st + 1);
-            pvalid = j < Np;
-            px = pvalid ? Pt[3 * (size_t)j] : 0.f;
-            py = pvalid ? Pt[3 * (size_t)j + 1] : 0.f;
-            pz = pvalid ? Pt[3 * (size_t)j + 2] : 0.f;
+            const bf16x8 *src = Bt + (size_t)target_of(st + 1) * 3;
+            q0 = src[0];
+            q1 = src[1];
+            q2 = src[2];
         }
         __syncthreads();
         // lanes of K-group 3 hold an all-zero query operand, so any finite staged operand gives
         // them zero products: they read K-chunk 0 instead of a stored zero chunk
+        const bf16x8 *sb = &stage[buf][gk][col];
 #pragma unroll 2
         for (int bt = 0; bt < SC_STAGE / 16; bt += 2) {
-            const bf16x8 B0 = stage[buf][gk][bt * 16 + (col ^ bt)];
-            const bf16x8 B1 = stage[buf][gk][bt * 16 + 16 + (col ^ (bt + 1))];
+            const bf16x8 B0 = sb[bt * SC_ROWPAD];
+            const bf16x8 B1 = sb[(bt + 1) * SC_ROWPAD];
 #pragma unroll
             for (int a = 0; a < SC_ATILES; ++a) {
                 const floatx4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B0, zero, 0, 0, 0);
@@ -335,9 +347,14 @@ __device__ __forceinline__ float canon_d2(float qx, float qy, float qz, const fl
 }
 
 constexpr int RF_THREADS = 256;
+constexpr int RF_TEAM = 16;                         // lanes per query
+constexpr int RF_TEAMS = RF_THREADS / RF_TEAM;
+constexpr int RF_QUERIES = 256;                     // queries per workgroup (16 per team)
 
-// exact re-evaluation of the candidate groups of light rows (heavy rows are left to the exact
-// kernel and skipped here)
+// Exact re-evaluation of the candidate groups of light rows (heavy rows are left to the exact
+// kernel and skipped here).  A team of 16 lanes takes one query; in each 64-target group a lane
+// evaluates 4 consecutive targets (48 contiguous bytes), then the team reduces the lexicographic
+// (distance, index) minimum.
 __global__ __launch_bounds__(RF_THREADS) void k_refine(const float *__restrict__ Q, int Nq,
                                                        const float *__restrict__ P, int Np,
                                                        const int32_t *__restrict__ rec,
@@ -348,46 +365,77 @@ __global__ __launch_bounds__(RF_THREADS) void k_refine(const float *__restrict__
     if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
     __syncthreads();
     const int t = blockIdx.y;
-    const int i = blockIdx.x * RF_THREADS + threadIdx.x;
-    unsigned ncand = 0, nheavy = 0;
-    if (i < Nq) {
-        const int32_t *rr = rec + ((size_t)t * Nq + i) * REC_INTS;
-        const int n = rr[0];
-        if (n < 0) {
-            nheavy = 1;
+    const int team = threadIdx.x / RF_TEAM, tl = threadIdx.x % RF_TEAM;
+    const float *Pt = P + (size_t)t * Np * 3;
+    unsigned my_cand = 0, my_heavy = 0;
+    for (int qq = 0; qq < RF_QUERIES / RF_TEAMS; ++qq) {
+    const int i = blockIdx.x * RF_QUERIES + qq * RF_TEAMS + team;
+    const int32_t *rr = rec + ((size_t)t * Nq + min(i, Nq - 1)) * REC_INTS;
+    const int n = (i < Nq) ? rr[0] : -2;
+    float qx = 0.f, qy = 0.f, qz = 0.f;
+    if (n >= 0) {
+        const float *q = Q + ((size_t)t * Nq + i) * 3;
+        qx = q[0];
+        qy = q[1];
+        qz = q[2];
+    }
+    float best = __builtin_inff();
+    int bj = 0x7fffffff;
+    for (int e = 0; e < n; ++e) {
+        const int code = rr[2 + e];
+        const int j = (code >> 4) * SC_CHUNK + 64 * (code & 15) + 4 * tl;
+        float c[12];
+        if (j + 3 < Np) {
+            const float4 *p4 = reinterpret_cast<const float4 *>(Pt + 3 * (size_t)j);
+            const float4 u0 = p4[0], u1 = p4[1], u2 = p4[2];
+            c[0] = u0.x; c[1] = u0.y; c[2] = u0.z; c[3] = u0.w;
+            c[4] = u1.x; c[5] = u1.y; c[6] = u1.z; c[7] = u1.w;
+            c[8] = u2.x; c[9] = u2.y; c[10] = u2.z; c[11] = u2.w;
         } else {
-            const float *Pt = P + (size_t)t * Np * 3;
-            const float *q = Q + ((size_t)t * Nq + i) * 3;
-            const float qx = q[0], qy = q[1], qz = q[2];
-            float best = __builtin_inff();
-            int bj = Np;
-            for (int e = 0; e < n; ++e) {
-                const int code = rr[2 + e];
-                const int j0 = (code >> 4) * SC_CHUNK + 64 * (code & 15);
-                const int j1 = min(Np, j0 + 64);
-                for (int j = j0; j < j1; ++j) {
-                    const float d = canon_d2(qx, qy, qz, Pt + 3 * (size_t)j);
-                    if (bj == Np || d < best || (d == best && j < bj)) {
-                        best = d;
-                        bj = j;
-                    }
+#pragma unroll
+            for (int k = 0; k < 12; ++k) c[k] = (j + k / 3 < Np) ? Pt[3 * (size_t)j + k] : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (j + k < Np) {
+                const float d = canon_d2(qx, qy, qz, c + 3 * k);
+                if (d < best || (d == best && j + k < bj)) {
+                    best = d;
+                    bj = j + k;
                 }
             }
-            if (bj == Np) {  // no candidate survived (non-finite data): first index
-                bj = 0;
-                best = canon_d2(qx, qy, qz, Pt);
-            }
-            idx[(size_t)t * Nq + i] = bj;
-            dist[(size_t)t * Nq + i] = best;
-            ncand = (unsigned)n;
         }
     }
+#pragma unroll
+    for (int off = RF_TEAM / 2; off > 0; off >>= 1) {
+        const float ob = __shfl_xor(best, off, RF_TEAM);
+        const int oj = __shfl_xor(bj, off, RF_TEAM);
+        if (ob < best || (ob == best && oj < bj)) {
+            best = ob;
+            bj = oj;
+        }
+    }
+    if (n >= 0 && tl == 0) {
+        if (bj == 0x7fffffff) {  // nothing comparable (non-finite data): first index
+            bj = 0;
+            best = canon_d2(qx, qy, qz, Pt);
+        }
+        idx[(size_t)t * Nq + i] = bj;
+        dist[(size_t)t * Nq + i] = best;
+    }
+    if (tl == 0 && i < Nq) {
+        my_cand += n >= 0 ? (unsigned)n : 0u;
+        my_heavy += n < 0 ? 1u : 0u;
+    }
+    }
     if (stats) {
-        atomicAdd(&cnt[0], ncand);
-        atomicAdd(&cnt[1], nheavy);
+        if (tl == 0) {
+            atomicAdd(&cnt[0], my_cand);
+            atomicAdd(&cnt[1], my_heavy);
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
-            const int live = min(RF_THREADS, Nq - (int)blockIdx.x * RF_THREADS);
+            const int live = min(RF_QUERIES, Nq - (int)blockIdx.x * RF_QUERIES);
             atomicAdd(&stats[0], (unsigned long long)live);
             atomicAdd(&stats[1], (unsigned long long)cnt[0]);
             atomicAdd(&stats[2], (unsigned long long)cnt[1]);
@@ -399,9 +447,12 @@ __global__ __launch_bounds__(RF_THREADS) void k_refine(const float *__restrict__
 
 bool screen_available() { return true; }
 
+static int padded_targets(int Np) { return ((Np + SC_CHUNK - 1) / SC_CHUNK) * SC_CHUNK; }
+
 size_t screen_scratch_bytes(int T, int Nq, int Np) {
     return Arena::need((size_t)T, 4) * 2 + Arena::need((size_t)T * Nq, 4) +
-           Arena::need((size_t)T * Nq * REC_INTS, 4) + nn_exact_list_scratch_bytes(T, Nq, Np);
+           Arena::need((size_t)T * Nq * REC_INTS, 4) + nn_exact_list_scratch_bytes(T, Nq, Np) +
+           Arena::need((size_t)T * padded_targets(Np) * 3, sizeof(bf16x8));
 }
 
 void launch_nn_screened(const float *Q, int Nq, const float *P, int Np, int T, int32_t *idx,
@@ -415,15 +466,19 @@ void launch_nn_screened(const float *Q, int Nq, const float *P, int Np, int T, i
     int32_t *heavy_list = ar.take<int32_t>((size_t)T * Nq);
     int32_t *rec = ar.take<int32_t>((size_t)T * Nq * REC_INTS);
     char *exact_scratch = ar.take<char>(nn_exact_list_scratch_bytes(T, Nq, Np));
+    const int Np_pad = padded_targets(Np);
+    bf16x8 *packed = ar.take<bf16x8>((size_t)T * Np_pad * 3);
     hipLaunchKernelGGL(k_norm_max, dim3(T), dim3(256), 0, s, P, Np, npmax, heavy_cnt);
+    hipLaunchKernelGGL(k_pack_targets, dim3(Np_pad / 256, T), dim3(256), 0, s, P, Np, Np_pad,
+                       packed);
     {
         ProfScope ps(prof, 0, s);
         hipLaunchKernelGGL(k_screen, dim3((Nq + SC_ROWS - 1) / SC_ROWS, T), dim3(SC_THREADS), 0,
-                           s, Q, Nq, P, Np, npmax, rec, heavy_cnt, heavy_list);
+                           s, Q, Nq, packed, Np, Np_pad, npmax, rec, heavy_cnt, heavy_list);
     }
     {
         ProfScope ps(prof, 1, s);
-        hipLaunchKernelGGL(k_refine, dim3((Nq + RF_THREADS - 1) / RF_THREADS, T),
+        hipLaunchKernelGGL(k_refine, dim3((Nq + RF_QUERIES - 1) / RF_QUERIES, T),
                            dim3(RF_THREADS), 0, s, Q, Nq, P, Np, rec, idx, dist, stats);
         launch_nn_exact_list(Q, Nq, P, Np, T, heavy_list, heavy_cnt, idx, dist, exact_scratch, s);
     }
