@@ -36,6 +36,9 @@ def _args():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample (0 disables it)")
     ap.add_argument("--frames", type=int, default=None, help="override the frame count")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving leg (256 Poisson requests, p50/p99 latency)")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one plain device-to-device copy of MIB mebibytes (to scale "
                          "hardware byte counters) and exit")
@@ -123,6 +126,59 @@ def _frame_words(oracle, seed, t, N):
     return oracle.words_from_seed(seed, t + 1, N)[t:t + 1]
 
 
+def run_serving(p, torch, rate_hz=None, n_requests=None, budget_bytes=64 << 30, max_slots=64,
+                precision=1, log=None):
+    """Serving leg: seeded requests of uneven mesh size, point counts and frame counts arrive as a
+    Poisson process; each is submitted to the library's serving loop at its arrival time and its
+    latency is completion minus scheduled arrival.  A second pass submits everything at once to
+    measure capacity."""
+    from paper_2204_03139_amd.serving import Server
+    from workloads import gen
+    reqs, arrivals = gen.serving_requests(n_requests=n_requests, rate_hz=rate_hz)
+    inputs = [gen.request_inputs(r) for r in reqs]
+    pairs = [float(r["T"]) * r["Na"] * r["Nb"] for r in reqs]
+    srv = Server(hbm_budget_bytes=budget_bytes, max_slots=max_slots)
+    # warm the loop (streams, pinned slots, code objects) with one request
+    v, f, o = inputs[0]
+    srv.wait(srv.submit(v, f, o, reqs[0]["Na"], reqs[0]["seed"], precision))
+
+    def drive(times):
+        pending = {}
+        done = {}
+        t0 = time.monotonic()
+        k = 0
+        while k < len(reqs) or pending:
+            now = time.monotonic() - t0
+            while k < len(reqs) and times[k] <= now:
+                v, f, o = inputs[k]
+                pending[srv.submit(v, f, o, reqs[k]["Na"], reqs[k]["seed"], precision)] = k
+                k += 1
+            for tk in list(pending):
+                st = srv.poll(tk)
+                if st != 1:
+                    kk = pending.pop(tk)
+                    status, loss, grad, tm = srv.take(tk, st)
+                    if status != 0:
+                        raise RuntimeError(f"request {kk} failed with status {status}")
+                    done[kk] = tm["done"] - (t0 + times[kk])
+            time.sleep(5e-5)
+        span = max(done[kk] + times[kk] for kk in done)
+        return np.array([done[kk] for kk in sorted(done)]), span
+
+    lat, span = drive(arrivals)
+    _, span_sat = drive(np.zeros(len(reqs)))
+    srv.close()
+    total = sum(pairs)
+    return dict(requests=len(reqs), rate_hz=gen.CONFIGS[5]["rate_hz"] if rate_hz is None else rate_hz,
+                p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                max_ms=float(lat.max() * 1e3), pairs_total=total,
+                pairs_per_s_at_offered_load=total / span, saturation_pairs_per_s=total / span_sat,
+                budget_bytes=budget_bytes, max_slots=max_slots,
+                precision="bf16_refine" if precision == 1 else "fp32",
+                workload="256 requests: grids 10x10..80x80, 512..32768 sampled and observed points "
+                         "(log-uniform, independent), 1..60 frames, Poisson arrivals")
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -147,6 +203,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(2)
+    if a.serving_only:
+        print(json.dumps(dict(metric=METRIC, serving=run_serving(p, torch))), flush=True)
+        return
     w = gen.workload(a.workload, T=a.frames)
     T, Na, Nb = w["T"], w["Na"], w["Nb"]
     pairs = float(T) * Na * Nb
@@ -188,6 +247,8 @@ def main():
                       flops_per_pair=FLOPS_PER_PAIR),
         paths=paths,
     )
+    if not a.no_serving:
+        line["serving"] = run_serving(p, torch)
     if a.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -206,6 +206,11 @@ typedef struct dc_result {
  * with DC_ERR_BUDGET at once.  *ticket identifies it for dc_poll().  Thread-safe. */
 int dc_submit(dc_ctx *ctx, const dc_request *req, dc_result *out, uint64_t *ticket);
 
+/* Device bytes the request would hold while admitted (inputs, intermediates, outputs, scratch),
+ * the amount admission reserves against the budget.  want_grad selects whether the backward runs
+ * (dc_submit runs it when the result's grad_verts is not NULL).  Errors: DC_ERR_INVALID. */
+int dc_request_bytes(const dc_request *req, int want_grad, size_t *bytes);
+
 /* DC_PENDING while queued or running; then the request's final status (DC_OK or an error),
  * after which the ticket is forgotten (a second poll gives DC_ERR_INVALID).  Thread-safe. */
 int dc_poll(dc_ctx *ctx, uint64_t ticket);

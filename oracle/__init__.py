@@ -274,27 +274,36 @@ def full_gradient(verts, faces, observed, face_idx, bary, points, reduction=0, f
 def fd_gradient(verts, faces, observed, face_idx, bary, coords, h=1e-4, reduction=0,
                 frame_w=None):
     """Central differences (L(V+h e_k) - L(V-h e_k)) / 2h in double for the listed
-    (frame, vertex, axis) coordinates, face choice and weights fixed.  Returns (fd, frozen_fd,
-    moved) where moved flags coordinates whose neighbours changed between V-h and V+h, and
-    frozen_fd repeats the difference with the neighbours of V held fixed."""
+    (frame, vertex, axis) coordinates, face choice and weights fixed.  A vertex of frame t only
+    moves frame t's points, so only that frame's term of the loss is differenced.  Returns
+    (fd, frozen_fd, moved): moved flags coordinates whose neighbours changed between V-h and V+h,
+    and frozen_fd repeats the difference with the neighbours at V held fixed."""
     V64 = np.asarray(verts, dtype=np.float64).copy()
     if V64.ndim == 2:
         V64 = V64[None]
-    p0 = points_f64(V64, faces, face_idx, bary)
-    _, ia0, ib0 = loss_f64(p0, observed, reduction, frame_w, return_idx=True)
+    obs = np.asarray(observed, dtype=np.float32)
+    fw = None if frame_w is None else np.asarray(frame_w, np.float32)
     fd = np.zeros(len(coords))
     fdz = np.zeros(len(coords))
     moved = np.zeros(len(coords), bool)
+    base = {}
     for n, (t, v, k) in enumerate(coords):
+        sl = slice(t, t + 1)
+        fwt = None if fw is None else fw[sl]
+        if t not in base:
+            p0 = points_f64(V64[sl], faces, face_idx[sl], bary[sl])
+            _, ia0, ib0 = loss_f64(p0, obs[sl], reduction, fwt, return_idx=True)
+            base[t] = (ia0, ib0)
+        ia0, ib0 = base[t]
         old = V64[t, v, k]
         V64[t, v, k] = old + h
-        pp = points_f64(V64, faces, face_idx, bary)
-        lp, iap, ibp = loss_f64(pp, observed, reduction, frame_w, return_idx=True)
-        lpz = loss_f64(pp, observed, reduction, frame_w, idx_a=ia0, idx_b=ib0)
+        pp = points_f64(V64[sl], faces, face_idx[sl], bary[sl])
+        lp, iap, ibp = loss_f64(pp, obs[sl], reduction, fwt, return_idx=True)
+        lpz = loss_f64(pp, obs[sl], reduction, fwt, idx_a=ia0, idx_b=ib0)
         V64[t, v, k] = old - h
-        pm = points_f64(V64, faces, face_idx, bary)
-        lm, iam, ibm = loss_f64(pm, observed, reduction, frame_w, return_idx=True)
-        lmz = loss_f64(pm, observed, reduction, frame_w, idx_a=ia0, idx_b=ib0)
+        pm = points_f64(V64[sl], faces, face_idx[sl], bary[sl])
+        lm, iam, ibm = loss_f64(pm, obs[sl], reduction, fwt, return_idx=True)
+        lmz = loss_f64(pm, obs[sl], reduction, fwt, idx_a=ia0, idx_b=ib0)
         V64[t, v, k] = old
         fd[n] = (lp - lm) / (2 * h)
         fdz[n] = (lpz - lmz) / (2 * h)

@@ -404,6 +404,18 @@ int dc_submit(dc_ctx *ctx, const dc_request *req, dc_result *out, uint64_t *tick
     return sched_submit(ctx, req, out, ticket);
 }
 
+int dc_request_bytes(const dc_request *req, int want_grad, size_t *bytes) {
+    clear_error();
+    if (!req || !bytes || req->T < 1 || req->V < 1 || req->F < 1 || req->n_sim < 1 ||
+        req->n_obs < 1) {
+        set_error("dc_request_bytes: invalid request");
+        return DC_ERR_INVALID;
+    }
+    *bytes = request_bytes(req->T, req->V, req->F, req->n_sim, req->n_obs, req->precision,
+                           want_grad != 0);
+    return DC_OK;
+}
+
 int dc_poll(dc_ctx *ctx, uint64_t ticket) {
     clear_error();
     if (!ctx) return DC_ERR_INVALID;

@@ -113,7 +113,20 @@ static size_t host_bytes(const Req *r) {
 static int run_request(Scheduler *S, Req *r) {
     dc_ctx *ctx = S->ctx;
     hipStream_t s = S->streams[r->stream];
-    DC_HIP(hipMallocAsync(reinterpret_cast<void **>(&r->dmem), r->bytes, s));
+    {
+        std::lock_guard<std::mutex> g(ctx->budget_mu);
+        if (ctx->fail_next_alloc > 0) {  // test hook: a forced allocation failure
+            --ctx->fail_next_alloc;
+            set_error("device allocation failed (forced)");
+            return DC_ERR_NOMEM;
+        }
+    }
+    if (hipMallocAsync(reinterpret_cast<void **>(&r->dmem), r->bytes, s) != hipSuccess) {
+        (void)hipGetLastError();
+        r->dmem = nullptr;
+        set_error("device allocation of a request failed");
+        return DC_ERR_NOMEM;
+    }
     Arena ar;
     ar.base = r->dmem;
     ar.cap = r->bytes;

@@ -1,0 +1,129 @@
+"""The serving loop (dc_submit / dc_poll): results equal the direct calls bit for bit, a request's
+result is the same alone and in a mix, admission respects the HBM budget, and failures stay with
+the request that caused them."""
+import numpy as np
+import pytest
+
+from workloads import gen
+
+from gpu_helpers import dev, gpu, host, say, torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _request(k, n=None, T=None, Na=None, Nb=None):
+    r = np.random.default_rng(100 + k)
+    n = n or int(r.integers(6, 30))
+    T = T or int(r.integers(1, 5))
+    Na = Na or int(r.integers(200, 3000))
+    Nb = Nb or int(r.integers(200, 3000))
+    verts, faces = gen.trajectory(n, T, 5, extra=k)
+    obs = gen.observed_cloud(n, T, Nb, 5, extra=k)
+    return dict(verts=verts, faces=faces, obs=obs, Na=Na, seed=7000 + k)
+
+
+def _direct(p, q, precision, reduction=0, frame_w=None):
+    """The same pipeline through the direct entry points."""
+    T, V = q["verts"].shape[:2]
+    verts, faces, obs = dev(q["verts"]), dev(q["faces"]), dev(q["obs"])
+    fw = None if frame_w is None else dev(frame_w)
+    pts, fi, ba = p.sample_surface(verts, faces, q["Na"], seed=q["seed"])
+    f = p.chamfer_fwd(pts, obs, precision=precision, reduction=reduction, frame_w=fw)
+    ga, _ = p.chamfer_bwd(torch.ones(T, dtype=torch.float64, device="cuda"), pts, obs,
+                          f["idx_a"], f["idx_b"], reduction=reduction, frame_w=fw)
+    gv = p.sample_surface_bwd(ga, faces, fi, ba, V)
+    torch.cuda.synchronize()
+    return host(f["loss"]), host(gv)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_serving_matches_direct_calls(precision):
+    p = gpu()
+    from paper_2204_03139_amd.serving import Server
+    say(f"[serving] direct parity precision={precision}")
+    srv = Server(hbm_budget_bytes=1 << 30)
+    reqs = [_request(k) for k in range(6)]
+    tickets = [srv.submit(q["verts"], q["faces"], q["obs"], q["Na"], q["seed"], precision)
+               for q in reqs]
+    for q, tk in zip(reqs, tickets):
+        st, loss, grad, times = srv.wait(tk)
+        assert st == 0
+        dl, dg = _direct(p, q, precision)
+        assert np.array_equal(loss.view(np.uint64), dl.view(np.uint64))
+        assert np.array_equal(grad.view(np.uint32), dg.view(np.uint32))
+        assert times["submit"] <= times["admit"] <= times["done"]
+    assert srv.poll(tickets[0]) == -1  # a finished ticket is forgotten
+    srv.close()
+
+
+def test_alone_equals_mixed():
+    """Request 0 run alone, then again while 15 others are in flight in a random order."""
+    p = gpu()
+    from paper_2204_03139_amd.serving import Server
+    say("[serving] alone vs mixed")
+    srv = Server(hbm_budget_bytes=2 << 30, max_slots=8)
+    q0 = _request(0, n=20, T=3, Na=2500, Nb=1800)
+    tk = srv.submit(q0["verts"], q0["faces"], q0["obs"], q0["Na"], q0["seed"])
+    st, loss_alone, grad_alone, _ = srv.wait(tk)
+    assert st == 0
+    others = [_request(k) for k in range(1, 16)]
+    order = np.random.default_rng(9).permutation(16)
+    tickets = {}
+    for k in order:
+        q = q0 if k == 0 else others[k - 1]
+        tickets[k] = srv.submit(q["verts"], q["faces"], q["obs"], q["Na"], q["seed"])
+    results = {k: srv.wait(t) for k, t in tickets.items()}
+    st, loss_mix, grad_mix, _ = results[0]
+    assert st == 0 and all(r[0] == 0 for r in results.values())
+    assert np.array_equal(loss_mix.view(np.uint64), loss_alone.view(np.uint64))
+    assert np.array_equal(grad_mix.view(np.uint32), grad_alone.view(np.uint32))
+    srv.close()
+
+
+def test_budget_rejects_and_queues():
+    p = gpu()
+    from paper_2204_03139_amd.serving import Server
+    say("[serving] budget")
+    q = _request(3, n=30, T=4, Na=3000, Nb=3000)
+    # a budget below one request's footprint: rejected at submit
+    srv = Server(hbm_budget_bytes=64 << 10)
+    with pytest.raises(p.DCError) as e:
+        srv.submit(q["verts"], q["faces"], q["obs"], q["Na"], q["seed"])
+    assert e.value.code == -3
+    srv.close()
+    # a budget that fits one request at a time: everything still completes, one after another
+    probe = Server(hbm_budget_bytes=1 << 30)
+    t = probe.submit(q["verts"], q["faces"], q["obs"], q["Na"], q["seed"])
+    st, loss_ref, _, _ = probe.wait(t)
+    probe.close()
+    need = Server.footprint(q["verts"], q["faces"], q["obs"], q["Na"])
+    srv = Server(hbm_budget_bytes=int(need * 1.5))
+    tickets = [srv.submit(q["verts"], q["faces"], q["obs"], q["Na"], q["seed"]) for _ in range(4)]
+    res = [srv.wait(t) for t in tickets]
+    assert all(r[0] == 0 for r in res)
+    for r in res:
+        assert np.array_equal(r[1], loss_ref)
+    admits = sorted((r[3]["admit"], r[3]["done"]) for r in res)
+    for (a0, d0), (a1, d1) in zip(admits, admits[1:]):
+        assert a1 >= d0 - 1e-3  # the next one waits for memory
+    srv.close()
+
+
+def test_failures_stay_with_their_request():
+    p = gpu()
+    from paper_2204_03139_amd.serving import Server
+    say("[serving] failure isolation")
+    srv = Server(hbm_budget_bytes=1 << 30)
+    good = _request(4)
+    srv.ctx.debug_fail_allocs(1)
+    t_fail = srv.submit(good["verts"], good["faces"], good["obs"], good["Na"], good["seed"])
+    st, _, _, _ = srv.wait(t_fail)
+    assert st == -2
+    bad = dict(good)
+    bad["verts"] = np.zeros_like(good["verts"])  # zero total area in every frame
+    t_bad = srv.submit(bad["verts"], bad["faces"], bad["obs"], bad["Na"], bad["seed"])
+    t_ok = srv.submit(good["verts"], good["faces"], good["obs"], good["Na"], good["seed"])
+    assert srv.wait(t_bad)[0] == -5
+    st, loss, grad, _ = srv.wait(t_ok)
+    assert st == 0 and np.all(np.isfinite(loss))
+    srv.close()
