@@ -136,8 +136,7 @@ int enqueue_sample(dc_ctx *prof, const float *verts, const int32_t *faces, int T
 }
 
 size_t chamfer_fwd_scratch_bytes(int T, int Na, int Nb, int precision) {
-    if (precision == DC_PREC_BF16_REFINE)
-        return std::max(screen_scratch_bytes(T, Na, Nb), screen_scratch_bytes(T, Nb, Na));
+    if (precision == DC_PREC_BF16_REFINE) return screen_scratch_bytes(T, Na, Nb);
     return std::max(nn_exact_scratch_bytes(T, Na, Nb), nn_exact_scratch_bytes(T, Nb, Na));
 }
 
@@ -146,8 +145,8 @@ int enqueue_chamfer_fwd(dc_ctx *prof, const float *a, const float *b, int T, int
                         int32_t *idx_a, float *dist_b, int32_t *idx_b, double *loss,
                         char *scratch, unsigned long long *stats, hipStream_t s) {
     if (precision == DC_PREC_BF16_REFINE) {
-        launch_nn_screened(a, Na, b, Nb, T, idx_a, dist_a, scratch, stats, prof, s);
-        launch_nn_screened(b, Nb, a, Na, T, idx_b, dist_b, scratch, stats, prof, s);
+        launch_chamfer_screened(a, Na, b, Nb, T, idx_a, dist_a, idx_b, dist_b, scratch, stats,
+                                prof, s);
     } else {
         {
             ProfScope ps(prof, 0, s);

@@ -113,12 +113,14 @@ void launch_nn_exact_list(const float *Q, int Nq, const float *P, int Np, int T,
                           const int32_t *qlist, const int32_t *qcount, int32_t *idx, float *dist,
                           char *scratch, hipStream_t st);
 
-// bf16 matrix-core screen + certified exact refine (same outputs as launch_nn_exact)
+// bf16 matrix-core screen + certified exact refine, both directions in one pass (the same
+// indices and distances as two exact fp32 searches)
 bool screen_available();
-size_t screen_scratch_bytes(int T, int Nq, int Np);
-void launch_nn_screened(const float *Q, int Nq, const float *P, int Np, int T, int32_t *idx,
-                        float *dist, char *scratch, unsigned long long *stats, dc_ctx *prof,
-                        hipStream_t s);
+size_t screen_scratch_bytes(int T, int Na, int Nb);
+void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int T,
+                             int32_t *idx_a, float *dist_a, int32_t *idx_b, float *dist_b,
+                             char *scratch, unsigned long long *stats, dc_ctx *prof,
+                             hipStream_t s);
 
 // per-frame loss from the float distances, accumulated in double
 void launch_loss(const float *dist_a, const float *dist_b, int T, int Na, int Nb, int reduction,

@@ -1,28 +1,33 @@
-// bf16 matrix-core screen + certified exact refine for the all-pairs nearest neighbour
-// (Sec. III-A, Eq. 1/2): the same indices as the exact single-precision search, found faster.
+// bf16 matrix-core screen + certified exact refine for the all-pairs nearest neighbours of
+// Sec. III-A (Eq. 1/2), in both directions at once: the same indices as the exact single-precision
+// search, found faster.
 //
-// Screen (k_screen): the squared distance is expanded as s_ij = |q_i|^2 + |p_j|^2 - 2 q_i.p_j and
+// Screen (k_screen): the squared distance is expanded as s_ij = |a_i|^2 + |b_j|^2 - 2 a_i.b_j and
 // evaluated as one K=32 dot product per pair on v_mfma_f32_16x16x32_bf16 with fp32 accumulation.
-// Each float coordinate is split exactly into three bf16 parts (x = h + m + l), and the six
-// products hH, hM, mH, hL, lH, mM per coordinate (18 K-slots) plus the two norms, each split in
-// three (6 K-slots), fill 24 of the 32 K-slots; the matrix unit does the whole distance, the vector
-// unit only keeps minimums (one v_min3 per two pairs).  Query rows stay in registers (64 per wave,
-// four 16-row tiles); targets stream through LDS in groups of 256, their bf16 operand built while
-// staging.  Targets are laid out so that, inside each chunk of 1024, result column c of the 64
-// tiles holds the 64 consecutive targets [64c, 64c+64): a (column, chunk) "slot group" is one
-// contiguous run.  For every (lane, row) the kernel keeps the minimum of each of its slot groups,
-// and the two best groups and the third-best value.
-// Certificate: with a rigorous bound e_ij <= C (|q_i|^2 + |p_j|^2) on |s_ij - d_ij| (bf16 splits
-// exact, products exact, at most 24 roundings of the fp32 accumulator at 2^-23), every index whose
-// canonical float distance can equal the minimum has s_ij <= m_i + Delta_i, where m_i is the
-// row's screened minimum and Delta_i bounds the error at the screened winner and at the canonical
-// winner (both lie within sqrt(m_i + e) of q_i, which bounds their norms).  Slot groups whose
-// minimum passes that test are candidates.  A row is "heavy" (searched exhaustively by the exact
-// kernel) if a slot has three passing groups, if it has more than MAXC candidates, or if its
-// minimum is not finite; heavy rows are appended to a per-frame list.
-// Refine (k_refine): one lane per light query evaluates the canonical distance
-// fma(dz,dz,fma(dy,dy,dx*dx)) over its candidate groups and keeps the lexicographic
-// (distance, index) minimum, which is exactly the argmin of the exhaustive search with the
+// Each float coordinate is split exactly into three bf16 parts (x = h + m + l); the products
+// hH, hM, mH, hL, lH, mM per coordinate (18 K-slots) plus the two norms in three parts each (6
+// K-slots) fill 24 of the 32 K-slots, so the matrix unit produces the whole screened distance.
+// Rows a stay in registers (64 per wave, four 16-row tiles); the b operands (packed once per
+// frame) stream through a double-buffered LDS stage.  Every 16x16 result tile feeds both
+// directions with v_min3 only:
+//   rows (a -> b): each (lane, row) folds its column of every tile into a running minimum;
+//     targets are laid out so that, inside each chunk of SC_CHUNK, result column c holds a
+//     contiguous run of SC_RUN targets (a "slot group"); the kernel keeps the two best slot
+//     groups and the third-best value per (lane, row);
+//   columns (b -> a): each lane folds its 16 rows of a tile into one value per (row group, b_j);
+//     after each stage the workgroup reduces its 16 row groups per b_j in LDS and writes the
+//     workgroup's minimum, the winning row group and an "ambiguous" flag (a second group within
+//     the certificate margin) to a per-workgroup partial array.
+// Certificate: every bf16 split is exact and every bf16 product is exact in fp32, so
+// |s_ij - d_ij| <= C (|a_i|^2 + |b_j|^2) (at most 24 fp32 roundings at 2^-23 on a sum of absolute
+// products <= 2.02 (|a|^2+|b|^2), plus dropped split products and float norms).  The canonical
+// float distance fma(dz,dz,fma(dy,dy,dx*dx)) is within 5u of the exact one (u = 2^-24).  Hence
+// any index whose canonical distance can equal the minimum has s <= m + Delta(m), m the screened
+// minimum of the query, Delta bounding the error at the screened and the canonical winner (both
+// within sqrt(m + e) of the query, which bounds their norms).  Candidates pass that test; a query
+// with too many candidates or a non-finite minimum is "heavy" and is searched exhaustively.
+// Refine: teams of 16 lanes evaluate the canonical distance over the candidates and keep the
+// lexicographic (distance, index) minimum: exactly the argmin of the exhaustive search with the
 // smallest-index rule.
 #include "dc_internal.h"
 
@@ -32,13 +37,28 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// tiling (overridable at build time for tuning sweeps)
+#ifndef DC_SCREEN_ATILES
+#define DC_SCREEN_ATILES 4
+#endif
+#ifndef DC_SCREEN_STAGE
+#define DC_SCREEN_STAGE 256
+#endif
+#ifndef DC_SCREEN_CHUNK
+#define DC_SCREEN_CHUNK 1024
+#endif
 constexpr int SC_WAVES = 4;
 constexpr int SC_THREADS = 64 * SC_WAVES;
-constexpr int SC_ATILES = 4;                            // 16-row tiles per wave
-constexpr int SC_ROWS = SC_WAVES * SC_ATILES * 16;       // 256 query rows per workgroup
-constexpr int SC_STAGE = 256;                            // targets staged in LDS per step
-constexpr int SC_CHUNK = 1024;                           // targets per tracking chunk
+constexpr int SC_ATILES = DC_SCREEN_ATILES;              // 16-row tiles per wave
+constexpr int SC_ROWS = SC_WAVES * SC_ATILES * 16;       // query rows per workgroup
+constexpr int SC_STAGE = DC_SCREEN_STAGE;                // targets staged in LDS per step
+constexpr int SC_CHUNK = DC_SCREEN_CHUNK;                // targets per tracking chunk
+constexpr int SC_TPS = SC_STAGE / 16;                    // tiles per stage
+constexpr int SC_RUN = SC_CHUNK / 16;                    // contiguous targets of a slot group
+constexpr int SC_PER_THREAD = SC_STAGE / SC_THREADS;     // targets staged per thread
 constexpr int SC_ROWPAD = 17;                            // LDS entries per staged tile
+static_assert(SC_STAGE % SC_THREADS == 0 && SC_CHUNK % SC_STAGE == 0, "tiling");
+static_assert(SC_RUN % 64 == 0, "slot groups are whole 64-target refine steps");
 constexpr int MAXC = 14;                                 // candidate slot groups per row
 constexpr int REC_INTS = 2 + MAXC;                       // n, spare, entries
 
@@ -170,18 +190,38 @@ __global__ __launch_bounds__(256) void k_norm_max(const float *__restrict__ P, i
     if (threadIdx.x == 0) out[t] = red[0];
 }
 
-__global__ __launch_bounds__(SC_THREADS) void k_screen(const float *__restrict__ Q, int Nq,
-                                                       const bf16x8 *__restrict__ packed,
-                                                       int Np, int Np_pad,
-                                                       const float *__restrict__ npmax,
-                                                       int32_t *__restrict__ rec,
-                                                       int32_t *__restrict__ heavy_cnt,
-                                                       int32_t *__restrict__ heavy_list) {
+// Certificate threshold: every index whose canonical float distance can equal the minimum has a
+// screened value <= threshold(m, nq, nmax), where m is the query's screened minimum, nq its squared
+// norm and nmax the largest squared norm among the points it is compared with.  Increasing in m.
+__device__ __forceinline__ float threshold(float m, float nq, float nmax) {
+    const float up = 1.0001f;
+    const float qn = __builtin_sqrtf(nq) * up;
+    const float mp = fmaxf(m, 0.f);
+    const float e0 = (SCREEN_C * (nq + nmax) + SCREEN_TAU) * up;
+    const float r0 = qn + __builtin_sqrtf(mp + e0) * up;
+    const float e1 = (SCREEN_C * (nq + r0 * r0) + SCREEN_TAU) * up;  // at the screened winner
+    const float d1 = (mp + e1) * (1.0f + CANON_U13) * up;
+    const float r1 = qn + __builtin_sqrtf(d1) * up;
+    const float e2 = (SCREEN_C * (nq + r1 * r1) + SCREEN_TAU) * up;  // at the canonical winner
+    const float th = m + e1 + e2 + CANON_U13 * (mp + e1);
+    return th + fabsf(th) * 1e-4f + SCREEN_TAU;
+}
+
+constexpr int SC_GROUPS = SC_WAVES * 4;  // row groups per workgroup: (wave, lane group g)
+constexpr int CP_PAD = SC_TPS + 1;       // column partial buffer: [group][column][tile], padded
+
+template <bool COLS>
+__global__ __launch_bounds__(SC_THREADS) void k_screen(
+    const float *__restrict__ Q, int Nq, const bf16x8 *__restrict__ packed,
+    const float *__restrict__ P, int Np, int Np_pad, const float *__restrict__ npmax,
+    const float *__restrict__ nqmax, int32_t *__restrict__ rec, int32_t *__restrict__ heavy_cnt,
+    int32_t *__restrict__ heavy_list, float *__restrict__ cpart, uint8_t *__restrict__ ctag) {
     // [buffer][K-chunk][entry] -> 16 bytes.  Entry 17*bt + c holds tile bt, result column c: the
     // operand reads (16 columns of one tile) are consecutive and the staging stores (8 tiles of
     // one column, 272 bytes apart) fall in distinct banks; the read address is a per-lane base
     // plus a compile-time offset.  K-chunk 3 is all zeros on the query side and is not stored.
-    __shared__ bf16x8 stage[2][3][SC_ROWPAD * 16];
+    __shared__ bf16x8 stage[2][3][SC_ROWPAD * SC_TPS];
+    __shared__ float colbuf[COLS ? SC_GROUPS : 1][16][CP_PAD];
     const int t = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -190,6 +230,7 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(const float *__restrict__
     const float *Qt = Q + (size_t)t * Nq * 3;
     const bf16x8 *Bt = packed + (size_t)t * Np_pad * 3;
     const int row0 = blockIdx.x * SC_ROWS + wave * (SC_ATILES * 16);
+    const int nwg = gridDim.x;
 
     // query operands, held for the whole sweep
     bf16x8 A[SC_ATILES];
@@ -200,13 +241,15 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(const float *__restrict__
         if (r < Nq)
             query_vector(Qt[3 * (size_t)r], Qt[3 * (size_t)r + 1], Qt[3 * (size_t)r + 2], v);
         else
-            query_vector(0.f, 0.f, 0.f, v);
+            query_vector(0.f, 0.f, 1e15f, v);  // padding row: far from everything
         A[a] = pick8(v, g);
     }
 
+    // per (lane, row): running minimum of the current chunk, the three best chunk minima, and
+    // the chunks of the best two packed as (best << 16) | second (0xFFFF = none)
     const float inf = __builtin_inff();
     float m[SC_ATILES][4], b1[SC_ATILES][4], b2[SC_ATILES][4], b3[SC_ATILES][4];
-    int c1[SC_ATILES][4], c2[SC_ATILES][4];
+    unsigned cc[SC_ATILES][4];
 #pragma unroll
     for (int a = 0; a < SC_ATILES; ++a)
 #pragma unroll
@@ -215,58 +258,81 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(const float *__restrict__
             b1[a][r] = inf;
             b2[a][r] = inf;
             b3[a][r] = inf;
-            c1[a][r] = -1;
-            c2[a][r] = -1;
+            cc[a][r] = 0xFFFFFFFFu;
         }
     const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
     const int nstage = Np_pad / SC_STAGE;
-    // staging position of this thread: tile-local position (btl, c) of a stage holds target
-    // 64c + 16*(stage in chunk) + btl of the chunk, so result column c of a chunk is the
-    // contiguous run [64c, 64c+64)
-    const int sc = threadIdx.x >> 4, sbtl = threadIdx.x & 15;
-    const int spos = sbtl * SC_ROWPAD + sc;
-    auto target_of = [&](int st) {
-        return (st / (SC_CHUNK / SC_STAGE)) * SC_CHUNK + 64 * sc + 16 * (st % (SC_CHUNK / SC_STAGE)) +
-               sbtl;
+    constexpr int SPC = SC_CHUNK / SC_STAGE;  // stages per chunk
+    // staging: entry (btl, c) of a stage holds target SC_RUN*c + SC_TPS*(stage in chunk) + btl of
+    // its chunk, so result column c of a chunk is the contiguous run [SC_RUN*c, SC_RUN*(c+1))
+    int spos[SC_PER_THREAD], soff[SC_PER_THREAD];
+#pragma unroll
+    for (int u = 0; u < SC_PER_THREAD; ++u) {
+        const int e = threadIdx.x + u * SC_THREADS;
+        const int c = e / SC_TPS, btl = e % SC_TPS;
+        spos[u] = btl * SC_ROWPAD + c;
+        soff[u] = SC_RUN * c + btl;
+    }
+    auto target_of = [&](int st, int u) {
+        return (st / SPC) * SC_CHUNK + SC_TPS * (st % SPC) + soff[u];
     };
-    // register prefetch of the next stage's operands, double-buffered LDS: one barrier per stage
-    bf16x8 q0, q1, q2;
-    {
-        const bf16x8 *src = Bt + (size_t)target_of(0) * 3;
-        q0 = src[0];
-        q1 = src[1];
-        q2 = src[2];
+    const float nqm = COLS ? nqmax[t] : 0.f;
+    // register prefetch of the next stage's operands, double-buffered LDS
+    bf16x8 q[SC_PER_THREAD][3];
+#pragma unroll
+    for (int u = 0; u < SC_PER_THREAD; ++u) {
+        const bf16x8 *src = Bt + (size_t)target_of(0, u) * 3;
+        q[u][0] = src[0];
+        q[u][1] = src[1];
+        q[u][2] = src[2];
     }
     const int gk = (g == 3) ? 0 : g;
     for (int st = 0; st < nstage; ++st) {
         const int buf = st & 1;
-        stage[buf][0][spos] = q0;
-        stage[buf][1][spos] = q1;
-        stage[buf][2][spos] = q2;
+#pragma unroll
+        for (int u = 0; u < SC_PER_THREAD; ++u) {
+            stage[buf][0][spos[u]] = q[u][0];
+            stage[buf][1][spos[u]] = q[u][1];
+            stage[buf][2][spos[u]] = q[u][2];
+        }
         if (st + 1 < nstage) {
-            const bf16x8 *src = Bt + (size_t)target_of(st + 1) * 3;
-            q0 = src[0];
-            q1 = src[1];
-            q2 = src[2];
+#pragma unroll
+            for (int u = 0; u < SC_PER_THREAD; ++u) {
+                const bf16x8 *src = Bt + (size_t)target_of(st + 1, u) * 3;
+                q[u][0] = src[0];
+                q[u][1] = src[1];
+                q[u][2] = src[2];
+            }
         }
         __syncthreads();
         // lanes of K-group 3 hold an all-zero query operand, so any finite staged operand gives
         // them zero products: they read K-chunk 0 instead of a stored zero chunk
         const bf16x8 *sb = &stage[buf][gk][col];
-#pragma unroll 2
-        for (int bt = 0; bt < SC_STAGE / 16; bt += 2) {
+#pragma unroll
+        for (int bt = 0; bt < SC_TPS; bt += 2) {
             const bf16x8 B0 = sb[bt * SC_ROWPAD];
             const bf16x8 B1 = sb[(bt + 1) * SC_ROWPAD];
+            float cm0 = inf, cm1 = inf;
 #pragma unroll
             for (int a = 0; a < SC_ATILES; ++a) {
                 const floatx4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B0, zero, 0, 0, 0);
                 const floatx4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B1, zero, 0, 0, 0);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) m[a][r] = fminf(fminf(m[a][r], d0[r]), d1[r]);
+                if (COLS) {
+                    cm0 = fminf(fminf(cm0, d0[0]), d0[1]);
+                    cm0 = fminf(fminf(cm0, d0[2]), d0[3]);
+                    cm1 = fminf(fminf(cm1, d1[0]), d1[1]);
+                    cm1 = fminf(fminf(cm1, d1[2]), d1[3]);
+                }
+            }
+            if (COLS) {
+                colbuf[COLS ? wave * 4 + g : 0][col][bt] = cm0;
+                colbuf[COLS ? wave * 4 + g : 0][col][bt + 1] = cm1;
             }
         }
-        if ((st + 1) % (SC_CHUNK / SC_STAGE) == 0) {  // end of a tracking chunk
-            const int k = st / (SC_CHUNK / SC_STAGE);
+        if ((st + 1) % SPC == 0) {  // end of a tracking chunk
+            const unsigned k = (unsigned)(st / SPC);
 #pragma unroll
             for (int a = 0; a < SC_ATILES; ++a)
 #pragma unroll
@@ -277,14 +343,47 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(const float *__restrict__
                     b3[a][r] = __builtin_amdgcn_fmed3f(x, b2[a][r], b3[a][r]);
                     b2[a][r] = __builtin_amdgcn_fmed3f(x, b1[a][r], b2[a][r]);
                     b1[a][r] = fminf(x, b1[a][r]);
-                    c2[a][r] = t1 ? c1[a][r] : (t2 ? k : c2[a][r]);
-                    c1[a][r] = t1 ? k : c1[a][r];
+                    const unsigned c1 = cc[a][r] >> 16;
+                    const unsigned up1 = (k << 16) | c1;       // x becomes best, old best second
+                    const unsigned up2 = (c1 << 16) | k;       // x becomes second
+                    cc[a][r] = t1 ? up1 : (t2 ? up2 : cc[a][r]);
                     m[a][r] = inf;
                 }
         }
+        if (COLS) {
+            // reduce the workgroup's row groups per target of this stage; the next stage's
+            // barrier orders these reads before the buffer is written again
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < SC_PER_THREAD; ++u) {
+                const int e = threadIdx.x + u * SC_THREADS;
+                const int c = e / SC_TPS, btl = e % SC_TPS;
+                const int j = target_of(st, u);
+                float best = inf, second = inf;
+                int bg = 0;
+#pragma unroll
+                for (int k = 0; k < SC_GROUPS; ++k) {
+                    const float v = colbuf[COLS ? k : 0][c][btl];
+                    second = fminf(second, fmaxf(v, best));
+                    bg = v < best ? k : bg;
+                    best = fminf(best, v);
+                }
+                if (j < Np) {
+                    const float *pj = P + ((size_t)t * Np + j) * 3;
+                    const float np = norm2(pj[0], pj[1], pj[2]);
+                    // another row group within the margin of this group's best: the merge must
+                    // rescan every row of the workgroup for this target
+                    const float th = threshold(best, np, nqm);
+                    const bool amb = !(second > th + fabsf(th) * 1e-6f);
+                    const size_t o = ((size_t)t * nwg + blockIdx.x) * Np_pad + j;
+                    cpart[o] = best;
+                    ctag[o] = (uint8_t)(bg | (amb ? 0x80 : 0));
+                }
+            }
+        }
     }
 
-    // certificate and candidate records; the 16 lanes of a group share one row per (a, r)
+    // row certificate and candidate records; the 16 lanes of a group share one row per (a, r)
     const float npm = npmax[t];
     const unsigned long long gmask = 0xFFFFull << (16 * g);
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -299,22 +398,12 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(const float *__restrict__
             float nq = 0.f;
             if (row < Nq)
                 nq = norm2(Qt[3 * (size_t)row], Qt[3 * (size_t)row + 1], Qt[3 * (size_t)row + 2]);
-            // Delta: error bound at the screened winner (E1) and at the canonical winner (E2);
-            // each winner lies within sqrt(distance) of q, which bounds its squared norm
-            const float up = 1.0001f;
-            const float qn = __builtin_sqrtf(nq) * up;
-            const float mp = fmaxf(mi, 0.f);
-            const float e0 = (SCREEN_C * (nq + npm) + SCREEN_TAU) * up;
-            const float r0 = qn + __builtin_sqrtf(mp + e0) * up;
-            const float e1 = (SCREEN_C * (nq + r0 * r0) + SCREEN_TAU) * up;
-            const float d1 = (mp + e1) * (1.0f + CANON_U13) * up;
-            const float r1 = qn + __builtin_sqrtf(d1) * up;
-            const float e2 = (SCREEN_C * (nq + r1 * r1) + SCREEN_TAU) * up;
-            const float theta = (mi + e1 + e2 + CANON_U13 * (mp + e1)) * up + SCREEN_TAU;
+            const float theta = threshold(mi, nq, npm);
             const bool finite = __builtin_isfinite(mi) && __builtin_isfinite(theta) &&
                                 __builtin_isfinite(npm);
-            const bool k1 = finite && c1[a][r] >= 0 && b1[a][r] <= theta;
-            const bool k2 = finite && c2[a][r] >= 0 && b2[a][r] <= theta;
+            const int c1 = (int)(cc[a][r] >> 16), c2 = (int)(cc[a][r] & 0xFFFFu);
+            const bool k1 = finite && c1 != 0xFFFF && b1[a][r] <= theta;
+            const bool k2 = finite && c2 != 0xFFFF && b2[a][r] <= theta;
             const bool over = finite && b3[a][r] <= theta;
             const unsigned long long m1 = __ballot(k1) & gmask;
             const unsigned long long m2 = __ballot(k2) & gmask;
@@ -332,11 +421,73 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(const float *__restrict__
                 }
                 if (!heavy) {
                     const int off = __popcll(m1 & below) + __popcll(m2 & below);
-                    if (k1) rr[2 + off] = (c1[a][r] << 4) | col;
-                    if (k2) rr[2 + off + (k1 ? 1 : 0)] = (c2[a][r] << 4) | col;
+                    if (k1) rr[2 + off] = (c1 << 4) | col;
+                    if (k2) rr[2 + off + (k1 ? 1 : 0)] = (c2 << 4) | col;
                 }
             }
         }
+}
+
+// Column merge: per target b_j, the CMAXC workgroups with the smallest partial minima (kept sorted
+// by insertion, which is rare after the first few workgroups) and the next value; candidates are
+// the workgroups passing the certificate.  Record per target: n (or -1 = heavy) and up to CMAXC
+// entries (workgroup << 8 | tag).
+constexpr int CMAXC = 6;
+constexpr int CREC_INTS = 1 + CMAXC + 1;
+
+__global__ __launch_bounds__(256) void k_colmerge(const float *__restrict__ P, int Np, int Np_pad,
+                                                  int nwg, const float *__restrict__ cpart,
+                                                  const uint8_t *__restrict__ ctag,
+                                                  const float *__restrict__ nqmax,
+                                                  int32_t *__restrict__ crec,
+                                                  int32_t *__restrict__ heavy_cnt,
+                                                  int32_t *__restrict__ heavy_list) {
+    const int t = blockIdx.y;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= Np) return;
+    const float inf = __builtin_inff();
+    float bv[CMAXC + 1];
+    int bw[CMAXC + 1];
+#pragma unroll
+    for (int k = 0; k <= CMAXC; ++k) {
+        bv[k] = inf;
+        bw[k] = -1;
+    }
+    for (int w = 0; w < nwg; ++w) {
+        float v = cpart[((size_t)t * nwg + w) * Np_pad + j];
+        if (v < bv[CMAXC]) {
+            int ww = w;
+#pragma unroll
+            for (int k = 0; k <= CMAXC; ++k) {
+                const bool lt = v < bv[k];
+                const float tv = bv[k];
+                const int tw = bw[k];
+                bv[k] = lt ? v : tv;
+                bw[k] = lt ? ww : tw;
+                v = lt ? tv : v;
+                ww = lt ? tw : ww;
+            }
+        }
+    }
+    const float *pj = P + ((size_t)t * Np + j) * 3;
+    const float np = norm2(pj[0], pj[1], pj[2]);
+    const float nqm = nqmax[t];
+    const float theta = threshold(bv[0], np, nqm);
+    const bool finite = __builtin_isfinite(bv[0]) && __builtin_isfinite(theta) &&
+                        __builtin_isfinite(nqm) && bw[0] >= 0;
+    int32_t *rr = crec + ((size_t)t * Np + j) * CREC_INTS;
+    if (!finite || bv[CMAXC] <= theta) {
+        rr[0] = -1;
+        const int pos = atomicAdd(&heavy_cnt[t], 1);
+        heavy_list[(size_t)t * Np + pos] = j;
+        return;
+    }
+    int n = 0;
+#pragma unroll
+    for (int k = 0; k < CMAXC; ++k)
+        if (bw[k] >= 0 && bv[k] <= theta)
+            rr[1 + n++] = (bw[k] << 8) | ctag[((size_t)t * nwg + bw[k]) * Np_pad + j];
+    rr[0] = n;
 }
 
 __device__ __forceinline__ float canon_d2(float qx, float qy, float qz, const float *p) {
@@ -351,10 +502,40 @@ constexpr int RF_TEAM = 16;                         // lanes per query
 constexpr int RF_TEAMS = RF_THREADS / RF_TEAM;
 constexpr int RF_QUERIES = 256;                     // queries per workgroup (16 per team)
 
-// Exact re-evaluation of the candidate groups of light rows (heavy rows are left to the exact
-// kernel and skipped here).  A team of 16 lanes takes one query; in each 64-target group a lane
-// evaluates 4 consecutive targets (48 contiguous bytes), then the team reduces the lexicographic
-// (distance, index) minimum.
+__device__ __forceinline__ void lex_min(float &best, int &bj, float d, int j) {
+    if (d < best || (d == best && j < bj)) {
+        best = d;
+        bj = j;
+    }
+}
+
+__device__ __forceinline__ void team_reduce(float &best, int &bj) {
+#pragma unroll
+    for (int off = RF_TEAM / 2; off > 0; off >>= 1) {
+        const float ob = __shfl_xor(best, off, RF_TEAM);
+        const int oj = __shfl_xor(bj, off, RF_TEAM);
+        lex_min(best, bj, ob, oj);
+    }
+}
+
+__device__ __forceinline__ void flush_stats(unsigned *cnt, unsigned long long *stats, int live,
+                                            unsigned my_cand, unsigned my_heavy, int tl) {
+    if (!stats) return;
+    if (tl == 0) {
+        atomicAdd(&cnt[0], my_cand);
+        atomicAdd(&cnt[1], my_heavy);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&stats[0], (unsigned long long)live);
+        atomicAdd(&stats[1], (unsigned long long)cnt[0]);
+        atomicAdd(&stats[2], (unsigned long long)cnt[1]);
+    }
+}
+
+// Row refine (a -> b): candidate slot groups of light rows; heavy rows are left to the exact
+// kernel.  A team of 16 lanes takes one query; each 64-target step gives every lane 4 consecutive
+// targets (48 contiguous bytes).
 __global__ __launch_bounds__(RF_THREADS) void k_refine(const float *__restrict__ Q, int Nq,
                                                        const float *__restrict__ P, int Np,
                                                        const int32_t *__restrict__ rec,
@@ -369,78 +550,121 @@ __global__ __launch_bounds__(RF_THREADS) void k_refine(const float *__restrict__
     const float *Pt = P + (size_t)t * Np * 3;
     unsigned my_cand = 0, my_heavy = 0;
     for (int qq = 0; qq < RF_QUERIES / RF_TEAMS; ++qq) {
-    const int i = blockIdx.x * RF_QUERIES + qq * RF_TEAMS + team;
-    const int32_t *rr = rec + ((size_t)t * Nq + min(i, Nq - 1)) * REC_INTS;
-    const int n = (i < Nq) ? rr[0] : -2;
-    float qx = 0.f, qy = 0.f, qz = 0.f;
-    if (n >= 0) {
-        const float *q = Q + ((size_t)t * Nq + i) * 3;
-        qx = q[0];
-        qy = q[1];
-        qz = q[2];
-    }
-    float best = __builtin_inff();
-    int bj = 0x7fffffff;
-    for (int e = 0; e < n; ++e) {
-        const int code = rr[2 + e];
-        const int j = (code >> 4) * SC_CHUNK + 64 * (code & 15) + 4 * tl;
-        float c[12];
-        if (j + 3 < Np) {
-            const float4 *p4 = reinterpret_cast<const float4 *>(Pt + 3 * (size_t)j);
-            const float4 u0 = p4[0], u1 = p4[1], u2 = p4[2];
-            c[0] = u0.x; c[1] = u0.y; c[2] = u0.z; c[3] = u0.w;
-            c[4] = u1.x; c[5] = u1.y; c[6] = u1.z; c[7] = u1.w;
-            c[8] = u2.x; c[9] = u2.y; c[10] = u2.z; c[11] = u2.w;
-        } else {
-#pragma unroll
-            for (int k = 0; k < 12; ++k) c[k] = (j + k / 3 < Np) ? Pt[3 * (size_t)j + k] : 0.f;
+        const int i = blockIdx.x * RF_QUERIES + qq * RF_TEAMS + team;
+        const int32_t *rr = rec + ((size_t)t * Nq + min(i, Nq - 1)) * REC_INTS;
+        const int n = (i < Nq) ? rr[0] : -2;
+        float qx = 0.f, qy = 0.f, qz = 0.f;
+        if (n >= 0) {
+            const float *q = Q + ((size_t)t * Nq + i) * 3;
+            qx = q[0];
+            qy = q[1];
+            qz = q[2];
         }
+        float best = __builtin_inff();
+        int bj = 0x7fffffff;
+        for (int e = 0; e < n * (SC_RUN / 64); ++e) {
+            const int code = rr[2 + e / (SC_RUN / 64)];
+            const int j = (code >> 4) * SC_CHUNK + SC_RUN * (code & 15) + 64 * (e % (SC_RUN / 64)) +
+                          4 * tl;
+            float c[12];
+            if (j + 3 < Np) {
+                const float4 *p4 = reinterpret_cast<const float4 *>(Pt + 3 * (size_t)j);
+                const float4 u0 = p4[0], u1 = p4[1], u2 = p4[2];
+                c[0] = u0.x; c[1] = u0.y; c[2] = u0.z; c[3] = u0.w;
+                c[4] = u1.x; c[5] = u1.y; c[6] = u1.z; c[7] = u1.w;
+                c[8] = u2.x; c[9] = u2.y; c[10] = u2.z; c[11] = u2.w;
+            } else {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (j + k < Np) {
-                const float d = canon_d2(qx, qy, qz, c + 3 * k);
-                if (d < best || (d == best && j + k < bj)) {
-                    best = d;
-                    bj = j + k;
+                for (int k = 0; k < 12; ++k) c[k] = (j + k / 3 < Np) ? Pt[3 * (size_t)j + k] : 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (j + k < Np) lex_min(best, bj, canon_d2(qx, qy, qz, c + 3 * k), j + k);
+        }
+        team_reduce(best, bj);
+        if (n >= 0 && tl == 0) {
+            if (bj == 0x7fffffff) {  // nothing comparable (non-finite data): first index
+                bj = 0;
+                best = canon_d2(qx, qy, qz, Pt);
+            }
+            idx[(size_t)t * Nq + i] = bj;
+            dist[(size_t)t * Nq + i] = best;
+        }
+        if (tl == 0 && i < Nq) {
+            my_cand += n >= 0 ? (unsigned)n : 0u;
+            my_heavy += n < 0 ? 1u : 0u;
+        }
+    }
+    flush_stats(cnt, stats, min(RF_QUERIES, Nq - (int)blockIdx.x * RF_QUERIES), my_cand,
+                my_heavy, tl);
+}
+
+// Column refine (b -> a): each candidate workgroup contributes its winning row group (16 rows:
+// one per lane) or, when flagged ambiguous, all of its rows.
+__global__ __launch_bounds__(RF_THREADS) void k_colrefine(const float *__restrict__ A, int Na,
+                                                          const float *__restrict__ B, int Nb,
+                                                          const int32_t *__restrict__ crec,
+                                                          int32_t *__restrict__ idx,
+                                                          float *__restrict__ dist,
+                                                          unsigned long long *__restrict__ stats) {
+    __shared__ unsigned cnt[2];
+    if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int t = blockIdx.y;
+    const int team = threadIdx.x / RF_TEAM, tl = threadIdx.x % RF_TEAM;
+    const float *At = A + (size_t)t * Na * 3;
+    unsigned my_cand = 0, my_heavy = 0;
+    for (int qq = 0; qq < RF_QUERIES / RF_TEAMS; ++qq) {
+        const int j = blockIdx.x * RF_QUERIES + qq * RF_TEAMS + team;
+        const int32_t *rr = crec + ((size_t)t * Nb + min(j, Nb - 1)) * CREC_INTS;
+        const int n = (j < Nb) ? rr[0] : -2;
+        float qx = 0.f, qy = 0.f, qz = 0.f;
+        if (n >= 0) {
+            const float *q = B + ((size_t)t * Nb + j) * 3;
+            qx = q[0];
+            qy = q[1];
+            qz = q[2];
+        }
+        float best = __builtin_inff();
+        int bi = 0x7fffffff;
+        for (int e = 0; e < n; ++e) {
+            const int code = rr[1 + e];
+            const int wg = code >> 8, grp = code & 0x7f;
+            const int wv = grp >> 2, gg = grp & 3;
+            if (code & 0x80) {  // ambiguous: every row of the workgroup
+                for (int k = 0; k < SC_ROWS / RF_TEAM; ++k) {
+                    const int i = wg * SC_ROWS + k * RF_TEAM + tl;
+                    if (i < Na) lex_min(best, bi, canon_d2(qx, qy, qz, At + 3 * (size_t)i), i);
+                }
+            } else {  // the row group: rows 16a + 4g + r of its wave, lane tl = 4a + r
+#pragma unroll
+                for (int k = 0; k < (SC_ATILES * 4 + RF_TEAM - 1) / RF_TEAM; ++k) {
+                    const int ar = k * RF_TEAM + tl;
+                    if (ar < SC_ATILES * 4) {
+                        const int i = wg * SC_ROWS + wv * (SC_ATILES * 16) + 16 * (ar >> 2) +
+                                      4 * gg + (ar & 3);
+                        if (i < Na)
+                            lex_min(best, bi, canon_d2(qx, qy, qz, At + 3 * (size_t)i), i);
+                    }
                 }
             }
         }
-    }
-#pragma unroll
-    for (int off = RF_TEAM / 2; off > 0; off >>= 1) {
-        const float ob = __shfl_xor(best, off, RF_TEAM);
-        const int oj = __shfl_xor(bj, off, RF_TEAM);
-        if (ob < best || (ob == best && oj < bj)) {
-            best = ob;
-            bj = oj;
+        team_reduce(best, bi);
+        if (n >= 0 && tl == 0) {
+            if (bi == 0x7fffffff) {
+                bi = 0;
+                best = canon_d2(qx, qy, qz, At);
+            }
+            idx[(size_t)t * Nb + j] = bi;
+            dist[(size_t)t * Nb + j] = best;
+        }
+        if (tl == 0 && j < Nb) {
+            my_cand += n >= 0 ? (unsigned)n : 0u;
+            my_heavy += n < 0 ? 1u : 0u;
         }
     }
-    if (n >= 0 && tl == 0) {
-        if (bj == 0x7fffffff) {  // nothing comparable (non-finite data): first index
-            bj = 0;
-            best = canon_d2(qx, qy, qz, Pt);
-        }
-        idx[(size_t)t * Nq + i] = bj;
-        dist[(size_t)t * Nq + i] = best;
-    }
-    if (tl == 0 && i < Nq) {
-        my_cand += n >= 0 ? (unsigned)n : 0u;
-        my_heavy += n < 0 ? 1u : 0u;
-    }
-    }
-    if (stats) {
-        if (tl == 0) {
-            atomicAdd(&cnt[0], my_cand);
-            atomicAdd(&cnt[1], my_heavy);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const int live = min(RF_QUERIES, Nq - (int)blockIdx.x * RF_QUERIES);
-            atomicAdd(&stats[0], (unsigned long long)live);
-            atomicAdd(&stats[1], (unsigned long long)cnt[0]);
-            atomicAdd(&stats[2], (unsigned long long)cnt[1]);
-        }
-    }
+    flush_stats(cnt, stats, min(RF_QUERIES, Nb - (int)blockIdx.x * RF_QUERIES), my_cand,
+                my_heavy, tl);
 }
 
 }  // namespace
@@ -449,38 +673,60 @@ bool screen_available() { return true; }
 
 static int padded_targets(int Np) { return ((Np + SC_CHUNK - 1) / SC_CHUNK) * SC_CHUNK; }
 
-size_t screen_scratch_bytes(int T, int Nq, int Np) {
-    return Arena::need((size_t)T, 4) * 2 + Arena::need((size_t)T * Nq, 4) +
-           Arena::need((size_t)T * Nq * REC_INTS, 4) + nn_exact_list_scratch_bytes(T, Nq, Np) +
-           Arena::need((size_t)T * padded_targets(Np) * 3, sizeof(bf16x8));
+size_t screen_scratch_bytes(int T, int Na, int Nb) {
+    const size_t nwg = (size_t)(Na + SC_ROWS - 1) / SC_ROWS;
+    const size_t Nb_pad = padded_targets(Nb);
+    return Arena::need((size_t)T, 4) * 4 +                           // norms, heavy counts
+           Arena::need((size_t)T * Na, 4) + Arena::need((size_t)T * Nb, 4) +  // heavy lists
+           Arena::need((size_t)T * Na * REC_INTS, 4) +                // row records
+           Arena::need((size_t)T * Nb * CREC_INTS, 4) +               // column records
+           Arena::need((size_t)T * Nb_pad * 3, sizeof(bf16x8)) +      // packed b operands
+           Arena::need((size_t)T * nwg * Nb_pad, 4) +                 // column partial minima
+           Arena::need((size_t)T * nwg * Nb_pad, 1) +                 // their tags
+           std::max(nn_exact_list_scratch_bytes(T, Na, Nb), nn_exact_list_scratch_bytes(T, Nb, Na));
 }
 
-void launch_nn_screened(const float *Q, int Nq, const float *P, int Np, int T, int32_t *idx,
-                        float *dist, char *scratch, unsigned long long *stats, dc_ctx *prof,
-                        hipStream_t s) {
+void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int T,
+                             int32_t *idx_a, float *dist_a, int32_t *idx_b, float *dist_b,
+                             char *scratch, unsigned long long *stats, dc_ctx *prof,
+                             hipStream_t s) {
     Arena ar;
     ar.base = scratch;
-    ar.cap = screen_scratch_bytes(T, Nq, Np);
-    float *npmax = ar.take<float>((size_t)T);
-    int32_t *heavy_cnt = ar.take<int32_t>((size_t)T);
-    int32_t *heavy_list = ar.take<int32_t>((size_t)T * Nq);
-    int32_t *rec = ar.take<int32_t>((size_t)T * Nq * REC_INTS);
-    char *exact_scratch = ar.take<char>(nn_exact_list_scratch_bytes(T, Nq, Np));
-    const int Np_pad = padded_targets(Np);
-    bf16x8 *packed = ar.take<bf16x8>((size_t)T * Np_pad * 3);
-    hipLaunchKernelGGL(k_norm_max, dim3(T), dim3(256), 0, s, P, Np, npmax, heavy_cnt);
-    hipLaunchKernelGGL(k_pack_targets, dim3(Np_pad / 256, T), dim3(256), 0, s, P, Np, Np_pad,
+    ar.cap = screen_scratch_bytes(T, Na, Nb);
+    const int nwg = (Na + SC_ROWS - 1) / SC_ROWS;
+    const int Nb_pad = padded_targets(Nb);
+    float *nbmax = ar.take<float>((size_t)T);
+    float *namax = ar.take<float>((size_t)T);
+    int32_t *hcnt_a = ar.take<int32_t>((size_t)T);
+    int32_t *hcnt_b = ar.take<int32_t>((size_t)T);
+    int32_t *hlist_a = ar.take<int32_t>((size_t)T * Na);
+    int32_t *hlist_b = ar.take<int32_t>((size_t)T * Nb);
+    int32_t *rec = ar.take<int32_t>((size_t)T * Na * REC_INTS);
+    int32_t *crec = ar.take<int32_t>((size_t)T * Nb * CREC_INTS);
+    bf16x8 *packed = ar.take<bf16x8>((size_t)T * Nb_pad * 3);
+    float *cpart = ar.take<float>((size_t)T * nwg * Nb_pad);
+    uint8_t *ctag = ar.take<uint8_t>((size_t)T * nwg * Nb_pad);
+    char *exact_scratch = ar.take<char>(
+        std::max(nn_exact_list_scratch_bytes(T, Na, Nb), nn_exact_list_scratch_bytes(T, Nb, Na)));
+    hipLaunchKernelGGL(k_norm_max, dim3(T), dim3(256), 0, s, b, Nb, nbmax, hcnt_a);
+    hipLaunchKernelGGL(k_norm_max, dim3(T), dim3(256), 0, s, a, Na, namax, hcnt_b);
+    hipLaunchKernelGGL(k_pack_targets, dim3(Nb_pad / 256, T), dim3(256), 0, s, b, Nb, Nb_pad,
                        packed);
     {
         ProfScope ps(prof, 0, s);
-        hipLaunchKernelGGL(k_screen, dim3((Nq + SC_ROWS - 1) / SC_ROWS, T), dim3(SC_THREADS), 0,
-                           s, Q, Nq, packed, Np, Np_pad, npmax, rec, heavy_cnt, heavy_list);
+        hipLaunchKernelGGL(k_screen<true>, dim3(nwg, T), dim3(SC_THREADS), 0, s, a, Na, packed, b,
+                           Nb, Nb_pad, nbmax, namax, rec, hcnt_a, hlist_a, cpart, ctag);
     }
     {
         ProfScope ps(prof, 1, s);
-        hipLaunchKernelGGL(k_refine, dim3((Nq + RF_QUERIES - 1) / RF_QUERIES, T),
-                           dim3(RF_THREADS), 0, s, Q, Nq, P, Np, rec, idx, dist, stats);
-        launch_nn_exact_list(Q, Nq, P, Np, T, heavy_list, heavy_cnt, idx, dist, exact_scratch, s);
+        hipLaunchKernelGGL(k_refine, dim3((Na + RF_QUERIES - 1) / RF_QUERIES, T),
+                           dim3(RF_THREADS), 0, s, a, Na, b, Nb, rec, idx_a, dist_a, stats);
+        hipLaunchKernelGGL(k_colmerge, dim3((Nb + 255) / 256, T), dim3(256), 0, s, b, Nb, Nb_pad,
+                           nwg, cpart, ctag, namax, crec, hcnt_b, hlist_b);
+        hipLaunchKernelGGL(k_colrefine, dim3((Nb + RF_QUERIES - 1) / RF_QUERIES, T),
+                           dim3(RF_THREADS), 0, s, a, Na, b, Nb, crec, idx_b, dist_b, stats);
+        launch_nn_exact_list(a, Na, b, Nb, T, hlist_a, hcnt_a, idx_a, dist_a, exact_scratch, s);
+        launch_nn_exact_list(b, Nb, a, Na, T, hlist_b, hcnt_b, idx_b, dist_b, exact_scratch, s);
     }
 }
 
