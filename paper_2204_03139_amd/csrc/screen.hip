@@ -45,7 +45,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 #define DC_SCREEN_STAGE 256
 #endif
 #ifndef DC_SCREEN_CHUNK
-#define DC_SCREEN_CHUNK 1024
+#define DC_SCREEN_CHUNK 2048
 #endif
 constexpr int SC_WAVES = 4;
 constexpr int SC_THREADS = 64 * SC_WAVES;
@@ -194,14 +194,15 @@ __global__ __launch_bounds__(256) void k_norm_max(const float *__restrict__ P, i
 // screened value <= threshold(m, nq, nmax), where m is the query's screened minimum, nq its squared
 // norm and nmax the largest squared norm among the points it is compared with.  Increasing in m.
 __device__ __forceinline__ float threshold(float m, float nq, float nmax) {
+    // v_sqrt_f32 is within 1 ulp; every use below is scaled up by `up`, which covers it
     const float up = 1.0001f;
-    const float qn = __builtin_sqrtf(nq) * up;
+    const float qn = __builtin_amdgcn_sqrtf(nq) * up;
     const float mp = fmaxf(m, 0.f);
     const float e0 = (SCREEN_C * (nq + nmax) + SCREEN_TAU) * up;
-    const float r0 = qn + __builtin_sqrtf(mp + e0) * up;
+    const float r0 = qn + __builtin_amdgcn_sqrtf(mp + e0) * up;
     const float e1 = (SCREEN_C * (nq + r0 * r0) + SCREEN_TAU) * up;  // at the screened winner
     const float d1 = (mp + e1) * (1.0f + CANON_U13) * up;
-    const float r1 = qn + __builtin_sqrtf(d1) * up;
+    const float r1 = qn + __builtin_amdgcn_sqrtf(d1) * up;
     const float e2 = (SCREEN_C * (nq + r1 * r1) + SCREEN_TAU) * up;  // at the canonical winner
     const float th = m + e1 + e2 + CANON_U13 * (mp + e1);
     return th + fabsf(th) * 1e-4f + SCREEN_TAU;
@@ -364,7 +365,7 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(
 #pragma unroll
                 for (int k = 0; k < SC_GROUPS; ++k) {
                     const float v = colbuf[COLS ? k : 0][c][btl];
-                    second = fminf(second, fmaxf(v, best));
+                    second = __builtin_amdgcn_fmed3f(v, best, second);  // best <= second
                     bg = v < best ? k : bg;
                     best = fminf(best, v);
                 }
@@ -435,6 +436,24 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(
 constexpr int CMAXC = 6;
 constexpr int CREC_INTS = 1 + CMAXC + 1;
 
+constexpr int CM_TPT = 4;  // targets per thread in the column merge (one 16-byte load each)
+
+__device__ __forceinline__ void colmerge_insert(float (&bv)[CMAXC + 1], int (&bw)[CMAXC + 1],
+                                                float v, int w) {
+    if (v < bv[CMAXC]) {
+#pragma unroll
+        for (int k = 0; k <= CMAXC; ++k) {
+            const bool lt = v < bv[k];
+            const float tv = bv[k];
+            const int tw = bw[k];
+            bv[k] = lt ? v : tv;
+            bw[k] = lt ? w : tw;
+            v = lt ? tv : v;
+            w = lt ? tw : w;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_colmerge(const float *__restrict__ P, int Np, int Np_pad,
                                                   int nwg, const float *__restrict__ cpart,
                                                   const uint8_t *__restrict__ ctag,
@@ -443,51 +462,50 @@ __global__ __launch_bounds__(256) void k_colmerge(const float *__restrict__ P, i
                                                   int32_t *__restrict__ heavy_cnt,
                                                   int32_t *__restrict__ heavy_list) {
     const int t = blockIdx.y;
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= Np) return;
+    const int j0 = (blockIdx.x * 256 + threadIdx.x) * CM_TPT;
+    if (j0 >= Np) return;
     const float inf = __builtin_inff();
-    float bv[CMAXC + 1];
-    int bw[CMAXC + 1];
+    float bv[CM_TPT][CMAXC + 1];
+    int bw[CM_TPT][CMAXC + 1];
 #pragma unroll
-    for (int k = 0; k <= CMAXC; ++k) {
-        bv[k] = inf;
-        bw[k] = -1;
-    }
-    for (int w = 0; w < nwg; ++w) {
-        float v = cpart[((size_t)t * nwg + w) * Np_pad + j];
-        if (v < bv[CMAXC]) {
-            int ww = w;
+    for (int u = 0; u < CM_TPT; ++u)
 #pragma unroll
-            for (int k = 0; k <= CMAXC; ++k) {
-                const bool lt = v < bv[k];
-                const float tv = bv[k];
-                const int tw = bw[k];
-                bv[k] = lt ? v : tv;
-                bw[k] = lt ? ww : tw;
-                v = lt ? tv : v;
-                ww = lt ? tw : ww;
-            }
+        for (int k = 0; k <= CMAXC; ++k) {
+            bv[u][k] = inf;
+            bw[u][k] = -1;
         }
+    const float *base = cpart + (size_t)t * nwg * Np_pad + j0;
+    for (int w = 0; w < nwg; ++w) {
+        const float4 v = *reinterpret_cast<const float4 *>(base + (size_t)w * Np_pad);
+        colmerge_insert(bv[0], bw[0], v.x, w);
+        colmerge_insert(bv[1], bw[1], v.y, w);
+        colmerge_insert(bv[2], bw[2], v.z, w);
+        colmerge_insert(bv[3], bw[3], v.w, w);
     }
-    const float *pj = P + ((size_t)t * Np + j) * 3;
-    const float np = norm2(pj[0], pj[1], pj[2]);
     const float nqm = nqmax[t];
-    const float theta = threshold(bv[0], np, nqm);
-    const bool finite = __builtin_isfinite(bv[0]) && __builtin_isfinite(theta) &&
-                        __builtin_isfinite(nqm) && bw[0] >= 0;
-    int32_t *rr = crec + ((size_t)t * Np + j) * CREC_INTS;
-    if (!finite || bv[CMAXC] <= theta) {
-        rr[0] = -1;
-        const int pos = atomicAdd(&heavy_cnt[t], 1);
-        heavy_list[(size_t)t * Np + pos] = j;
-        return;
-    }
-    int n = 0;
 #pragma unroll
-    for (int k = 0; k < CMAXC; ++k)
-        if (bw[k] >= 0 && bv[k] <= theta)
-            rr[1 + n++] = (bw[k] << 8) | ctag[((size_t)t * nwg + bw[k]) * Np_pad + j];
-    rr[0] = n;
+    for (int u = 0; u < CM_TPT; ++u) {
+        const int j = j0 + u;
+        if (j >= Np) break;
+        const float *pj = P + ((size_t)t * Np + j) * 3;
+        const float np = norm2(pj[0], pj[1], pj[2]);
+        const float theta = threshold(bv[u][0], np, nqm);
+        const bool finite = __builtin_isfinite(bv[u][0]) && __builtin_isfinite(theta) &&
+                            __builtin_isfinite(nqm) && bw[u][0] >= 0;
+        int32_t *rr = crec + ((size_t)t * Np + j) * CREC_INTS;
+        if (!finite || bv[u][CMAXC] <= theta) {
+            rr[0] = -1;
+            const int pos = atomicAdd(&heavy_cnt[t], 1);
+            heavy_list[(size_t)t * Np + pos] = j;
+            continue;
+        }
+        int n = 0;
+#pragma unroll
+        for (int k = 0; k < CMAXC; ++k)
+            if (bw[u][k] >= 0 && bv[u][k] <= theta)
+                rr[1 + n++] = (bw[u][k] << 8) | ctag[((size_t)t * nwg + bw[u][k]) * Np_pad + j];
+        rr[0] = n;
+    }
 }
 
 __device__ __forceinline__ float canon_d2(float qx, float qy, float qz, const float *p) {
@@ -721,8 +739,9 @@ void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int
         ProfScope ps(prof, 1, s);
         hipLaunchKernelGGL(k_refine, dim3((Na + RF_QUERIES - 1) / RF_QUERIES, T),
                            dim3(RF_THREADS), 0, s, a, Na, b, Nb, rec, idx_a, dist_a, stats);
-        hipLaunchKernelGGL(k_colmerge, dim3((Nb + 255) / 256, T), dim3(256), 0, s, b, Nb, Nb_pad,
-                           nwg, cpart, ctag, namax, crec, hcnt_b, hlist_b);
+        hipLaunchKernelGGL(k_colmerge, dim3((Nb + 256 * CM_TPT - 1) / (256 * CM_TPT), T),
+                           dim3(256), 0, s, b, Nb, Nb_pad, nwg, cpart, ctag, namax, crec, hcnt_b,
+                           hlist_b);
         hipLaunchKernelGGL(k_colrefine, dim3((Nb + RF_QUERIES - 1) / RF_QUERIES, T),
                            dim3(RF_THREADS), 0, s, a, Na, b, Nb, crec, idx_b, dist_b, stats);
         launch_nn_exact_list(a, Na, b, Nb, T, hlist_a, hcnt_a, idx_a, dist_a, exact_scratch, s);

@@ -1,128 +1,155 @@
 // Stable, atomic-free sort of per-frame integer keys (LSD radix, 8-bit digits).
 //
-// One workgroup of 1024 lanes (16 waves of 64) sorts one frame.  Items are visited in chunks of
-// 1024 in index order.  Inside a wave, lanes holding the same digit are found with eight ballots;
-// a lane's rank is the number of lower lanes in its group, and the group's lowest lane writes the
-// group size into a per-wave histogram in LDS (distinct digits, so no two writers collide).  A
-// prefix over (wave, digit) then gives every item its output slot, preserving input order among
-// equal digits.  Two sweeps per digit (count, then scatter), no atomics, so the permutation is
-// the same on every run.  The sorted keys and the original positions are the outputs.
+// Each digit pass is three launches over blocks of 1024 items (many blocks per frame):
+//   k_ss_hist    each block counts its digits: within a wave, lanes holding the same digit are
+//                found with eight ballots, the group's lowest lane records the group size in a
+//                per-wave LDS row (distinct digits, so no two writers collide); the block sums the
+//                rows and stores counts[t][digit][block];
+//   k_ss_scan    one workgroup per frame turns the counts, in (digit, block) order, into
+//                exclusive offsets;
+//   k_ss_scatter each block ranks its items again the same way, in item order (four rounds of 256
+//                items, waves in order inside a round), and writes item e to
+//                offset[digit][block] + rank, which preserves the input order among equal keys.
+// No atomics anywhere, so the permutation is the same on every run.  Keys outside [0, limit] are
+// clamped to limit (they sort last).
 #include "dc_internal.h"
 
 namespace dc {
 namespace {
 
-constexpr int SS_THREADS = 1024;
-constexpr int SS_WAVES = SS_THREADS / 64;
-constexpr int SS_BINS = 256;
+constexpr int SB_THREADS = 256;
+constexpr int SB_WAVES = SB_THREADS / 64;
+constexpr int SB_ROUNDS = 4;
+constexpr int SB_ITEMS = SB_THREADS * SB_ROUNDS;  // items per block
+constexpr int BINS = 256;
 
 __device__ __forceinline__ int load_key(const int32_t *keys, size_t o, int limit) {
     const int k = keys[o];
     return (k < 0 || k > limit) ? limit : k;
 }
 
-__global__ __launch_bounds__(SS_THREADS) void k_segsort(const int32_t *__restrict__ keys, int N,
-                                                        int key_limit, int passes,
-                                                        int32_t *__restrict__ tk0,
-                                                        int32_t *__restrict__ tv0,
-                                                        int32_t *__restrict__ tk1,
-                                                        int32_t *__restrict__ tv1,
-                                                        int32_t *__restrict__ out_keys,
-                                                        int32_t *__restrict__ out_vals) {
-    __shared__ int whist[SS_WAVES][SS_BINS];
-    __shared__ int running[SS_BINS];
-    const int t = blockIdx.x;
-    const size_t fo = (size_t)t * N;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+// lanes of this wave whose `valid` item has the same digit as this lane
+__device__ __forceinline__ unsigned long long same_digit(bool valid, int d) {
+    unsigned long long m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1;
+        const unsigned long long bb = __ballot(valid && bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+struct SortIO {
+    const int32_t *src_keys;  // previous pass output, or nullptr for the first pass
+    const int32_t *src_vals;
+    const int32_t *keys;      // first pass input
+    int limit;
+};
+
+__device__ __forceinline__ void read_item(const SortIO &io, size_t o, int e, int &key, int &val) {
+    key = io.src_keys ? io.src_keys[o] : load_key(io.keys, o, io.limit);
+    val = io.src_vals ? io.src_vals[o] : e;
+}
+
+__global__ __launch_bounds__(SB_THREADS) void k_ss_hist(SortIO io, int N, int shift, int nblk,
+                                                        int32_t *__restrict__ counts) {
+    __shared__ int whist[SB_WAVES][BINS];
+    __shared__ int total[BINS];
+    const int t = blockIdx.y, blk = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-
-    for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
-        const int32_t *sk = (p == 0) ? nullptr : ((p & 1) ? tk0 : tk1);
-        const int32_t *sv = (p == 0) ? nullptr : ((p & 1) ? tv0 : tv1);
-        int32_t *dk = (p == passes - 1) ? out_keys : ((p & 1) ? tk1 : tk0);
-        int32_t *dv = (p == passes - 1) ? out_vals : ((p & 1) ? tv1 : tv0);
-
-        // ---- count sweep: digit totals
-        if (threadIdx.x < SS_BINS) running[threadIdx.x] = 0;
-        for (int c = 0; c < N; c += SS_THREADS) {
-            for (int k = threadIdx.x; k < SS_WAVES * SS_BINS; k += SS_THREADS)
-                (&whist[0][0])[k] = 0;
-            __syncthreads();
-            const int e = c + threadIdx.x;
-            const bool valid = e < N;
-            int key = 0;
-            if (valid) key = sk ? sk[fo + e] : load_key(keys, fo + e, key_limit);
-            const int d = (key >> shift) & (SS_BINS - 1);
-            unsigned long long m = __ballot(valid);
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const bool bit = (d >> b) & 1;
-                const unsigned long long bb = __ballot(valid && bit);
-                m &= bit ? bb : ~bb;
-            }
-            if (valid && __popcll(m & below) == 0) whist[wave][d] = __popcll(m);
-            __syncthreads();
-            if (threadIdx.x < SS_BINS) {
-                int acc = running[threadIdx.x];
-                for (int w = 0; w < SS_WAVES; ++w) acc += whist[w][threadIdx.x];
-                running[threadIdx.x] = acc;
-            }
-            __syncthreads();
-        }
-        // exclusive prefix over digits
-        if (threadIdx.x == 0) {
-            int acc = 0;
-            for (int b = 0; b < SS_BINS; ++b) {
-                const int c = running[b];
-                running[b] = acc;
-                acc += c;
-            }
-        }
+    total[threadIdx.x] = 0;
+    for (int r = 0; r < SB_ROUNDS; ++r) {
+        for (int k = threadIdx.x; k < SB_WAVES * BINS; k += SB_THREADS) (&whist[0][0])[k] = 0;
         __syncthreads();
-        // ---- scatter sweep
-        for (int c = 0; c < N; c += SS_THREADS) {
-            for (int k = threadIdx.x; k < SS_WAVES * SS_BINS; k += SS_THREADS)
-                (&whist[0][0])[k] = 0;
-            __syncthreads();
-            const int e = c + threadIdx.x;
-            const bool valid = e < N;
-            int key = 0, val = 0;
-            if (valid) {
-                key = sk ? sk[fo + e] : load_key(keys, fo + e, key_limit);
-                val = sv ? sv[fo + e] : e;
-            }
-            const int d = (key >> shift) & (SS_BINS - 1);
-            unsigned long long m = __ballot(valid);
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const bool bit = (d >> b) & 1;
-                const unsigned long long bb = __ballot(valid && bit);
-                m &= bit ? bb : ~bb;
-            }
-            const int rank = __popcll(m & below);
-            if (valid && rank == 0) whist[wave][d] = __popcll(m);
-            __syncthreads();
-            if (threadIdx.x < SS_BINS) {  // per digit: offsets of each wave's group
-                int acc = running[threadIdx.x];
-                for (int w = 0; w < SS_WAVES; ++w) {
-                    const int c2 = whist[w][threadIdx.x];
-                    whist[w][threadIdx.x] = acc;
-                    acc += c2;
-                }
-                running[threadIdx.x] = acc;
-            }
-            __syncthreads();
-            if (valid) {
-                const int pos = whist[wave][d] + rank;
-                dk[fo + pos] = key;
-                dv[fo + pos] = val;
-            }
-            __syncthreads();
+        const int e = blk * SB_ITEMS + r * SB_THREADS + threadIdx.x;
+        const bool valid = e < N;
+        int key = 0, val = 0;
+        if (valid) read_item(io, (size_t)t * N + e, e, key, val);
+        const int d = (key >> shift) & (BINS - 1);
+        const unsigned long long m = same_digit(valid, d);
+        if (valid && __popcll(m & below) == 0) whist[wave][d] = __popcll(m);
+        __syncthreads();
+        int acc = total[threadIdx.x];
+        for (int w = 0; w < SB_WAVES; ++w) acc += whist[w][threadIdx.x];
+        total[threadIdx.x] = acc;
+        __syncthreads();
+    }
+    counts[((size_t)t * BINS + threadIdx.x) * nblk + blk] = total[threadIdx.x];
+}
+
+// exclusive prefix over (digit, block) of one frame, in place
+__global__ __launch_bounds__(1024) void k_ss_scan(int32_t *__restrict__ counts, int nblk) {
+    __shared__ int part[1024];
+    const int t = blockIdx.x;
+    int32_t *c = counts + (size_t)t * BINS * nblk;
+    const int n = BINS * nblk;
+    const int per = (n + 1023) / 1024;
+    const int lo = threadIdx.x * per, hi = min(n, lo + per);
+    int s = 0;
+    for (int k = lo; k < hi; ++k) s += c[k];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int k = 0; k < 1024; ++k) {
+            const int v = part[k];
+            part[k] = acc;
+            acc += v;
         }
     }
+    __syncthreads();
+    int acc = part[threadIdx.x];
+    for (int k = lo; k < hi; ++k) {
+        const int v = c[k];
+        c[k] = acc;
+        acc += v;
+    }
 }
+
+__global__ __launch_bounds__(SB_THREADS) void k_ss_scatter(SortIO io, int N, int shift, int nblk,
+                                                           const int32_t *__restrict__ offsets,
+                                                           int32_t *__restrict__ dst_keys,
+                                                           int32_t *__restrict__ dst_vals) {
+    __shared__ int whist[SB_WAVES][BINS];
+    __shared__ int running[BINS];
+    const int t = blockIdx.y, blk = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    running[threadIdx.x] = offsets[((size_t)t * BINS + threadIdx.x) * nblk + blk];
+    for (int r = 0; r < SB_ROUNDS; ++r) {
+        for (int k = threadIdx.x; k < SB_WAVES * BINS; k += SB_THREADS) (&whist[0][0])[k] = 0;
+        __syncthreads();
+        const int e = blk * SB_ITEMS + r * SB_THREADS + threadIdx.x;
+        const bool valid = e < N;
+        int key = 0, val = 0;
+        if (valid) read_item(io, (size_t)t * N + e, e, key, val);
+        const int d = (key >> shift) & (BINS - 1);
+        const unsigned long long m = same_digit(valid, d);
+        const int rank = __popcll(m & below);
+        if (valid && rank == 0) whist[wave][d] = __popcll(m);
+        __syncthreads();
+        {  // per digit: starting slot of each wave's group in this round
+            int acc = running[threadIdx.x];
+            for (int w = 0; w < SB_WAVES; ++w) {
+                const int c = whist[w][threadIdx.x];
+                whist[w][threadIdx.x] = acc;
+                acc += c;
+            }
+            running[threadIdx.x] = acc;
+        }
+        __syncthreads();
+        if (valid) {
+            const size_t pos = (size_t)t * N + whist[wave][d] + rank;
+            dst_keys[pos] = key;
+            dst_vals[pos] = val;
+        }
+        __syncthreads();
+    }
+}
+
+static_assert(SB_THREADS == BINS, "one thread per digit bin");
 
 }  // namespace
 
@@ -132,17 +159,37 @@ static int ss_passes(int key_limit) {
     return (bits + 7) / 8;
 }
 
-size_t segsort_scratch_bytes(int T, int N) { return 4 * Arena::need((size_t)T * N, 4); }
+static int ss_blocks(int N) { return (N + SB_ITEMS - 1) / SB_ITEMS; }
+
+size_t segsort_scratch_bytes(int T, int N) {
+    return 4 * Arena::need((size_t)T * N, 4) + Arena::need((size_t)T * BINS * ss_blocks(N), 4);
+}
 
 void launch_segsort(const int32_t *keys, int T, int N, int key_limit, int32_t *out_keys,
                     int32_t *out_vals, char *scratch, hipStream_t s) {
     const size_t piece = Arena::need((size_t)T * N, 4);
-    int32_t *tk0 = reinterpret_cast<int32_t *>(scratch);
-    int32_t *tv0 = reinterpret_cast<int32_t *>(scratch + piece);
-    int32_t *tk1 = reinterpret_cast<int32_t *>(scratch + 2 * piece);
-    int32_t *tv1 = reinterpret_cast<int32_t *>(scratch + 3 * piece);
-    hipLaunchKernelGGL(k_segsort, dim3(T), dim3(SS_THREADS), 0, s, keys, N, key_limit,
-                       ss_passes(key_limit), tk0, tv0, tk1, tv1, out_keys, out_vals);
+    int32_t *tk[2] = {reinterpret_cast<int32_t *>(scratch),
+                      reinterpret_cast<int32_t *>(scratch + 2 * piece)};
+    int32_t *tv[2] = {reinterpret_cast<int32_t *>(scratch + piece),
+                      reinterpret_cast<int32_t *>(scratch + 3 * piece)};
+    int32_t *counts = reinterpret_cast<int32_t *>(scratch + 4 * piece);
+    if (T <= 0 || N <= 0) return;
+    const int nblk = ss_blocks(N);
+    const int passes = ss_passes(key_limit);
+    const dim3 grid(nblk, T);
+    for (int p = 0; p < passes; ++p) {
+        SortIO io;
+        io.keys = keys;
+        io.limit = key_limit;
+        io.src_keys = p == 0 ? nullptr : tk[(p - 1) & 1];
+        io.src_vals = p == 0 ? nullptr : tv[(p - 1) & 1];
+        int32_t *dk = (p == passes - 1) ? out_keys : tk[p & 1];
+        int32_t *dv = (p == passes - 1) ? out_vals : tv[p & 1];
+        hipLaunchKernelGGL(k_ss_hist, grid, dim3(SB_THREADS), 0, s, io, N, 8 * p, nblk, counts);
+        hipLaunchKernelGGL(k_ss_scan, dim3(T), dim3(1024), 0, s, counts, nblk);
+        hipLaunchKernelGGL(k_ss_scatter, grid, dim3(SB_THREADS), 0, s, io, N, 8 * p, nblk, counts,
+                           dk, dv);
+    }
 }
 
 }  // namespace dc
