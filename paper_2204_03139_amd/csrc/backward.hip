@@ -76,31 +76,52 @@ __global__ void k_bounds(const int32_t *__restrict__ sorted, int N, int K,
     start[(size_t)t * (K + 1) + f] = lower_bound(sorted + (size_t)t * N, N, f);
 }
 
-// grad_verts[t,v] = sum over incident (face f, corner c) in increasing (f, c), then over the
-// points i of face f in increasing i, of bary[t,i,c] * g[t,i]
-__global__ __launch_bounds__(BW_THREADS) void k_sample_bwd(
+// per face and corner: fg[t,f,c] = sum over the points i of face f, in increasing i, of
+// bary[t,i,c] * g[t,i]
+__global__ __launch_bounds__(BW_THREADS) void k_face_grad(
     const float *__restrict__ gpts, const float *__restrict__ bary,
-    const int32_t *__restrict__ pts_by_face, const int32_t *__restrict__ face_start,
-    const int32_t *__restrict__ corners_by_vertex, const int32_t *__restrict__ vert_start, int V,
-    int F, int N, float *__restrict__ gverts) {
+    const int32_t *__restrict__ pts_by_face, const int32_t *__restrict__ face_start, int F, int N,
+    float *__restrict__ fg) {
     const int t = blockIdx.y;
-    const int v = blockIdx.x * BW_THREADS + threadIdx.x;
-    if (v >= V) return;
+    const int f = blockIdx.x * BW_THREADS + threadIdx.x;
+    if (f >= F) return;
     const int32_t *fs = face_start + (size_t)t * (F + 1);
     const int32_t *pf = pts_by_face + (size_t)t * N;
     const float *gt = gpts + (size_t)t * N * 3;
     const float *bt = bary + (size_t)t * N * 3;
+    float acc[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    for (int p = fs[f]; p < fs[f + 1]; ++p) {
+        const int i = pf[p];
+        const float g0 = gt[3 * (size_t)i], g1 = gt[3 * (size_t)i + 1], g2 = gt[3 * (size_t)i + 2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float w = bt[3 * (size_t)i + c];
+            acc[c][0] = __builtin_fmaf(w, g0, acc[c][0]);
+            acc[c][1] = __builtin_fmaf(w, g1, acc[c][1]);
+            acc[c][2] = __builtin_fmaf(w, g2, acc[c][2]);
+        }
+    }
+    float *o = fg + ((size_t)t * F + f) * 9;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) o[3 * c + d] = acc[c][d];
+}
+
+// grad_verts[t,v] = sum over the incident (face f, corner c), in increasing (f, c), of fg[t,f,c]
+__global__ __launch_bounds__(BW_THREADS) void k_vertex_grad(
+    const float *__restrict__ fg, const int32_t *__restrict__ corners_by_vertex,
+    const int32_t *__restrict__ vert_start, int V, int F, float *__restrict__ gverts) {
+    const int t = blockIdx.y;
+    const int v = blockIdx.x * BW_THREADS + threadIdx.x;
+    if (v >= V) return;
+    const float *ft = fg + (size_t)t * F * 9;
     float a0 = 0.f, a1 = 0.f, a2 = 0.f;
     for (int q = vert_start[v]; q < vert_start[v + 1]; ++q) {
-        const int fc = corners_by_vertex[q];
-        const int f = fc / 3, c = fc - 3 * (fc / 3);
-        for (int p = fs[f]; p < fs[f + 1]; ++p) {
-            const int i = pf[p];
-            const float w = bt[3 * (size_t)i + c];
-            a0 = __builtin_fmaf(w, gt[3 * (size_t)i], a0);
-            a1 = __builtin_fmaf(w, gt[3 * (size_t)i + 1], a1);
-            a2 = __builtin_fmaf(w, gt[3 * (size_t)i + 2], a2);
-        }
+        const int fc = corners_by_vertex[q];  // 3 f + c
+        a0 += ft[3 * (size_t)fc];
+        a1 += ft[3 * (size_t)fc + 1];
+        a2 += ft[3 * (size_t)fc + 2];
     }
     float *o = gverts + ((size_t)t * V + v) * 3;
     o[0] = a0;
@@ -148,7 +169,8 @@ void launch_chamfer_bwd(const double *grad_loss, const float *a, const float *b,
 size_t sample_bwd_scratch_bytes(int T, int V, int F, int N) {
     return 2 * Arena::need((size_t)T * N, 4) + segsort_scratch_bytes(T, N) +
            Arena::need((size_t)T * (F + 1), 4) + 2 * Arena::need((size_t)3 * F, 4) +
-           segsort_scratch_bytes(1, 3 * F) + Arena::need((size_t)V + 1, 4);
+           segsort_scratch_bytes(1, 3 * F) + Arena::need((size_t)V + 1, 4) +
+           Arena::need((size_t)T * F * 9, 4);
 }
 
 void launch_sample_bwd(const float *grad_points, const int32_t *faces, const int32_t *face_idx,
@@ -165,6 +187,7 @@ void launch_sample_bwd(const float *grad_points, const int32_t *faces, const int
     int32_t *cv = ar.take<int32_t>((size_t)3 * F);
     char *ss2 = ar.take<char>(segsort_scratch_bytes(1, 3 * F));
     int32_t *vstart = ar.take<int32_t>((size_t)V + 1);
+    float *fg = ar.take<float>((size_t)T * F * 9);
     // points grouped by face (face -1 of a degenerate frame sorts last, as key F, and is unused)
     launch_segsort(face_idx, T, N, F, fk, fv, ss1, s);
     hipLaunchKernelGGL(k_bounds, dim3((F + 1 + 255) / 256, T), dim3(256), 0, s, fk, N, F, fstart);
@@ -172,8 +195,10 @@ void launch_sample_bwd(const float *grad_points, const int32_t *faces, const int
     launch_segsort(faces, 1, 3 * F, V, ck, cv, ss2, s);
     hipLaunchKernelGGL(k_bounds, dim3((V + 1 + 255) / 256, 1), dim3(256), 0, s, ck, 3 * F, V,
                        vstart);
-    hipLaunchKernelGGL(k_sample_bwd, dim3((V + BW_THREADS - 1) / BW_THREADS, T), dim3(BW_THREADS),
-                       0, s, grad_points, bary, fv, fstart, cv, vstart, V, F, N, grad_verts);
+    hipLaunchKernelGGL(k_face_grad, dim3((F + BW_THREADS - 1) / BW_THREADS, T), dim3(BW_THREADS),
+                       0, s, grad_points, bary, fv, fstart, F, N, fg);
+    hipLaunchKernelGGL(k_vertex_grad, dim3((V + BW_THREADS - 1) / BW_THREADS, T),
+                       dim3(BW_THREADS), 0, s, fg, cv, vstart, V, F, grad_verts);
 }
 
 }  // namespace dc

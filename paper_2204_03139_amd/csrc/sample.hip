@@ -39,14 +39,18 @@ __global__ __launch_bounds__(AC_THREADS) void k_area_cdf(const float *__restrict
                                                          int F, double *__restrict__ cdf,
                                                          int32_t *__restrict__ lastpos,
                                                          unsigned *__restrict__ status) {
-    __shared__ double area[AC_CHUNK];
+    __shared__ double area[AC_CHUNK];  // areas, overwritten in place by the running sums
     __shared__ int bad;
+    __shared__ int lastw[AC_THREADS / 64];
+    __shared__ double carry;
     const int t = blockIdx.x;
     const float *vt = verts + (size_t)t * V * 3;
     double *ct = cdf + (size_t)t * F;
-    if (threadIdx.x == 0) bad = 0;
-    double run = 0.0;  // meaningful in lane 0 only
-    int last = -1;
+    if (threadIdx.x == 0) {
+        bad = 0;
+        carry = 0.0;
+    }
+    int last = -1;  // last face with a positive area, per thread, then per workgroup
     for (int base = 0; base < F; base += AC_CHUNK) {
         const int n = min(AC_CHUNK, F - base);
         __syncthreads();
@@ -59,20 +63,29 @@ __global__ __launch_bounds__(AC_THREADS) void k_area_cdf(const float *__restrict
             else
                 bad = 1;
             area[k] = a;
+            last = (a > 0.0) ? base + k : last;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == 0) {  // the sequential sum, in face order
+            double run = carry;
 #pragma unroll 8
             for (int k = 0; k < n; ++k) {
-                const double a = area[k];
-                run = run + a;
-                ct[base + k] = run;
-                last = (a > 0.0) ? base + k : last;
+                run = run + area[k];
+                area[k] = run;
             }
+            carry = run;
         }
+        __syncthreads();
+        for (int k = threadIdx.x; k < n; k += AC_THREADS) ct[base + k] = area[k];
     }
+    // faces are visited in increasing order per thread, so the maximum is the last positive one
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) last = max(last, __shfl_xor(last, off, 64));
+    if ((threadIdx.x & 63) == 0) lastw[threadIdx.x >> 6] = last;
     __syncthreads();
     if (threadIdx.x == 0) {
+        for (int w = 0; w < AC_THREADS / 64; ++w) last = max(last, lastw[w]);
+        const double run = carry;
         const bool degenerate = !(run > 0.0) || !__builtin_isfinite(run);
         lastpos[t] = (degenerate || bad) ? -1 : last;
         if (bad) atomicOr(status, (unsigned)ST_BAD_FACE);

@@ -155,20 +155,6 @@ __device__ __forceinline__ bf16x8 pick8(const __bf16 (&v)[32], int g) {
 
 // Target operands of every frame, packed once: target j's three non-zero K-chunks (48 bytes).
 // Padding targets up to a whole chunk get a huge norm so they never win a minimum.
-__global__ __launch_bounds__(256) void k_pack_targets(const float *__restrict__ P, int Np,
-                                                      int Np_pad, bf16x8 *__restrict__ packed) {
-    const int t = blockIdx.y;
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= Np_pad) return;
-    const bool valid = j < Np;
-    const float *p = P + ((size_t)t * Np + (valid ? j : 0)) * 3;
-    __bf16 v[32];
-    target_vector(valid ? p[0] : 0.f, valid ? p[1] : 0.f, valid ? p[2] : 0.f, valid, v);
-    bf16x8 *o = packed + ((size_t)t * Np_pad + j) * 3;
-    o[0] = pick8(v, 0);
-    o[1] = pick8(v, 1);
-    o[2] = pick8(v, 2);
-}
 
 // largest squared norm of each frame's targets (for the certificate)
 __global__ __launch_bounds__(256) void k_norm_max(const float *__restrict__ P, int Np,
@@ -208,15 +194,73 @@ __device__ __forceinline__ float threshold(float m, float nq, float nmax) {
     return th + fabsf(th) * 1e-4f + SCREEN_TAU;
 }
 
+// A larger bound that is affine in max(m, 0), for the per-stage ambiguity test of the column
+// direction: replacing the squared radii of the threshold above by (a + b)^2 <= 1.125 a^2 + 9 b^2
+// makes every term linear, so th(m) <= m + A(nq, nmax) + AFF_B * max(m, 0), with A depending only
+// on the point (computed once per target) and AFF_B a constant.  Both carry a 1e-3 relative margin
+// for the float evaluation; the margin also exceeds the rounding of the final additions, since a
+// negative m is at most the error at the screened winner, which A contains.
+constexpr double AFF_C = (double)SCREEN_C, AFF_U13 = 13.0 * 5.9604644775390625e-8;
+constexpr float AFF_B = (float)((9 * AFF_C + 9 * AFF_C * (1 + AFF_U13) * (1 + 9 * AFF_C) +
+                                 AFF_U13 * (1 + 9 * AFF_C)) * 1.001);
+
+__device__ __forceinline__ float affine_slack(float nq, float nmax) {
+    const float e0 = SCREEN_C * (nq + nmax) + SCREEN_TAU;
+    const float c1 = SCREEN_C * (2.125f * nq + 9.0f * e0) + SCREEN_TAU;
+    const float k = (float)(1.0 + 9 * AFF_C * (1 + AFF_U13) + AFF_U13);
+    return (c1 * k + 2.125f * SCREEN_C * nq + SCREEN_TAU) * 1.001f;
+}
+
+__device__ __forceinline__ float threshold_affine(float m, float slack) {
+    const float th = m + __builtin_fmaf(AFF_B, fmaxf(m, 0.f), slack);
+    return th + fabsf(th) * 1e-4f + SCREEN_TAU;
+}
+
+// Target operands of every frame, packed once: target j's three non-zero K-chunks (48 bytes), and
+// the affine threshold slack of the column direction.  Padding targets up to a whole chunk get a
+// huge norm so they never win a minimum.
+__global__ __launch_bounds__(256) void k_pack_targets(const float *__restrict__ P, int Np,
+                                                      int Np_pad, const float *__restrict__ nqmax,
+                                                      bf16x8 *__restrict__ packed,
+                                                      float *__restrict__ slack) {
+    const int t = blockIdx.y;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= Np_pad) return;
+    const bool valid = j < Np;
+    const float *p = P + ((size_t)t * Np + (valid ? j : 0)) * 3;
+    const float x = valid ? p[0] : 0.f, y = valid ? p[1] : 0.f, z = valid ? p[2] : 0.f;
+    __bf16 v[32];
+    target_vector(x, y, z, valid, v);
+    bf16x8 *o = packed + ((size_t)t * Np_pad + j) * 3;
+    o[0] = pick8(v, 0);
+    o[1] = pick8(v, 1);
+    o[2] = pick8(v, 2);
+    slack[(size_t)t * Np_pad + j] = affine_slack(norm2(x, y, z), nqmax[t]);
+}
+
+// Column partial minima are stored as the upper 16 bits of the float (a bf16 bit pattern), rounded
+// toward minus infinity, so the stored value is a lower bound of the partial.
+__device__ __forceinline__ uint16_t lower_bf16_bits(float v) {
+    const unsigned b = __float_as_uint(v);
+    const unsigned hi = b >> 16;
+    return (uint16_t)(hi + (((b >> 31) & ((b & 0xFFFFu) != 0u)) ? 1u : 0u));
+}
+
+// an upper bound of any float whose rounded-down bf16 pattern is x: one bf16 step (at most 2^-7
+// relative, or the bf16 denormal step) above x, rounded up in float
+__device__ __forceinline__ float bf16_step_up(float x) {
+    return x + fabsf(x) * (0.0078125f + 1e-6f) + SCREEN_TAU;
+}
+
 constexpr int SC_GROUPS = SC_WAVES * 4;  // row groups per workgroup: (wave, lane group g)
 constexpr int CP_PAD = SC_TPS + 1;       // column partial buffer: [group][column][tile], padded
 
 template <bool COLS>
 __global__ __launch_bounds__(SC_THREADS) void k_screen(
     const float *__restrict__ Q, int Nq, const bf16x8 *__restrict__ packed,
-    const float *__restrict__ P, int Np, int Np_pad, const float *__restrict__ npmax,
-    const float *__restrict__ nqmax, int32_t *__restrict__ rec, int32_t *__restrict__ heavy_cnt,
-    int32_t *__restrict__ heavy_list, float *__restrict__ cpart, uint8_t *__restrict__ ctag) {
+    const float *__restrict__ slack, int Np, int Np_pad, const float *__restrict__ npmax,
+    int32_t *__restrict__ rec, int32_t *__restrict__ heavy_cnt,
+    int32_t *__restrict__ heavy_list, uint16_t *__restrict__ cpart, uint8_t *__restrict__ ctag) {
     // [buffer][K-chunk][entry] -> 16 bytes.  Entry 17*bt + c holds tile bt, result column c: the
     // operand reads (16 columns of one tile) are consecutive and the staging stores (8 tiles of
     // one column, 272 bytes apart) fall in distinct banks; the read address is a per-lane base
@@ -277,7 +321,6 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(
     auto target_of = [&](int st, int u) {
         return (st / SPC) * SC_CHUNK + SC_TPS * (st % SPC) + soff[u];
     };
-    const float nqm = COLS ? nqmax[t] : 0.f;
     // register prefetch of the next stage's operands, double-buffered LDS
     bf16x8 q[SC_PER_THREAD][3];
 #pragma unroll
@@ -309,10 +352,15 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(
         // lanes of K-group 3 hold an all-zero query operand, so any finite staged operand gives
         // them zero products: they read K-chunk 0 instead of a stored zero chunk
         const bf16x8 *sb = &stage[buf][gk][col];
+        // operands of the next tile pair are read one pair ahead
+        bf16x8 N0 = sb[0], N1 = sb[SC_ROWPAD];
 #pragma unroll
         for (int bt = 0; bt < SC_TPS; bt += 2) {
-            const bf16x8 B0 = sb[bt * SC_ROWPAD];
-            const bf16x8 B1 = sb[(bt + 1) * SC_ROWPAD];
+            const bf16x8 B0 = N0, B1 = N1;
+            if (bt + 2 < SC_TPS) {
+                N0 = sb[(bt + 2) * SC_ROWPAD];
+                N1 = sb[(bt + 3) * SC_ROWPAD];
+            }
             float cm0 = inf, cm1 = inf;
 #pragma unroll
             for (int a = 0; a < SC_ATILES; ++a) {
@@ -370,14 +418,12 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(
                     best = fminf(best, v);
                 }
                 if (j < Np) {
-                    const float *pj = P + ((size_t)t * Np + j) * 3;
-                    const float np = norm2(pj[0], pj[1], pj[2]);
                     // another row group within the margin of this group's best: the merge must
                     // rescan every row of the workgroup for this target
-                    const float th = threshold(best, np, nqm);
+                    const float th = threshold_affine(best, slack[(size_t)t * Np_pad + j]);
                     const bool amb = !(second > th + fabsf(th) * 1e-6f);
                     const size_t o = ((size_t)t * nwg + blockIdx.x) * Np_pad + j;
-                    cpart[o] = best;
+                    cpart[o] = lower_bf16_bits(best);
                     ctag[o] = (uint8_t)(bg | (amb ? 0x80 : 0));
                 }
             }
@@ -436,7 +482,7 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(
 constexpr int CMAXC = 6;
 constexpr int CREC_INTS = 1 + CMAXC + 1;
 
-constexpr int CM_TPT = 4;  // targets per thread in the column merge (one 16-byte load each)
+constexpr int CM_TPT = 4;  // targets per thread in the column merge (one 8-byte load each)
 
 __device__ __forceinline__ void colmerge_insert(float (&bv)[CMAXC + 1], int (&bw)[CMAXC + 1],
                                                 float v, int w) {
@@ -455,7 +501,7 @@ __device__ __forceinline__ void colmerge_insert(float (&bv)[CMAXC + 1], int (&bw
 }
 
 __global__ __launch_bounds__(256) void k_colmerge(const float *__restrict__ P, int Np, int Np_pad,
-                                                  int nwg, const float *__restrict__ cpart,
+                                                  int nwg, const uint16_t *__restrict__ cpart,
                                                   const uint8_t *__restrict__ ctag,
                                                   const float *__restrict__ nqmax,
                                                   int32_t *__restrict__ crec,
@@ -474,13 +520,13 @@ __global__ __launch_bounds__(256) void k_colmerge(const float *__restrict__ P, i
             bv[u][k] = inf;
             bw[u][k] = -1;
         }
-    const float *base = cpart + (size_t)t * nwg * Np_pad + j0;
+    const uint16_t *base = cpart + (size_t)t * nwg * Np_pad + j0;
     for (int w = 0; w < nwg; ++w) {
-        const float4 v = *reinterpret_cast<const float4 *>(base + (size_t)w * Np_pad);
-        colmerge_insert(bv[0], bw[0], v.x, w);
-        colmerge_insert(bv[1], bw[1], v.y, w);
-        colmerge_insert(bv[2], bw[2], v.z, w);
-        colmerge_insert(bv[3], bw[3], v.w, w);
+        const uint2 v = *reinterpret_cast<const uint2 *>(base + (size_t)w * Np_pad);
+        colmerge_insert(bv[0], bw[0], __uint_as_float(v.x << 16), w);
+        colmerge_insert(bv[1], bw[1], __uint_as_float(v.x & 0xFFFF0000u), w);
+        colmerge_insert(bv[2], bw[2], __uint_as_float(v.y << 16), w);
+        colmerge_insert(bv[3], bw[3], __uint_as_float(v.y & 0xFFFF0000u), w);
     }
     const float nqm = nqmax[t];
 #pragma unroll
@@ -489,7 +535,9 @@ __global__ __launch_bounds__(256) void k_colmerge(const float *__restrict__ P, i
         if (j >= Np) break;
         const float *pj = P + ((size_t)t * Np + j) * 3;
         const float np = norm2(pj[0], pj[1], pj[2]);
-        const float theta = threshold(bv[u][0], np, nqm);
+        // the partials are lower bounds within one bf16 step; the threshold is taken at an upper
+        // bound of the true minimum, and a workgroup is kept when its lower bound passes it
+        const float theta = threshold(bf16_step_up(bv[u][0]), np, nqm);
         const bool finite = __builtin_isfinite(bv[u][0]) && __builtin_isfinite(theta) &&
                             __builtin_isfinite(nqm) && bw[u][0] >= 0;
         int32_t *rr = crec + ((size_t)t * Np + j) * CREC_INTS;
@@ -699,7 +747,8 @@ size_t screen_scratch_bytes(int T, int Na, int Nb) {
            Arena::need((size_t)T * Na * REC_INTS, 4) +                // row records
            Arena::need((size_t)T * Nb * CREC_INTS, 4) +               // column records
            Arena::need((size_t)T * Nb_pad * 3, sizeof(bf16x8)) +      // packed b operands
-           Arena::need((size_t)T * nwg * Nb_pad, 4) +                 // column partial minima
+           Arena::need((size_t)T * Nb_pad, 4) +                       // their threshold slack
+           Arena::need((size_t)T * nwg * Nb_pad, 2) +                 // column partial minima
            Arena::need((size_t)T * nwg * Nb_pad, 1) +                 // their tags
            std::max(nn_exact_list_scratch_bytes(T, Na, Nb), nn_exact_list_scratch_bytes(T, Nb, Na));
 }
@@ -722,18 +771,19 @@ void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int
     int32_t *rec = ar.take<int32_t>((size_t)T * Na * REC_INTS);
     int32_t *crec = ar.take<int32_t>((size_t)T * Nb * CREC_INTS);
     bf16x8 *packed = ar.take<bf16x8>((size_t)T * Nb_pad * 3);
-    float *cpart = ar.take<float>((size_t)T * nwg * Nb_pad);
+    float *slack = ar.take<float>((size_t)T * Nb_pad);
+    uint16_t *cpart = ar.take<uint16_t>((size_t)T * nwg * Nb_pad);
     uint8_t *ctag = ar.take<uint8_t>((size_t)T * nwg * Nb_pad);
     char *exact_scratch = ar.take<char>(
         std::max(nn_exact_list_scratch_bytes(T, Na, Nb), nn_exact_list_scratch_bytes(T, Nb, Na)));
     hipLaunchKernelGGL(k_norm_max, dim3(T), dim3(256), 0, s, b, Nb, nbmax, hcnt_a);
     hipLaunchKernelGGL(k_norm_max, dim3(T), dim3(256), 0, s, a, Na, namax, hcnt_b);
     hipLaunchKernelGGL(k_pack_targets, dim3(Nb_pad / 256, T), dim3(256), 0, s, b, Nb, Nb_pad,
-                       packed);
+                       namax, packed, slack);
     {
         ProfScope ps(prof, 0, s);
-        hipLaunchKernelGGL(k_screen<true>, dim3(nwg, T), dim3(SC_THREADS), 0, s, a, Na, packed, b,
-                           Nb, Nb_pad, nbmax, namax, rec, hcnt_a, hlist_a, cpart, ctag);
+        hipLaunchKernelGGL(k_screen<true>, dim3(nwg, T), dim3(SC_THREADS), 0, s, a, Na, packed,
+                           slack, Nb, Nb_pad, nbmax, rec, hcnt_a, hlist_a, cpart, ctag);
     }
     {
         ProfScope ps(prof, 1, s);

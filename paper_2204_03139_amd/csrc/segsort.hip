@@ -79,28 +79,31 @@ __global__ __launch_bounds__(SB_THREADS) void k_ss_hist(SortIO io, int N, int sh
     counts[((size_t)t * BINS + threadIdx.x) * nblk + blk] = total[threadIdx.x];
 }
 
-// exclusive prefix over (digit, block) of one frame, in place
-__global__ __launch_bounds__(1024) void k_ss_scan(int32_t *__restrict__ counts, int nblk) {
-    __shared__ int part[1024];
+// exclusive prefix over (digit, block) of one frame, in place: each thread sums a contiguous run,
+// the runs' totals are scanned across the workgroup (in-wave shuffles, then the 16 wave totals),
+// and each thread rewrites its run from its exclusive start
+constexpr int SCAN_THREADS = 1024;
+__global__ __launch_bounds__(SCAN_THREADS) void k_ss_scan(int32_t *__restrict__ counts, int nblk) {
+    __shared__ int wsum[SCAN_THREADS / 64];
     const int t = blockIdx.x;
     int32_t *c = counts + (size_t)t * BINS * nblk;
     const int n = BINS * nblk;
-    const int per = (n + 1023) / 1024;
-    const int lo = threadIdx.x * per, hi = min(n, lo + per);
+    const int per = (n + SCAN_THREADS - 1) / SCAN_THREADS;
+    const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int s = 0;
     for (int k = lo; k < hi; ++k) s += c[k];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int k = 0; k < 1024; ++k) {
-            const int v = part[k];
-            part[k] = acc;
-            acc += v;
-        }
+    int incl = s;  // inclusive scan of the run totals inside the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
     }
+    if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    int acc = part[threadIdx.x];
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    int acc = before + incl - s;
     for (int k = lo; k < hi; ++k) {
         const int v = c[k];
         c[k] = acc;
@@ -186,7 +189,7 @@ void launch_segsort(const int32_t *keys, int T, int N, int key_limit, int32_t *o
         int32_t *dk = (p == passes - 1) ? out_keys : tk[p & 1];
         int32_t *dv = (p == passes - 1) ? out_vals : tv[p & 1];
         hipLaunchKernelGGL(k_ss_hist, grid, dim3(SB_THREADS), 0, s, io, N, 8 * p, nblk, counts);
-        hipLaunchKernelGGL(k_ss_scan, dim3(T), dim3(1024), 0, s, counts, nblk);
+        hipLaunchKernelGGL(k_ss_scan, dim3(T), dim3(SCAN_THREADS), 0, s, counts, nblk);
         hipLaunchKernelGGL(k_ss_scatter, grid, dim3(SB_THREADS), 0, s, io, N, 8 * p, nblk, counts,
                            dk, dv);
     }
