@@ -267,15 +267,26 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(
     // plus a compile-time offset.  K-chunk 3 is all zeros on the query side and is not stored.
     __shared__ bf16x8 stage[2][3][SC_ROWPAD * SC_TPS];
     __shared__ float colbuf[COLS ? SC_GROUPS : 1][16][CP_PAD];
-    const int t = blockIdx.y;
+    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs, so the ids of one
+    // XCD are mapped onto one contiguous range of (frame, row block) items; each XCD's L2 then
+    // holds the packed targets of about T/8 frames instead of every frame
+    const int nwg = gridDim.x;
+    int wgx, t;
+    {
+        const unsigned total = (unsigned)nwg * gridDim.y;
+        const unsigned id = blockIdx.x + (unsigned)nwg * blockIdx.y;
+        const unsigned c = id % 8u, k = id / 8u, per = total / 8u, rem = total % 8u;
+        const unsigned item = c * per + (c < rem ? c : rem) + k;
+        t = (int)(item / (unsigned)nwg);
+        wgx = (int)(item % (unsigned)nwg);
+    }
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4;   // K-chunk of the operands; row group of the result
     const int col = lane & 15; // row of the A operand; column (slot) of the result
     const float *Qt = Q + (size_t)t * Nq * 3;
     const bf16x8 *Bt = packed + (size_t)t * Np_pad * 3;
-    const int row0 = blockIdx.x * SC_ROWS + wave * (SC_ATILES * 16);
-    const int nwg = gridDim.x;
+    const int row0 = wgx * SC_ROWS + wave * (SC_ATILES * 16);
 
     // query operands, held for the whole sweep
     bf16x8 A[SC_ATILES];
@@ -422,7 +433,7 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(
                     // rescan every row of the workgroup for this target
                     const float th = threshold_affine(best, slack[(size_t)t * Np_pad + j]);
                     const bool amb = !(second > th + fabsf(th) * 1e-6f);
-                    const size_t o = ((size_t)t * nwg + blockIdx.x) * Np_pad + j;
+                    const size_t o = ((size_t)t * nwg + wgx) * Np_pad + j;
                     cpart[o] = lower_bf16_bits(best);
                     ctag[o] = (uint8_t)(bg | (amb ? 0x80 : 0));
                 }
