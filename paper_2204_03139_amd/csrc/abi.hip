@@ -5,12 +5,13 @@
 #include <new>
 #include <string>
 
-#include "dc_internal.h"
+#include "batch.h"
 #include "scheduler.h"
 
 namespace dc {
 
 static thread_local std::string g_err;
+thread_local Recording *g_record = nullptr;
 
 void set_error(const std::string &msg) { g_err = msg; }
 void clear_error() { g_err.clear(); }

@@ -2,7 +2,7 @@
 // the sampling gradient through Eq. 4 (Sec. III-B).  Both are gathers over segments built by the
 // stable atomic-free sort, summed in increasing index order, so every result is bitwise
 // reproducible and independent of scheduling.
-#include "dc_internal.h"
+#include "batch.h"
 
 namespace dc {
 namespace {
@@ -24,13 +24,32 @@ __device__ __forceinline__ int lower_bound(const int32_t *sorted, int n, int key
 
 // g_x[t,i] = g_t w_t ( cs * (x_i - y_{nn_x[i]}) + cm * sum_{j: nn_y[j]=i} (x_i - y_j) )
 // for x = a (cs = 2 alpha, cm = 2 beta) or x = b (cs = 2 beta, cm = 2 alpha).
-__global__ __launch_bounds__(BW_THREADS) void k_chamfer_bwd(
-    const double *__restrict__ grad_loss, const float *__restrict__ X, const float *__restrict__ Y,
-    const int32_t *__restrict__ nn_x, const int32_t *__restrict__ ykeys_sorted,
-    const int32_t *__restrict__ yvals_sorted, int Nx, int Ny, double cself, double cmutual,
-    const float *__restrict__ frame_w, float *__restrict__ gX) {
-    const int t = blockIdx.y;
-    const int i = blockIdx.x * BW_THREADS + threadIdx.x;
+struct ChamferBwdParams {
+    const double *grad_loss;
+    const float *X;
+    const float *Y;
+    const int32_t *nn_x;
+    const int32_t *ykeys_sorted;
+    const int32_t *yvals_sorted;
+    const float *frame_w;
+    float *gX;
+    double cself, cmutual;
+    int Nx, Ny;
+};
+
+__device__ __forceinline__ void chamfer_bwd_body(const ChamferBwdParams &pr, const Blk &blk) {
+    const double *__restrict__ grad_loss = pr.grad_loss;
+    const float *__restrict__ X = pr.X;
+    const float *__restrict__ Y = pr.Y;
+    const int32_t *__restrict__ nn_x = pr.nn_x;
+    const int32_t *__restrict__ ykeys_sorted = pr.ykeys_sorted;
+    const int32_t *__restrict__ yvals_sorted = pr.yvals_sorted;
+    const int Nx = pr.Nx, Ny = pr.Ny;
+    const double cself = pr.cself, cmutual = pr.cmutual;
+    const float *__restrict__ frame_w = pr.frame_w;
+    float *__restrict__ gX = pr.gX;
+    const int t = blk.y;
+    const int i = blk.x * BW_THREADS + threadIdx.x;
     if (i >= Nx) return;
     const double g = grad_loss[t] * (frame_w ? (double)frame_w[t] : 1.0);
     const float cs = (float)(cself * g);
@@ -67,23 +86,46 @@ __global__ __launch_bounds__(BW_THREADS) void k_chamfer_bwd(
     o[2] = g2;
 }
 
-// face_start[t][f] = first sorted position whose face is >= f, for f in [0, F]
-__global__ void k_bounds(const int32_t *__restrict__ sorted, int N, int K,
-                         int32_t *__restrict__ start) {
-    const int t = blockIdx.y;
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f > K) return;
-    start[(size_t)t * (K + 1) + f] = lower_bound(sorted + (size_t)t * N, N, f);
+__global__ __launch_bounds__(BW_THREADS) void k_chamfer_bwd(ChamferBwdParams p) {
+    chamfer_bwd_body(p, grid_blk());
 }
+
+// face_start[t][f] = first sorted position whose face is >= f, for f in [0, F]
+struct BoundsParams {
+    const int32_t *sorted;
+    int32_t *start;
+    int N, K;
+};
+
+__device__ __forceinline__ void bounds_body(const BoundsParams &p, const Blk &blk) {
+    const int t = blk.y;
+    const int f = blk.x * BW_THREADS + threadIdx.x;
+    if (f > p.K) return;
+    p.start[(size_t)t * (p.K + 1) + f] = lower_bound(p.sorted + (size_t)t * p.N, p.N, f);
+}
+
+__global__ __launch_bounds__(BW_THREADS) void k_bounds(BoundsParams p) { bounds_body(p, grid_blk()); }
 
 // per face and corner: fg[t,f,c] = sum over the points i of face f, in increasing i, of
 // bary[t,i,c] * g[t,i]
-__global__ __launch_bounds__(BW_THREADS) void k_face_grad(
-    const float *__restrict__ gpts, const float *__restrict__ bary,
-    const int32_t *__restrict__ pts_by_face, const int32_t *__restrict__ face_start, int F, int N,
-    float *__restrict__ fg) {
-    const int t = blockIdx.y;
-    const int f = blockIdx.x * BW_THREADS + threadIdx.x;
+struct FaceGradParams {
+    const float *gpts;
+    const float *bary;
+    const int32_t *pts_by_face;
+    const int32_t *face_start;
+    float *fg;
+    int F, N;
+};
+
+__device__ __forceinline__ void face_grad_body(const FaceGradParams &pr, const Blk &blk) {
+    const float *__restrict__ gpts = pr.gpts;
+    const float *__restrict__ bary = pr.bary;
+    const int32_t *__restrict__ pts_by_face = pr.pts_by_face;
+    const int32_t *__restrict__ face_start = pr.face_start;
+    const int F = pr.F, N = pr.N;
+    float *__restrict__ fg = pr.fg;
+    const int t = blk.y;
+    const int f = blk.x * BW_THREADS + threadIdx.x;
     if (f >= F) return;
     const int32_t *fs = face_start + (size_t)t * (F + 1);
     const int32_t *pf = pts_by_face + (size_t)t * N;
@@ -108,12 +150,27 @@ __global__ __launch_bounds__(BW_THREADS) void k_face_grad(
         for (int d = 0; d < 3; ++d) o[3 * c + d] = acc[c][d];
 }
 
+__global__ __launch_bounds__(BW_THREADS) void k_face_grad(FaceGradParams p) {
+    face_grad_body(p, grid_blk());
+}
+
 // grad_verts[t,v] = sum over the incident (face f, corner c), in increasing (f, c), of fg[t,f,c]
-__global__ __launch_bounds__(BW_THREADS) void k_vertex_grad(
-    const float *__restrict__ fg, const int32_t *__restrict__ corners_by_vertex,
-    const int32_t *__restrict__ vert_start, int V, int F, float *__restrict__ gverts) {
-    const int t = blockIdx.y;
-    const int v = blockIdx.x * BW_THREADS + threadIdx.x;
+struct VertexGradParams {
+    const float *fg;
+    const int32_t *corners_by_vertex;
+    const int32_t *vert_start;
+    float *gverts;
+    int V, F;
+};
+
+__device__ __forceinline__ void vertex_grad_body(const VertexGradParams &pr, const Blk &blk) {
+    const float *__restrict__ fg = pr.fg;
+    const int32_t *__restrict__ corners_by_vertex = pr.corners_by_vertex;
+    const int32_t *__restrict__ vert_start = pr.vert_start;
+    const int V = pr.V, F = pr.F;
+    float *__restrict__ gverts = pr.gverts;
+    const int t = blk.y;
+    const int v = blk.x * BW_THREADS + threadIdx.x;
     if (v >= V) return;
     const float *ft = fg + (size_t)t * F * 9;
     float a0 = 0.f, a1 = 0.f, a2 = 0.f;
@@ -127,6 +184,10 @@ __global__ __launch_bounds__(BW_THREADS) void k_vertex_grad(
     o[0] = a0;
     o[1] = a1;
     o[2] = a2;
+}
+
+__global__ __launch_bounds__(BW_THREADS) void k_vertex_grad(VertexGradParams p) {
+    vertex_grad_body(p, grid_blk());
 }
 
 }  // namespace
@@ -152,17 +213,41 @@ void launch_chamfer_bwd(const double *grad_loss, const float *a, const float *b,
     int32_t *vb = ar.take<int32_t>((size_t)T * Nb);
     char *ssb = ar.take<char>(segsort_scratch_bytes(T, Nb));
     if (beta != 0.0) launch_segsort(idx_b, T, Nb, Na, kb, vb, ssb, s);
-    hipLaunchKernelGGL(k_chamfer_bwd, dim3((Na + BW_THREADS - 1) / BW_THREADS, T),
-                       dim3(BW_THREADS), 0, s, grad_loss, a, b, idx_a, kb, vb, Na, Nb, 2.0 * alpha,
-                       2.0 * beta, frame_w, grad_a);
+    ChamferBwdParams cp;
+    cp.grad_loss = grad_loss;
+    cp.X = a;
+    cp.Y = b;
+    cp.nn_x = idx_a;
+    cp.ykeys_sorted = kb;
+    cp.yvals_sorted = vb;
+    cp.frame_w = frame_w;
+    cp.gX = grad_a;
+    cp.cself = 2.0 * alpha;
+    cp.cmutual = 2.0 * beta;
+    cp.Nx = Na;
+    cp.Ny = Nb;
+    dispatch(KT_CHAMFER_BWD, k_chamfer_bwd, dim3((Na + BW_THREADS - 1) / BW_THREADS, T),
+             BW_THREADS, cp, s);
     if (grad_b) {
         int32_t *ka = ar.take<int32_t>((size_t)T * Na);
         int32_t *va = ar.take<int32_t>((size_t)T * Na);
         char *ssa = ar.take<char>(segsort_scratch_bytes(T, Na));
         launch_segsort(idx_a, T, Na, Nb, ka, va, ssa, s);
-        hipLaunchKernelGGL(k_chamfer_bwd, dim3((Nb + BW_THREADS - 1) / BW_THREADS, T),
-                           dim3(BW_THREADS), 0, s, grad_loss, b, a, idx_b, ka, va, Nb, Na,
-                           2.0 * beta, 2.0 * alpha, frame_w, grad_b);
+        ChamferBwdParams cq;
+        cq.grad_loss = grad_loss;
+        cq.X = b;
+        cq.Y = a;
+        cq.nn_x = idx_b;
+        cq.ykeys_sorted = ka;
+        cq.yvals_sorted = va;
+        cq.frame_w = frame_w;
+        cq.gX = grad_b;
+        cq.cself = 2.0 * beta;
+        cq.cmutual = 2.0 * alpha;
+        cq.Nx = Nb;
+        cq.Ny = Na;
+        dispatch(KT_CHAMFER_BWD, k_chamfer_bwd, dim3((Nb + BW_THREADS - 1) / BW_THREADS, T),
+                 BW_THREADS, cq, s);
     }
 }
 
@@ -190,15 +275,45 @@ void launch_sample_bwd(const float *grad_points, const int32_t *faces, const int
     float *fg = ar.take<float>((size_t)T * F * 9);
     // points grouped by face (face -1 of a degenerate frame sorts last, as key F, and is unused)
     launch_segsort(face_idx, T, N, F, fk, fv, ss1, s);
-    hipLaunchKernelGGL(k_bounds, dim3((F + 1 + 255) / 256, T), dim3(256), 0, s, fk, N, F, fstart);
+    BoundsParams bp;
+    bp.sorted = fk;
+    bp.start = fstart;
+    bp.N = N;
+    bp.K = F;
+    dispatch(KT_BOUNDS, k_bounds, dim3((F + BW_THREADS) / BW_THREADS, T), BW_THREADS, bp, s);
     // (face, corner) slots grouped by vertex: the vertex-incidence CSR of the topology
     launch_segsort(faces, 1, 3 * F, V, ck, cv, ss2, s);
-    hipLaunchKernelGGL(k_bounds, dim3((V + 1 + 255) / 256, 1), dim3(256), 0, s, ck, 3 * F, V,
-                       vstart);
-    hipLaunchKernelGGL(k_face_grad, dim3((F + BW_THREADS - 1) / BW_THREADS, T), dim3(BW_THREADS),
-                       0, s, grad_points, bary, fv, fstart, F, N, fg);
-    hipLaunchKernelGGL(k_vertex_grad, dim3((V + BW_THREADS - 1) / BW_THREADS, T),
-                       dim3(BW_THREADS), 0, s, fg, cv, vstart, V, F, grad_verts);
+    bp.sorted = ck;
+    bp.start = vstart;
+    bp.N = 3 * F;
+    bp.K = V;
+    dispatch(KT_BOUNDS, k_bounds, dim3((V + BW_THREADS) / BW_THREADS, 1), BW_THREADS, bp, s);
+    FaceGradParams fp;
+    fp.gpts = grad_points;
+    fp.bary = bary;
+    fp.pts_by_face = fv;
+    fp.face_start = fstart;
+    fp.fg = fg;
+    fp.F = F;
+    fp.N = N;
+    dispatch(KT_FACE_GRAD, k_face_grad, dim3((F + BW_THREADS - 1) / BW_THREADS, T), BW_THREADS, fp,
+             s);
+    VertexGradParams vp;
+    vp.fg = fg;
+    vp.corners_by_vertex = cv;
+    vp.vert_start = vstart;
+    vp.gverts = grad_verts;
+    vp.V = V;
+    vp.F = F;
+    dispatch(KT_VERTEX_GRAD, k_vertex_grad, dim3((V + BW_THREADS - 1) / BW_THREADS, T), BW_THREADS,
+             vp, s);
+}
+
+void register_backward_kernels(BatchedKernel *table) {
+    table[KT_CHAMFER_BWD] = batched_kernel<ChamferBwdParams, chamfer_bwd_body, BW_THREADS, 1024>();
+    table[KT_BOUNDS] = batched_kernel<BoundsParams, bounds_body, BW_THREADS, 512>();
+    table[KT_FACE_GRAD] = batched_kernel<FaceGradParams, face_grad_body, BW_THREADS, 1024>();
+    table[KT_VERTEX_GRAD] = batched_kernel<VertexGradParams, vertex_grad_body, BW_THREADS, 1024>();
 }
 
 }  // namespace dc

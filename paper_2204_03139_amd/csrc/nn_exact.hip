@@ -10,7 +10,7 @@
 // index among the exact ties, so the result is the exact argmin with the smallest-index rule.
 // Large frames split the target range over grid.z slices; a merge kernel combines the slices in
 // slice order with the same strict-less rule.
-#include "dc_internal.h"
+#include "batch.h"
 
 namespace dc {
 namespace {
@@ -29,25 +29,38 @@ __device__ __forceinline__ float canon_d2(float qx, float qy, float qz, float px
 
 // qlist/qcount (optional): per frame, only the queries qlist[t*Nq + k], k < qcount[t], are
 // searched; slice partials are then indexed by k and the merge maps them back to the rows.
+struct NNParams {
+    const float *Q;
+    const float *P;
+    int32_t *idx;
+    float *dist;
+    const int32_t *qlist;
+    const int32_t *qcount;
+    size_t slice_stride;
+    int Nq, Np, slice_len;
+};
+
 template <int QPT>
-__global__ __launch_bounds__(NN_THREADS) void k_nn_exact(const float *__restrict__ Q, int Nq,
-                                                         const float *__restrict__ P, int Np,
-                                                         int slice_len, int32_t *__restrict__ idx,
-                                                         float *__restrict__ dist,
-                                                         size_t slice_stride,
-                                                         const int32_t *__restrict__ qlist,
-                                                         const int32_t *__restrict__ qcount) {
+__device__ __forceinline__ void nn_exact_body(const NNParams &pr, const Blk &blk) {
+    const float *__restrict__ Q = pr.Q;
+    const float *__restrict__ P = pr.P;
+    const int Nq = pr.Nq, Np = pr.Np, slice_len = pr.slice_len;
+    int32_t *__restrict__ idx = pr.idx;
+    float *__restrict__ dist = pr.dist;
+    const size_t slice_stride = pr.slice_stride;
+    const int32_t *__restrict__ qlist = pr.qlist;
+    const int32_t *__restrict__ qcount = pr.qcount;
     __shared__ float4 tile[NN_TILE];
-    const int t = blockIdx.y;
-    const int z = blockIdx.z;
+    const int t = blk.y;
+    const int z = blk.z;
     const int nq_live = qlist ? qcount[t] : Nq;
     const float *Qt = Q + (size_t)t * Nq * 3;
     const float *Pt = P + (size_t)t * Np * 3;
     const int j_begin = z * slice_len;
     const int j_end = min(Np, j_begin + slice_len);
     // the list of a frame is short and its length only known on the device: each workgroup
-    // walks query blocks blockIdx.x, blockIdx.x + gridDim.x, ... (one step without a list)
-    for (int qb = blockIdx.x; qb * NN_THREADS * QPT < nq_live; qb += gridDim.x) {
+    // walks query blocks x, x + gx, ... of its logical grid (one step without a list)
+    for (int qb = blk.x; qb * NN_THREADS * QPT < nq_live; qb += blk.gx) {
     const int q0 = qb * NN_THREADS * QPT + threadIdx.x;
 
     float qx[QPT], qy[QPT], qz[QPT], best[QPT];
@@ -134,14 +147,35 @@ __global__ __launch_bounds__(NN_THREADS) void k_nn_exact(const float *__restrict
     }
 }
 
+template <int QPT>
+__global__ __launch_bounds__(NN_THREADS) void k_nn_exact(NNParams p) {
+    nn_exact_body<QPT>(p, grid_blk());
+}
+
 // combine per-slice winners; slices hold increasing index ranges, so strict-less keeps the
 // smallest index among equal distances.  With a query list, position k of frame t goes back to
 // row qlist[t*Nq + k].
-__global__ void k_nn_merge(const int32_t *__restrict__ pidx, const float *__restrict__ pdist,
-                           int slices, size_t slice_stride, int Nq, int T,
-                           int32_t *__restrict__ idx, float *__restrict__ dist,
-                           const int32_t *__restrict__ qlist, const int32_t *__restrict__ qcount) {
-    const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+struct NNMergeParams {
+    const int32_t *pidx;
+    const float *pdist;
+    int32_t *idx;
+    float *dist;
+    const int32_t *qlist;
+    const int32_t *qcount;
+    size_t slice_stride;
+    int slices, Nq, T;
+};
+
+constexpr int MERGE_THREADS = 256;
+
+__device__ __forceinline__ void nn_merge_body(const NNMergeParams &pr, const Blk &blk) {
+    const int32_t *__restrict__ pidx = pr.pidx;
+    const float *__restrict__ pdist = pr.pdist;
+    const int slices = pr.slices, Nq = pr.Nq, T = pr.T;
+    const size_t slice_stride = pr.slice_stride;
+    const int32_t *__restrict__ qlist = pr.qlist;
+    const int32_t *__restrict__ qcount = pr.qcount;
+    const size_t o = (size_t)blk.x * MERGE_THREADS + threadIdx.x;
     if (o >= (size_t)T * Nq) return;
     const int t = (int)(o / Nq);
     const int k = (int)(o - (size_t)t * Nq);
@@ -156,20 +190,33 @@ __global__ void k_nn_merge(const int32_t *__restrict__ pidx, const float *__rest
         }
     }
     const size_t out = qlist ? (size_t)t * Nq + qlist[o] : o;
-    idx[out] = bi;
-    dist[out] = b;
+    pr.idx[out] = bi;
+    pr.dist[out] = b;
+}
+
+__global__ __launch_bounds__(MERGE_THREADS) void k_nn_merge(NNMergeParams p) {
+    nn_merge_body(p, grid_blk());
 }
 
 constexpr int LOSS_THREADS = 256;
 
+struct LossParams {
+    const float *da;
+    const float *db;
+    const float *frame_w;
+    double *loss;
+    double alpha, beta;
+    int Na, Nb;
+};
+
 // loss[t] = w_t (alpha sum_i dist_a + beta sum_j dist_b), in double, in a fixed order
-__global__ __launch_bounds__(LOSS_THREADS) void k_loss(const float *__restrict__ da,
-                                                       const float *__restrict__ db, int Na,
-                                                       int Nb, double alpha, double beta,
-                                                       const float *__restrict__ frame_w,
-                                                       double *__restrict__ loss) {
+__device__ __forceinline__ void loss_body(const LossParams &p, const Blk &blk) {
+    const float *__restrict__ da = p.da;
+    const float *__restrict__ db = p.db;
+    const int Na = p.Na, Nb = p.Nb;
+    const double alpha = p.alpha, beta = p.beta;
     __shared__ double sa[LOSS_THREADS], sb[LOSS_THREADS];
-    const int t = blockIdx.x;
+    const int t = blk.x;
     double xa = 0.0, xb = 0.0;
     for (int i = threadIdx.x; i < Na; i += LOSS_THREADS) xa += (double)da[(size_t)t * Na + i];
     if (beta != 0.0)
@@ -185,10 +232,12 @@ __global__ __launch_bounds__(LOSS_THREADS) void k_loss(const float *__restrict__
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const double w = frame_w ? (double)frame_w[t] : 1.0;
-        loss[t] = w * (alpha * sa[0] + beta * sb[0]);
+        const double w = p.frame_w ? (double)p.frame_w[t] : 1.0;
+        p.loss[t] = w * (alpha * sa[0] + beta * sb[0]);
     }
 }
+
+__global__ __launch_bounds__(LOSS_THREADS) void k_loss(LossParams p) { loss_body(p, grid_blk()); }
 
 }  // namespace
 
@@ -224,19 +273,38 @@ static void launch_nn_exact_impl(const float *Q, int Nq, const float *P, int Np,
     const size_t kstride = s > 1 ? stride : 0;
     const int qblocks = (Nq + NN_THREADS * qpt - 1) / (NN_THREADS * qpt);
     const dim3 grid(qlist ? 1 : qblocks, T, s);
+    NNParams np;
+    np.Q = Q;
+    np.P = P;
+    np.idx = pidx;
+    np.dist = pdist;
+    np.qlist = qlist;
+    np.qcount = qcount;
+    np.slice_stride = kstride;
+    np.Nq = Nq;
+    np.Np = Np;
+    np.slice_len = slice_len;
     if (qpt == 8)
-        hipLaunchKernelGGL(k_nn_exact<8>, grid, dim3(NN_THREADS), 0, st, Q, Nq, P, Np, slice_len,
-                           pidx, pdist, kstride, qlist, qcount);
+        dispatch(KT_NN8, k_nn_exact<8>, grid, NN_THREADS, np, st);
     else if (qpt == 4)
-        hipLaunchKernelGGL(k_nn_exact<4>, grid, dim3(NN_THREADS), 0, st, Q, Nq, P, Np, slice_len,
-                           pidx, pdist, kstride, qlist, qcount);
+        dispatch(KT_NN4, k_nn_exact<4>, grid, NN_THREADS, np, st);
     else
-        hipLaunchKernelGGL(k_nn_exact<1>, grid, dim3(NN_THREADS), 0, st, Q, Nq, P, Np, slice_len,
-                           pidx, pdist, kstride, qlist, qcount);
+        dispatch(KT_NN1, k_nn_exact<1>, grid, NN_THREADS, np, st);
     if (s > 1) {
         const size_t total = (size_t)T * Nq;
-        hipLaunchKernelGGL(k_nn_merge, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                           pidx, pdist, s, stride, Nq, T, idx, dist, qlist, qcount);
+        NNMergeParams mp;
+        mp.pidx = pidx;
+        mp.pdist = pdist;
+        mp.idx = idx;
+        mp.dist = dist;
+        mp.qlist = qlist;
+        mp.qcount = qcount;
+        mp.slice_stride = stride;
+        mp.slices = s;
+        mp.Nq = Nq;
+        mp.T = T;
+        dispatch(KT_NN_MERGE, k_nn_merge, dim3((unsigned)((total + MERGE_THREADS - 1) / MERGE_THREADS)),
+                 MERGE_THREADS, mp, st);
     }
 }
 
@@ -272,8 +340,24 @@ void launch_loss(const float *dist_a, const float *dist_b, int T, int Na, int Nb
                  const float *frame_w, double *loss, hipStream_t s) {
     const double alpha = reduction == DC_RED_SIM2REAL_SUM ? 1.0 : 1.0 / (double)Na;
     const double beta = reduction == DC_RED_SIM2REAL_SUM ? 0.0 : 1.0 / (double)Nb;
-    hipLaunchKernelGGL(k_loss, dim3(T), dim3(LOSS_THREADS), 0, s, dist_a, dist_b, Na, Nb, alpha,
-                       beta, frame_w, loss);
+    LossParams lp;
+    lp.da = dist_a;
+    lp.db = dist_b;
+    lp.frame_w = frame_w;
+    lp.loss = loss;
+    lp.alpha = alpha;
+    lp.beta = beta;
+    lp.Na = Na;
+    lp.Nb = Nb;
+    dispatch(KT_LOSS, k_loss, dim3(T), LOSS_THREADS, lp, s);
+}
+
+void register_nn_kernels(BatchedKernel *table) {
+    table[KT_NN1] = batched_kernel<NNParams, nn_exact_body<1>, NN_THREADS, 2048>();
+    table[KT_NN4] = batched_kernel<NNParams, nn_exact_body<4>, NN_THREADS, 2048>();
+    table[KT_NN8] = batched_kernel<NNParams, nn_exact_body<8>, NN_THREADS, 2048>();
+    table[KT_NN_MERGE] = batched_kernel<NNMergeParams, nn_merge_body, MERGE_THREADS, 512>();
+    table[KT_LOSS] = batched_kernel<LossParams, loss_body, LOSS_THREADS, 512>();
 }
 
 }  // namespace dc

@@ -7,7 +7,7 @@
 //   k_sample     one lane per point: random words (given, or Philox4x64-10), inverse-CDF face
 //                choice by an upper-bound binary search, barycentric point in float.
 // Built with -ffp-contract=off: only the fma calls written out below are fused.
-#include "dc_internal.h"
+#include "batch.h"
 
 namespace dc {
 namespace {
@@ -34,18 +34,26 @@ __device__ __forceinline__ double tri_area_f64(const float *p1, const float *p2,
     return 0.5 * __builtin_sqrt(sq);
 }
 
-__global__ __launch_bounds__(AC_THREADS) void k_area_cdf(const float *__restrict__ verts,
-                                                         const int32_t *__restrict__ faces, int V,
-                                                         int F, double *__restrict__ cdf,
-                                                         int32_t *__restrict__ lastpos,
-                                                         unsigned *__restrict__ status) {
+struct AreaCdfParams {
+    const float *verts;
+    const int32_t *faces;
+    int V, F;
+    double *cdf;
+    int32_t *lastpos;
+    unsigned *status;
+};
+
+__device__ __forceinline__ void area_cdf_body(const AreaCdfParams &p, const Blk &blk) {
+    const float *__restrict__ verts = p.verts;
+    const int32_t *__restrict__ faces = p.faces;
+    const int V = p.V, F = p.F;
     __shared__ double area[AC_CHUNK];  // areas, overwritten in place by the running sums
     __shared__ int bad;
     __shared__ int lastw[AC_THREADS / 64];
     __shared__ double carry;
-    const int t = blockIdx.x;
+    const int t = blk.x;
     const float *vt = verts + (size_t)t * V * 3;
-    double *ct = cdf + (size_t)t * F;
+    double *ct = p.cdf + (size_t)t * F;
     if (threadIdx.x == 0) {
         bad = 0;
         carry = 0.0;
@@ -87,10 +95,14 @@ __global__ __launch_bounds__(AC_THREADS) void k_area_cdf(const float *__restrict
         for (int w = 0; w < AC_THREADS / 64; ++w) last = max(last, lastw[w]);
         const double run = carry;
         const bool degenerate = !(run > 0.0) || !__builtin_isfinite(run);
-        lastpos[t] = (degenerate || bad) ? -1 : last;
-        if (bad) atomicOr(status, (unsigned)ST_BAD_FACE);
-        if (degenerate) atomicOr(status, (unsigned)ST_DEGENERATE);
+        p.lastpos[t] = (degenerate || bad) ? -1 : last;
+        if (bad) atomicOr(p.status, (unsigned)ST_BAD_FACE);
+        if (degenerate) atomicOr(p.status, (unsigned)ST_DEGENERATE);
     }
+}
+
+__global__ __launch_bounds__(AC_THREADS) void k_area_cdf(AreaCdfParams p) {
+    area_cdf_body(p, grid_blk());
 }
 
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 64x64->128 products
@@ -126,16 +138,33 @@ __device__ __forceinline__ Words4 philox_words(uint64_t seed, uint32_t t, uint32
 
 constexpr int SP_THREADS = 256;
 
-__global__ __launch_bounds__(SP_THREADS) void k_sample(
-    const float *__restrict__ verts, const int32_t *__restrict__ faces, int V, int F, int N,
-    uint64_t seed, const uint32_t *__restrict__ uniforms, const double *__restrict__ cdf,
-    const int32_t *__restrict__ lastpos, float *__restrict__ points, int32_t *__restrict__ face_idx,
-    float *__restrict__ bary) {
-    const int t = blockIdx.y;
-    const int i = blockIdx.x * SP_THREADS + threadIdx.x;
+struct SampleParams {
+    const float *verts;
+    const int32_t *faces;
+    int V, F, N;
+    uint64_t seed;
+    const uint32_t *uniforms;
+    const double *cdf;
+    const int32_t *lastpos;
+    float *points;
+    int32_t *face_idx;
+    float *bary;
+};
+
+__device__ __forceinline__ void sample_body(const SampleParams &pr, const Blk &blk) {
+    const float *__restrict__ verts = pr.verts;
+    const int32_t *__restrict__ faces = pr.faces;
+    const int V = pr.V, F = pr.F, N = pr.N;
+    const uint32_t *__restrict__ uniforms = pr.uniforms;
+    const double *__restrict__ cdf = pr.cdf;
+    float *__restrict__ points = pr.points;
+    int32_t *__restrict__ face_idx = pr.face_idx;
+    float *__restrict__ bary = pr.bary;
+    const int t = blk.y;
+    const int i = blk.x * SP_THREADS + threadIdx.x;
     if (i >= N) return;
     const size_t o = (size_t)t * N + i;
-    const int lp = lastpos[t];
+    const int lp = pr.lastpos[t];
     if (lp < 0) {  // degenerate frame or bad faces: reported through the status word
         const float nan = __builtin_nanf("");
         points[3 * o] = nan;
@@ -155,7 +184,7 @@ __global__ __launch_bounds__(SP_THREADS) void k_sample(
         w.w2 = u.z;
         w.w3 = u.w;
     } else {
-        w = philox_words(seed, (uint32_t)t, (uint32_t)i);
+        w = philox_words(pr.seed, (uint32_t)t, (uint32_t)i);
     }
     // inverse CDF: first k with C_k > r * S
     const double *ct = cdf + (size_t)t * F;
@@ -192,6 +221,8 @@ __global__ __launch_bounds__(SP_THREADS) void k_sample(
     face_idx[o] = f;
 }
 
+__global__ __launch_bounds__(SP_THREADS) void k_sample(SampleParams p) { sample_body(p, grid_blk()); }
+
 }  // namespace
 
 size_t sample_scratch_bytes(int T, int F) {
@@ -202,11 +233,34 @@ void launch_sample(const float *verts, const int32_t *faces, int T, int V, int F
                    uint64_t seed, const uint32_t *uniforms, float *points, int32_t *face_idx,
                    float *bary, double *cdf_scratch, int32_t *lastpos_scratch, unsigned *status,
                    hipStream_t s) {
-    hipLaunchKernelGGL(k_area_cdf, dim3(T), dim3(AC_THREADS), 0, s, verts, faces, V, F,
-                       cdf_scratch, lastpos_scratch, status);
-    dim3 grid((N + SP_THREADS - 1) / SP_THREADS, T);
-    hipLaunchKernelGGL(k_sample, grid, dim3(SP_THREADS), 0, s, verts, faces, V, F, N, seed,
-                       uniforms, cdf_scratch, lastpos_scratch, points, face_idx, bary);
+    AreaCdfParams ap;
+    ap.verts = verts;
+    ap.faces = faces;
+    ap.V = V;
+    ap.F = F;
+    ap.cdf = cdf_scratch;
+    ap.lastpos = lastpos_scratch;
+    ap.status = status;
+    dispatch(KT_AREA_CDF, k_area_cdf, dim3(T), AC_THREADS, ap, s);
+    SampleParams sp;
+    sp.verts = verts;
+    sp.faces = faces;
+    sp.V = V;
+    sp.F = F;
+    sp.N = N;
+    sp.seed = seed;
+    sp.uniforms = uniforms;
+    sp.cdf = cdf_scratch;
+    sp.lastpos = lastpos_scratch;
+    sp.points = points;
+    sp.face_idx = face_idx;
+    sp.bary = bary;
+    dispatch(KT_SAMPLE, k_sample, dim3((N + SP_THREADS - 1) / SP_THREADS, T), SP_THREADS, sp, s);
+}
+
+void register_sample_kernels(BatchedKernel *table) {
+    table[KT_AREA_CDF] = batched_kernel<AreaCdfParams, area_cdf_body, AC_THREADS, 256>();
+    table[KT_SAMPLE] = batched_kernel<SampleParams, sample_body, SP_THREADS, 1024>();
 }
 
 }  // namespace dc

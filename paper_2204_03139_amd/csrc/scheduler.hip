@@ -1,13 +1,20 @@
-// Serving loop: continuous admission of calibration requests under an HBM budget.
+// Serving loop: continuous batching of calibration requests under an HBM budget, replayed as
+// captured graphs of persistent kernels.
 //
-// dc_submit copies a request's host inputs and queues it.  A scheduler thread admits queued
-// requests in arrival order whenever a slot is free and the request's device footprint fits
-// under the budget, uploads its inputs, and enqueues its whole pipeline (sampling, Chamfer
-// forward, Chamfer backward, sampling backward, result download) on one of several streams, so
-// requests admitted while others run overlap on the device.  Completion is detected with events;
-// device memory then returns to the budget and dc_poll reports the result.  A request's work is
-// enqueued with exactly the same launches as when it runs alone, so its results do not depend on
-// what else is in flight.
+// dc_submit copies a request's host inputs and queues it.  A scheduler thread forms batches from
+// the queue in arrival order (at most MAX_BATCH requests, a bounded amount of pair work, the
+// context's slot limit and its HBM budget), and runs each batch on one of NSLOTS batch slots, so
+// requests that arrive while others are on the device are admitted into the next free slot and
+// their work overlaps with the batches already running.
+//
+// A batch runs as one replay of a graph built once per slot: the fixed program below, one
+// persistent kernel node per stage, with the stages that have no work in the batch switched off.  For every request the host code of the direct calls is run in
+// recording mode, which yields the request's launches (kernel, logical grid, parameters) instead
+// of executing them; each launch is assigned, in order, to the next program stage of its kernel,
+// and the batch's stage tables are uploaded to the slot's device descriptor before the replay.
+// Inputs are uploaded from pinned staging in one copy per request, results come back the same
+// way, and an event marks the batch's completion.  Every request executes exactly the launches
+// of its direct calls, so its results do not depend on what it is batched with.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -16,27 +23,87 @@
 #include <unordered_map>
 #include <vector>
 
+#include "batch.h"
 #include "scheduler.h"
 
 namespace dc {
 namespace {
 
-constexpr int NSTREAMS = 4;
+constexpr int NSLOTS = 3;              // batches in flight
+constexpr double BATCH_PAIRS = 5e9;    // pair work that closes a batch (about 0.5 ms of device time)
+constexpr int FILL_THREADS = 256;
 
 double now_s() {
     using namespace std::chrono;
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-__global__ void k_fill_f64(double *p, int n, double v) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+struct FillU32Params {
+    unsigned *p;
+    int n;
+    unsigned v;
+};
+
+struct FillF64Params {
+    double *p;
+    double v;
+    int n;
+    int pad;
+};
+
+__device__ __forceinline__ void fill_u32_body(const FillU32Params &q, const Blk &b) {
+    const int i = b.x * FILL_THREADS + threadIdx.x;
+    if (i < q.n) q.p[i] = q.v;
 }
 
-__global__ void k_fill_u32(unsigned *p, int n, unsigned v) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+__device__ __forceinline__ void fill_f64_body(const FillF64Params &q, const Blk &b) {
+    const int i = b.x * FILL_THREADS + threadIdx.x;
+    if (i < q.n) q.p[i] = q.v;
 }
+
+__global__ __launch_bounds__(FILL_THREADS) void k_fill_u32(FillU32Params q) {
+    fill_u32_body(q, grid_blk());
+}
+
+__global__ __launch_bounds__(FILL_THREADS) void k_fill_f64(FillF64Params q) {
+    fill_f64_body(q, grid_blk());
+}
+
+void fill_u32(unsigned *p, int n, unsigned v, hipStream_t s) {
+    FillU32Params q;
+    q.p = p;
+    q.n = n;
+    q.v = v;
+    dispatch(KT_FILL_U32, k_fill_u32, dim3((n + FILL_THREADS - 1) / FILL_THREADS), FILL_THREADS, q,
+             s);
+}
+
+void fill_f64(double *p, int n, double v, hipStream_t s) {
+    FillF64Params q;
+    q.p = p;
+    q.v = v;
+    q.n = n;
+    q.pad = 0;
+    dispatch(KT_FILL_F64, k_fill_f64, dim3((n + FILL_THREADS - 1) / FILL_THREADS), FILL_THREADS, q,
+             s);
+}
+
+// The serving program: every request's recorded launches form a subsequence of it.  Exact
+// searches may use any of the three queries-per-lane variants; each sort has room for four
+// 8-bit digit passes (keys below 2^32).
+#define SORT_PASSES                                                                           \
+    KT_SS_HIST, KT_SS_SCAN, KT_SS_SCATTER, KT_SS_HIST, KT_SS_SCAN, KT_SS_SCATTER, KT_SS_HIST, \
+        KT_SS_SCAN, KT_SS_SCATTER, KT_SS_HIST, KT_SS_SCAN, KT_SS_SCATTER
+const int PROGRAM[] = {
+    KT_FILL_U32,  KT_AREA_CDF, KT_SAMPLE,                                      // sampling
+    KT_NORM_MAX,  KT_NORM_MAX, KT_PACK,     KT_SCREEN, KT_REFINE, KT_COLMERGE,  // screen
+    KT_COLREFINE, KT_NN8,      KT_NN4,      KT_NN1,    KT_NN_MERGE,            // exact a -> b
+    KT_NN8,       KT_NN4,      KT_NN1,      KT_NN_MERGE,                       // exact b -> a
+    KT_LOSS,      KT_FILL_F64, SORT_PASSES, KT_CHAMFER_BWD,                    // Chamfer bwd
+    SORT_PASSES,  KT_BOUNDS,   SORT_PASSES, KT_BOUNDS,  KT_FACE_GRAD, KT_VERTEX_GRAD};
+#undef SORT_PASSES
+constexpr int NPROG = (int)(sizeof(PROGRAM) / sizeof(PROGRAM[0]));
+static_assert(NPROG <= MAX_STAGES, "program longer than the descriptor");
 
 enum { Q_QUEUED = 0, Q_RUNNING = 1, Q_DONE = 2 };
 
@@ -49,39 +116,26 @@ struct Req {
     std::vector<float> verts, obs, fw;
     std::vector<int32_t> faces;
     size_t bytes = 0;
-    char *dmem = nullptr;
-    int slot = -1;
-    int stream = 0;
-    hipEvent_t ev = nullptr;
+    double pairs = 0;
     int state = Q_QUEUED;
     int status = DC_OK;
+    // within the batch
+    size_t dev_off = 0, in_off = 0, out_off = 0;
+    std::vector<OpRec> ops;
+    std::vector<int> stage_of;
 };
 
-// pinned host staging for results, one per slot, grown on demand
-struct Slot {
-    char *host = nullptr;
-    size_t cap = 0;
-    bool busy = false;
+// device pieces of one request, carved from its region: inputs, then outputs, then the rest
+struct Layout {
+    float *verts, *obs, *fw, *pts, *bary, *da, *db, *gpts, *gverts;
+    int32_t *faces, *fidx, *ia, *ib;
+    double *loss, *gl;
+    unsigned *status;
+    char *scratch;
+    size_t in_bytes, out_bytes;
 };
 
-}  // namespace
-
-struct Scheduler {
-    dc_ctx *ctx = nullptr;
-    std::mutex mu;
-    std::condition_variable cv;
-    std::deque<Req *> queue;
-    std::vector<Req *> running;
-    std::unordered_map<uint64_t, Req *> table;
-    std::vector<Slot> slots;
-    uint64_t next_ticket = 1;
-    bool stop = false;
-    hipStream_t streams[NSTREAMS] = {};
-    int rr = 0;
-    std::thread th;
-};
-
-static size_t scratch_bytes(int T, int V, int F, int Na, int Nb, int precision, bool want_grad) {
+size_t scratch_bytes(int T, int V, int F, int Na, int Nb, int precision, bool want_grad) {
     size_t s = sample_scratch_bytes(T, F);
     s = std::max(s, chamfer_fwd_scratch_bytes(T, Na, Nb, precision));
     if (want_grad) {
@@ -90,6 +144,130 @@ static size_t scratch_bytes(int T, int V, int F, int Na, int Nb, int precision, 
     }
     return s;
 }
+
+Layout carve(const Req *r, char *base) {
+    Arena ar;
+    ar.base = base;
+    ar.cap = r->bytes;
+    const int T = r->T, V = r->V, F = r->F, Na = r->Na, Nb = r->Nb;
+    const size_t TV = (size_t)T * V, TA = (size_t)T * Na, TB = (size_t)T * Nb;
+    Layout L;
+    L.verts = ar.take<float>(TV * 3);
+    L.faces = ar.take<int32_t>((size_t)F * 3);
+    L.obs = ar.take<float>(TB * 3);
+    L.fw = ar.take<float>(T);
+    L.in_bytes = ar.off;
+    L.loss = ar.take<double>(T);
+    L.status = ar.take<unsigned>(4);
+    L.gverts = r->want_grad ? ar.take<float>(TV * 3) : nullptr;
+    L.out_bytes = ar.off - L.in_bytes;
+    L.pts = ar.take<float>(TA * 3);
+    L.bary = ar.take<float>(TA * 3);
+    L.fidx = ar.take<int32_t>(TA);
+    L.da = ar.take<float>(TA);
+    L.ia = ar.take<int32_t>(TA);
+    L.db = ar.take<float>(TB);
+    L.ib = ar.take<int32_t>(TB);
+    L.gl = r->want_grad ? ar.take<double>(T) : nullptr;
+    L.gpts = r->want_grad ? ar.take<float>(TA * 3) : nullptr;
+    L.scratch = ar.take<char>(scratch_bytes(T, V, F, Na, Nb, r->precision, r->want_grad));
+    return L;
+}
+
+// the launches of a request's whole pipeline, issued through dispatch()
+int issue_request(const Req *r, const Layout &L, unsigned long long *stats) {
+    const int T = r->T, V = r->V, F = r->F, Na = r->Na, Nb = r->Nb;
+    hipStream_t s = nullptr;  // unused while recording
+    fill_u32(L.status, 4, 0u, s);
+    Arena sar;
+    sar.base = L.scratch;
+    sar.cap = r->bytes;
+    int rc = enqueue_sample(nullptr, L.verts, L.faces, T, V, F, Na, r->seed, nullptr, L.pts,
+                            L.fidx, L.bary, sar, L.status, s);
+    if (rc) return rc;
+    rc = enqueue_chamfer_fwd(nullptr, L.pts, L.obs, T, Na, Nb, r->precision, r->reduction,
+                             r->has_w ? L.fw : nullptr, L.da, L.ia, L.db, L.ib, L.loss, L.scratch,
+                             stats, s);
+    if (rc) return rc;
+    if (r->want_grad) {
+        fill_f64(L.gl, T, 1.0, s);
+        launch_chamfer_bwd(L.gl, L.pts, L.obs, L.ia, L.ib, T, Na, Nb, r->reduction,
+                           r->has_w ? L.fw : nullptr, L.gpts, nullptr, L.scratch, s);
+        launch_sample_bwd(L.gpts, L.faces, L.fidx, L.bary, T, V, F, Na, L.gverts, L.scratch, s);
+    }
+    return DC_OK;
+}
+
+// record a request's launches against a region at `base` and assign them to program stages
+int plan_request(Req *r, char *base, unsigned long long *stats) {
+    Recording rec;
+    g_record = &rec;
+    const Layout L = carve(r, base);
+    const int rc = issue_request(r, L, stats);
+    g_record = nullptr;
+    if (rc) return rc;
+    r->ops.swap(rec.ops);
+    r->stage_of.assign(r->ops.size(), -1);
+    int pos = 0;
+    for (size_t k = 0; k < r->ops.size(); ++k) {
+        while (pos < NPROG && PROGRAM[pos] != rec.types[k]) ++pos;
+        const long items = (long)r->ops[k].gx * r->ops[k].gy * r->ops[k].gz;
+        if (pos == NPROG || items > (1L << 26)) {
+            set_error("request does not fit the serving program");
+            return DC_ERR_UNSUPPORTED;
+        }
+        r->stage_of[k] = pos++;
+    }
+    return DC_OK;
+}
+
+// one batch slot: a stream, the captured program over the slot's descriptor, pinned staging
+struct BatchSlot {
+    hipStream_t stream = nullptr;
+    BatchDesc *d_desc = nullptr;
+    BatchDesc *h_desc = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t nodes[MAX_STAGES] = {};
+    bool enabled[MAX_STAGES] = {};
+    char *h_in = nullptr, *h_out = nullptr;
+    size_t in_cap = 0, out_cap = 0;
+    char *dmem = nullptr;
+    hipEvent_t ev = nullptr;
+    std::vector<Req *> reqs;
+    bool busy = false;
+};
+
+int grow_pinned(char **p, size_t *cap, size_t need) {
+    if (*cap >= need) return DC_OK;
+    if (*p) (void)hipHostFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    const size_t n = std::max(need, (size_t)1 << 20) * 5 / 4;
+    if (hipHostMalloc(reinterpret_cast<void **>(p), n, 0) != hipSuccess) {
+        *p = nullptr;
+        set_error("pinned staging allocation failed");
+        return DC_ERR_NOMEM;
+    }
+    *cap = n;
+    return DC_OK;
+}
+
+}  // namespace
+
+struct Scheduler {
+    dc_ctx *ctx = nullptr;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Req *> queue;
+    std::unordered_map<uint64_t, Req *> table;
+    uint64_t next_ticket = 1;
+    int running = 0;  // requests admitted and not finished
+    bool stop = false;
+    BatchedKernel kern[KT_COUNT] = {};
+    BatchSlot slots[NSLOTS];
+    std::thread th;
+};
 
 size_t request_bytes(int T, int V, int F, int Na, int Nb, int precision, bool want_grad) {
     const size_t TV = (size_t)T * V, TA = (size_t)T * Na, TB = (size_t)T * Nb;
@@ -104,96 +282,8 @@ size_t request_bytes(int T, int V, int F, int Na, int Nb, int precision, bool wa
     return b;
 }
 
-static size_t host_bytes(const Req *r) {
-    return Arena::need((size_t)r->T, 8) + Arena::need(16, 1) +
-           (r->want_grad ? Arena::need((size_t)r->T * r->V * 3, 4) : 0);
-}
-
-// enqueue the request's whole pipeline on its stream; returns a status code
-static int run_request(Scheduler *S, Req *r) {
-    dc_ctx *ctx = S->ctx;
-    hipStream_t s = S->streams[r->stream];
-    {
-        std::lock_guard<std::mutex> g(ctx->budget_mu);
-        if (ctx->fail_next_alloc > 0) {  // test hook: a forced allocation failure
-            --ctx->fail_next_alloc;
-            set_error("device allocation failed (forced)");
-            return DC_ERR_NOMEM;
-        }
-    }
-    if (hipMallocAsync(reinterpret_cast<void **>(&r->dmem), r->bytes, s) != hipSuccess) {
-        (void)hipGetLastError();
-        r->dmem = nullptr;
-        set_error("device allocation of a request failed");
-        return DC_ERR_NOMEM;
-    }
-    Arena ar;
-    ar.base = r->dmem;
-    ar.cap = r->bytes;
-    const int T = r->T, V = r->V, F = r->F, Na = r->Na, Nb = r->Nb;
-    const size_t TV = (size_t)T * V, TA = (size_t)T * Na, TB = (size_t)T * Nb;
-    float *verts = ar.take<float>(TV * 3);
-    int32_t *faces = ar.take<int32_t>((size_t)F * 3);
-    float *obs = ar.take<float>(TB * 3);
-    float *fw = ar.take<float>(T);
-    unsigned *status = ar.take<unsigned>(4);
-    float *pts = ar.take<float>(TA * 3);
-    float *bary = ar.take<float>(TA * 3);
-    int32_t *fidx = ar.take<int32_t>(TA);
-    float *da = ar.take<float>(TA);
-    int32_t *ia = ar.take<int32_t>(TA);
-    float *db = ar.take<float>(TB);
-    int32_t *ib = ar.take<int32_t>(TB);
-    double *loss = ar.take<double>(T);
-    double *gl = nullptr;
-    float *gpts = nullptr, *gverts = nullptr;
-    if (r->want_grad) {
-        gl = ar.take<double>(T);
-        gpts = ar.take<float>(TA * 3);
-        gverts = ar.take<float>(TV * 3);
-    }
-    char *scratch = ar.take<char>(scratch_bytes(T, V, F, Na, Nb, r->precision, r->want_grad));
-
-    DC_HIP(hipMemcpyAsync(verts, r->verts.data(), TV * 3 * 4, hipMemcpyHostToDevice, s));
-    DC_HIP(hipMemcpyAsync(faces, r->faces.data(), (size_t)F * 3 * 4, hipMemcpyHostToDevice, s));
-    DC_HIP(hipMemcpyAsync(obs, r->obs.data(), TB * 3 * 4, hipMemcpyHostToDevice, s));
-    if (r->has_w) DC_HIP(hipMemcpyAsync(fw, r->fw.data(), (size_t)T * 4, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, status, 4, 0u);
-
-    Arena sar;
-    sar.base = scratch;
-    sar.cap = r->bytes;
-    int rc = enqueue_sample(nullptr, verts, faces, T, V, F, Na, r->seed, nullptr, pts, fidx, bary, sar,
-                            status, s);
-    if (rc) return rc;
-    rc = enqueue_chamfer_fwd(nullptr, pts, obs, T, Na, Nb, r->precision, r->reduction,
-                             r->has_w ? fw : nullptr, da, ia, db, ib, loss, scratch, ctx->d_stats,
-                             s);
-    if (rc) return rc;
-    if (r->want_grad) {
-        hipLaunchKernelGGL(k_fill_f64, dim3((T + 255) / 256), dim3(256), 0, s, gl, T, 1.0);
-        launch_chamfer_bwd(gl, pts, obs, ia, ib, T, Na, Nb,
-                           r->reduction, r->has_w ? fw : nullptr, gpts, nullptr, scratch, s);
-        launch_sample_bwd(gpts, faces, fidx, bary, T, V, F, Na, gverts, scratch, s);
-    }
-    Slot &sl = S->slots[r->slot];
-    char *h = sl.host;
-    DC_HIP(hipMemcpyAsync(h, loss, (size_t)T * 8, hipMemcpyDeviceToHost, s));
-    DC_HIP(hipMemcpyAsync(h + Arena::need(T, 8), status, 16, hipMemcpyDeviceToHost, s));
-    if (r->want_grad)
-        DC_HIP(hipMemcpyAsync(h + Arena::need(T, 8) + Arena::need(16, 1), gverts, TV * 3 * 4,
-                              hipMemcpyDeviceToHost, s));
-    DC_HIP(hipFreeAsync(r->dmem, s));
-    r->dmem = nullptr;
-    DC_HIP(hipEventRecord(r->ev, s));
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "serving launch");
-    return DC_OK;
-}
-
-static void finish(Scheduler *S, Req *r) {
-    if (r->status == DC_OK) {
-        const char *h = S->slots[r->slot].host;
+static void finish_req(Scheduler *S, Req *r, const char *h) {
+    if (r->status == DC_OK && h) {
         std::memcpy(r->out->loss, h, (size_t)r->T * 8);
         unsigned st = 0;
         std::memcpy(&st, h + Arena::need(r->T, 8), 4);
@@ -202,98 +292,266 @@ static void finish(Scheduler *S, Req *r) {
         else if (st & ST_DEGENERATE)
             r->status = DC_ERR_DEGENERATE;
         if (r->want_grad)
-            std::memcpy(r->out->grad_verts, h + Arena::need(r->T, 8) + Arena::need(16, 1),
+            std::memcpy(r->out->grad_verts, h + Arena::need(r->T, 8) + Arena::need(4, 4),
                         (size_t)r->T * r->V * 3 * 4);
     }
-    if (r->slot >= 0) S->slots[r->slot].busy = false;
     budget_give(S->ctx, r->bytes);
+    --S->running;
     r->out->t_done = now_s();
     r->out->status = r->status;
     r->state = Q_DONE;
-    // free the input copies now; the record itself lives until polled
     std::vector<float>().swap(r->verts);
     std::vector<float>().swap(r->obs);
     std::vector<int32_t>().swap(r->faces);
+    std::vector<OpRec>().swap(r->ops);
+}
+
+// upload, replay and download one batch on slot `sl`; on failure every request of the batch
+// fails with the returned status
+static int run_batch(Scheduler *S, BatchSlot &sl) {
+    hipStream_t s = sl.stream;
+    size_t dbytes = 0, in_bytes = 0, out_bytes = 0;
+    for (Req *r : sl.reqs) {
+        r->dev_off = dbytes;
+        dbytes += Arena::need(r->bytes, 1);
+    }
+    if (hipMallocAsync(reinterpret_cast<void **>(&sl.dmem), dbytes, s) != hipSuccess) {
+        (void)hipGetLastError();
+        sl.dmem = nullptr;
+        set_error("device allocation of a batch failed");
+        return DC_ERR_NOMEM;
+    }
+    // record every request against its region, then lay the stages out
+    std::vector<Layout> lay;
+    for (Req *r : sl.reqs) {
+        const int rc = plan_request(r, sl.dmem + r->dev_off, S->ctx->d_stats);
+        if (rc) return rc;
+        lay.push_back(carve(r, sl.dmem + r->dev_off));
+        r->in_off = in_bytes;
+        r->out_off = out_bytes;
+        in_bytes += lay.back().in_bytes;
+        out_bytes += lay.back().out_bytes;
+    }
+    int rc = grow_pinned(&sl.h_in, &sl.in_cap, in_bytes);
+    if (rc == DC_OK) rc = grow_pinned(&sl.h_out, &sl.out_cap, out_bytes);
+    if (rc) return rc;
+    BatchDesc *D = sl.h_desc;
+    int nops = 0;
+    for (int st = 0; st < NPROG; ++st) {
+        D->stage[st].first = nops;
+        D->stage[st].nops = 0;
+        long total = 0;
+        for (Req *r : sl.reqs)
+            for (size_t k = 0; k < r->ops.size(); ++k) {
+                if (r->stage_of[k] != st) continue;
+                OpRec &o = D->op[nops++];
+                o = r->ops[k];
+                o.start = (int)total;
+                total += (long)o.gx * o.gy * o.gz;
+                ++D->stage[st].nops;
+            }
+        D->stage[st].total = (int)total;
+    }
+    // inputs: one copy per request from pinned staging laid out like its device region
+    for (size_t q = 0; q < sl.reqs.size(); ++q) {
+        const Req *r = sl.reqs[q];
+        const Layout &L = lay[q];
+        char *h = sl.h_in + r->in_off;
+        const char *d0 = reinterpret_cast<const char *>(L.verts);
+        std::memcpy(h, r->verts.data(), r->verts.size() * 4);
+        std::memcpy(h + (reinterpret_cast<const char *>(L.faces) - d0), r->faces.data(),
+                    r->faces.size() * 4);
+        std::memcpy(h + (reinterpret_cast<const char *>(L.obs) - d0), r->obs.data(),
+                    r->obs.size() * 4);
+        if (r->has_w)
+            std::memcpy(h + (reinterpret_cast<const char *>(L.fw) - d0), r->fw.data(),
+                        r->fw.size() * 4);
+        DC_HIP(hipMemcpyAsync(L.verts, h, L.in_bytes, hipMemcpyHostToDevice, s));
+    }
+    const size_t dsz = sizeof(D->stage) + (size_t)nops * sizeof(OpRec);
+    DC_HIP(hipMemcpyAsync(sl.d_desc, D, dsz, hipMemcpyHostToDevice, s));
+    // stages without work in this batch are switched off (the slot is idle, so its executable
+    // graph may be updated)
+    for (int st = 0; st < NPROG; ++st) {
+        const bool on = D->stage[st].total > 0;
+        if (on != sl.enabled[st]) {
+            DC_HIP(hipGraphNodeSetEnabled(sl.exec, sl.nodes[st], on ? 1u : 0u));
+            sl.enabled[st] = on;
+        }
+    }
+    DC_HIP(hipGraphLaunch(sl.exec, s));
+    for (size_t q = 0; q < sl.reqs.size(); ++q) {
+        const Layout &L = lay[q];
+        DC_HIP(hipMemcpyAsync(sl.h_out + sl.reqs[q]->out_off, L.loss, L.out_bytes,
+                              hipMemcpyDeviceToHost, s));
+    }
+    DC_HIP(hipFreeAsync(sl.dmem, s));
+    sl.dmem = nullptr;
+    DC_HIP(hipEventRecord(sl.ev, s));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "serving batch launch");
+    return DC_OK;
+}
+
+static void fail_batch(Scheduler *S, BatchSlot &sl, int rc) {
+    (void)hipStreamSynchronize(sl.stream);  // anything already enqueued has finished
+    if (sl.dmem) (void)hipFree(sl.dmem);
+    sl.dmem = nullptr;
+    for (Req *r : sl.reqs) {
+        r->status = rc;
+        finish_req(S, r, nullptr);
+    }
+    sl.reqs.clear();
+    sl.busy = false;
+}
+
+// take queued requests for a new batch in arrival order; false when nothing can be admitted
+static bool form_batch(Scheduler *S, BatchSlot &sl) {
+    double pairs = 0;
+    while (!S->queue.empty() && (int)sl.reqs.size() < MAX_BATCH &&
+           S->running < S->ctx->max_slots) {
+        Req *r = S->queue.front();
+        if (!sl.reqs.empty() && pairs + r->pairs > BATCH_PAIRS) break;
+        if (budget_take(S->ctx, r->bytes) != DC_OK) break;
+        S->queue.pop_front();
+        ++S->running;
+        r->state = Q_RUNNING;
+        r->out->t_admit = now_s();
+        bool fail = false;
+        {
+            std::lock_guard<std::mutex> g(S->ctx->budget_mu);
+            if (S->ctx->fail_next_alloc > 0) {  // test hook: a forced allocation failure
+                --S->ctx->fail_next_alloc;
+                fail = true;
+            }
+        }
+        if (fail) {
+            r->status = DC_ERR_NOMEM;
+            finish_req(S, r, nullptr);
+            continue;
+        }
+        sl.reqs.push_back(r);
+        pairs += r->pairs;
+    }
+    return !sl.reqs.empty();
 }
 
 static void loop(Scheduler *S) {
     (void)hipSetDevice(S->ctx->device);
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
-        if (S->stop && S->queue.empty() && S->running.empty()) break;
-        // admit in arrival order while a slot and the budget allow
-        while (!S->queue.empty() && (int)S->running.size() < S->ctx->max_slots) {
-            Req *r = S->queue.front();
-            if (budget_take(S->ctx, r->bytes) != DC_OK) break;
-            S->queue.pop_front();
-            int slot = -1;
-            for (size_t k = 0; k < S->slots.size(); ++k)
-                if (!S->slots[k].busy) {
-                    slot = (int)k;
-                    break;
-                }
-            Slot &sl = S->slots[slot];
-            sl.busy = true;
-            r->slot = slot;
-            r->stream = S->rr;
-            S->rr = (S->rr + 1) % NSTREAMS;
-            r->state = Q_RUNNING;
-            r->out->t_admit = now_s();
-            const size_t hb = host_bytes(r);
-            int rc = DC_OK;
-            if (sl.cap < hb) {
-                if (sl.host) (void)hipHostFree(sl.host);
-                sl.host = nullptr;
-                sl.cap = 0;
-                if (hipHostMalloc(reinterpret_cast<void **>(&sl.host), hb, 0) != hipSuccess) {
-                    sl.host = nullptr;
-                    rc = DC_ERR_NOMEM;
-                } else {
-                    sl.cap = hb;
-                }
-            }
-            if (rc == DC_OK && hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess)
-                rc = DC_ERR_HIP;
-            if (rc == DC_OK) rc = run_request(S, r);
-            S->running.push_back(r);
-            if (rc != DC_OK) {
-                r->status = rc;
-                // wait for anything already enqueued for it before releasing its memory
-                (void)hipStreamSynchronize(S->streams[r->stream]);
-                if (r->dmem) (void)hipFree(r->dmem);
-                r->dmem = nullptr;
-            }
-        }
+        bool any_busy = false;
+        for (auto &sl : S->slots) any_busy |= sl.busy;
+        if (S->stop && S->queue.empty() && !any_busy) break;
         bool progressed = false;
-        for (size_t k = 0; k < S->running.size();) {
-            Req *r = S->running[k];
-            bool done = r->status != DC_OK;
-            if (!done && hipEventQuery(r->ev) == hipSuccess) done = true;
-            if (done) {
-                if (r->ev) (void)hipEventDestroy(r->ev);
-                r->ev = nullptr;
-                finish(S, r);
-                S->running.erase(S->running.begin() + k);
-                progressed = true;
-            } else {
-                ++k;
+        for (auto &sl : S->slots) {
+            if (sl.busy) continue;
+            if (!form_batch(S, sl)) {
+                if (S->queue.empty()) break;
+                continue;
             }
+            sl.busy = true;
+            progressed = true;
+            // staging and launching run unlocked: the slot and its requests belong to this
+            // thread until they finish, and submit / poll only touch the queue and the table
+            lk.unlock();
+            const int rc = run_batch(S, sl);
+            lk.lock();
+            if (rc != DC_OK) fail_batch(S, sl, rc);
+        }
+        for (auto &sl : S->slots) {
+            if (!sl.busy || hipEventQuery(sl.ev) != hipSuccess) continue;
+            for (Req *r : sl.reqs) finish_req(S, r, sl.h_out + r->out_off);
+            sl.reqs.clear();
+            sl.busy = false;
+            progressed = true;
         }
         if (!progressed) S->cv.wait_for(lk, std::chrono::microseconds(50));
     }
+}
+
+static int init_slot(Scheduler *S, BatchSlot &sl) {
+    DC_HIP(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
+    DC_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+    DC_HIP(hipMalloc(reinterpret_cast<void **>(&sl.d_desc), sizeof(BatchDesc)));
+    DC_HIP(hipHostMalloc(reinterpret_cast<void **>(&sl.h_desc), sizeof(BatchDesc), 0));
+    // an empty descriptor: a replay before the first upload does nothing
+    std::memset(sl.h_desc, 0, sizeof(BatchDesc));
+    DC_HIP(hipMemcpy(sl.d_desc, sl.h_desc, sizeof(sl.h_desc->stage), hipMemcpyHostToDevice));
+    // the program as a chain of kernel nodes over the slot's descriptor
+    DC_HIP(hipGraphCreate(&sl.graph, 0));
+    for (int st = 0; st < NPROG; ++st) {
+        const BatchedKernel &k = S->kern[PROGRAM[st]];
+        const BatchDesc *desc = sl.d_desc;
+        int stage = st;
+        void *args[2] = {&desc, &stage};
+        hipKernelNodeParams kp;
+        std::memset(&kp, 0, sizeof(kp));
+        kp.func = const_cast<void *>(k.func);
+        kp.gridDim = dim3(k.blocks);
+        kp.blockDim = dim3(k.threads);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        DC_HIP(hipGraphAddKernelNode(&sl.nodes[st], sl.graph, st ? &sl.nodes[st - 1] : nullptr,
+                                     st ? 1 : 0, &kp));
+        sl.enabled[st] = true;
+    }
+    DC_HIP(hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0));
+    return DC_OK;
+}
+
+static void release_slot(BatchSlot &sl) {
+    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+    if (sl.graph) (void)hipGraphDestroy(sl.graph);
+    if (sl.d_desc) (void)hipFree(sl.d_desc);
+    if (sl.h_desc) (void)hipHostFree(sl.h_desc);
+    if (sl.h_in) (void)hipHostFree(sl.h_in);
+    if (sl.h_out) (void)hipHostFree(sl.h_out);
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
 }
 
 static int ensure_scheduler(dc_ctx *ctx) {
     if (ctx->sched) return DC_OK;
     Scheduler *S = new Scheduler();
     S->ctx = ctx;
-    S->slots.resize(ctx->max_slots);
-    DC_HIP(hipSetDevice(ctx->device));
-    for (int k = 0; k < NSTREAMS; ++k)
-        DC_HIP(hipStreamCreateWithFlags(&S->streams[k], hipStreamNonBlocking));
+    register_sample_kernels(S->kern);
+    register_nn_kernels(S->kern);
+    register_screen_kernels(S->kern);
+    register_sort_kernels(S->kern);
+    register_backward_kernels(S->kern);
+    register_fill_kernels(S->kern);
+    for (int k = 0; k < KT_COUNT; ++k)
+        if (!S->kern[k].func) {
+            delete S;
+            set_error("serving program: a kernel has no batched form");
+            return DC_ERR_HIP;
+        }
+    int rc = DC_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) rc = DC_ERR_HIP;
+    // batches allocate from the device's stream-ordered pool: keep freed memory in the pool
+    // instead of returning it to the driver after every batch
+    hipMemPool_t pool = nullptr;
+    if (rc == DC_OK && hipDeviceGetDefaultMemPool(&pool, ctx->device) == hipSuccess) {
+        uint64_t keep = ~0ull;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    for (auto &sl : S->slots)
+        if (rc == DC_OK) rc = init_slot(S, sl);
+    if (rc != DC_OK) {
+        for (auto &sl : S->slots) release_slot(sl);
+        delete S;
+        return rc;
+    }
     S->th = std::thread(loop, S);
     ctx->sched = S;
     return DC_OK;
+}
+
+void register_fill_kernels(BatchedKernel *table) {
+    table[KT_FILL_U32] = batched_kernel<FillU32Params, fill_u32_body, FILL_THREADS, 64>();
+    table[KT_FILL_F64] = batched_kernel<FillF64Params, fill_f64_body, FILL_THREADS, 64>();
 }
 
 int sched_submit(dc_ctx *ctx, const dc_request *q, dc_result *out, uint64_t *ticket) {
@@ -331,6 +589,7 @@ int sched_submit(dc_ctx *ctx, const dc_request *q, dc_result *out, uint64_t *tic
     r->seed = q->seed;
     r->want_grad = want_grad;
     r->bytes = bytes;
+    r->pairs = (double)q->T * q->n_sim * q->n_obs;
     r->verts.assign(q->verts, q->verts + (size_t)q->T * q->V * 3);
     r->faces.assign(q->faces, q->faces + (size_t)q->F * 3);
     r->obs.assign(q->observed, q->observed + (size_t)q->T * q->n_obs * 3);
@@ -390,10 +649,7 @@ void sched_destroy(dc_ctx *ctx) {
     S->cv.notify_one();
     S->th.join();
     for (auto &kv : S->table) delete kv.second;
-    for (auto &sl : S->slots)
-        if (sl.host) (void)hipHostFree(sl.host);
-    for (int k = 0; k < NSTREAMS; ++k)
-        if (S->streams[k]) (void)hipStreamDestroy(S->streams[k]);
+    for (auto &sl : S->slots) release_slot(sl);
     delete S;
 }
 

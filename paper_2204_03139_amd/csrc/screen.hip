@@ -29,7 +29,7 @@
 // Refine: teams of 16 lanes evaluate the canonical distance over the candidates and keep the
 // lexicographic (distance, index) minimum: exactly the argmin of the exhaustive search with the
 // smallest-index rule.
-#include "dc_internal.h"
+#include "batch.h"
 
 namespace dc {
 namespace {
@@ -157,11 +157,20 @@ __device__ __forceinline__ bf16x8 pick8(const __bf16 (&v)[32], int g) {
 // Padding targets up to a whole chunk get a huge norm so they never win a minimum.
 
 // largest squared norm of each frame's targets (for the certificate)
-__global__ __launch_bounds__(256) void k_norm_max(const float *__restrict__ P, int Np,
-                                                  float *__restrict__ out,
-                                                  int32_t *__restrict__ heavy_cnt) {
+struct NormMaxParams {
+    const float *P;
+    float *out;
+    int32_t *heavy_cnt;
+    int Np;
+};
+
+__device__ __forceinline__ void norm_max_body(const NormMaxParams &pr, const Blk &blk) {
+    const float *__restrict__ P = pr.P;
+    const int Np = pr.Np;
+    float *__restrict__ out = pr.out;
+    int32_t *__restrict__ heavy_cnt = pr.heavy_cnt;
     __shared__ float red[256];
-    const int t = blockIdx.x;
+    const int t = blk.x;
     if (threadIdx.x == 0) heavy_cnt[t] = 0;
     const float *pt = P + (size_t)t * Np * 3;
     float m = 0.f;
@@ -175,6 +184,8 @@ __global__ __launch_bounds__(256) void k_norm_max(const float *__restrict__ P, i
     }
     if (threadIdx.x == 0) out[t] = red[0];
 }
+
+__global__ __launch_bounds__(256) void k_norm_max(NormMaxParams p) { norm_max_body(p, grid_blk()); }
 
 // Certificate threshold: every index whose canonical float distance can equal the minimum has a
 // screened value <= threshold(m, nq, nmax), where m is the query's screened minimum, nq its squared
@@ -219,24 +230,33 @@ __device__ __forceinline__ float threshold_affine(float m, float slack) {
 // Target operands of every frame, packed once: target j's three non-zero K-chunks (48 bytes), and
 // the affine threshold slack of the column direction.  Padding targets up to a whole chunk get a
 // huge norm so they never win a minimum.
-__global__ __launch_bounds__(256) void k_pack_targets(const float *__restrict__ P, int Np,
-                                                      int Np_pad, const float *__restrict__ nqmax,
-                                                      bf16x8 *__restrict__ packed,
-                                                      float *__restrict__ slack) {
-    const int t = blockIdx.y;
-    const int j = blockIdx.x * 256 + threadIdx.x;
+struct PackParams {
+    const float *P;
+    const float *nqmax;
+    bf16x8 *packed;
+    float *slack;
+    int Np, Np_pad;
+};
+
+__device__ __forceinline__ void pack_body(const PackParams &pr, const Blk &blk) {
+    const float *__restrict__ P = pr.P;
+    const int Np = pr.Np, Np_pad = pr.Np_pad;
+    const int t = blk.y;
+    const int j = blk.x * 256 + threadIdx.x;
     if (j >= Np_pad) return;
     const bool valid = j < Np;
     const float *p = P + ((size_t)t * Np + (valid ? j : 0)) * 3;
     const float x = valid ? p[0] : 0.f, y = valid ? p[1] : 0.f, z = valid ? p[2] : 0.f;
     __bf16 v[32];
     target_vector(x, y, z, valid, v);
-    bf16x8 *o = packed + ((size_t)t * Np_pad + j) * 3;
+    bf16x8 *o = pr.packed + ((size_t)t * Np_pad + j) * 3;
     o[0] = pick8(v, 0);
     o[1] = pick8(v, 1);
     o[2] = pick8(v, 2);
-    slack[(size_t)t * Np_pad + j] = affine_slack(norm2(x, y, z), nqmax[t]);
+    pr.slack[(size_t)t * Np_pad + j] = affine_slack(norm2(x, y, z), pr.nqmax[t]);
 }
+
+__global__ __launch_bounds__(256) void k_pack_targets(PackParams p) { pack_body(p, grid_blk()); }
 
 // Column partial minima are stored as the upper 16 bits of the float (a bf16 bit pattern), rounded
 // toward minus infinity, so the stored value is a lower bound of the partial.
@@ -255,31 +275,38 @@ __device__ __forceinline__ float bf16_step_up(float x) {
 constexpr int SC_GROUPS = SC_WAVES * 4;  // row groups per workgroup: (wave, lane group g)
 constexpr int CP_PAD = SC_TPS + 1;       // column partial buffer: [group][column][tile], padded
 
+struct ScreenParams {
+    const float *Q;
+    const bf16x8 *packed;
+    const float *slack;
+    const float *npmax;
+    int32_t *rec;
+    int32_t *heavy_cnt;
+    int32_t *heavy_list;
+    uint16_t *cpart;
+    uint8_t *ctag;
+    int Nq, Np, Np_pad;
+};
+
+// logical workgroup: x = row block of the frame, y = frame, gx = row blocks per frame
 template <bool COLS>
-__global__ __launch_bounds__(SC_THREADS) void k_screen(
-    const float *__restrict__ Q, int Nq, const bf16x8 *__restrict__ packed,
-    const float *__restrict__ slack, int Np, int Np_pad, const float *__restrict__ npmax,
-    int32_t *__restrict__ rec, int32_t *__restrict__ heavy_cnt,
-    int32_t *__restrict__ heavy_list, uint16_t *__restrict__ cpart, uint8_t *__restrict__ ctag) {
+__device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &blk) {
+    const float *__restrict__ Q = pr.Q;
+    const bf16x8 *__restrict__ packed = pr.packed;
+    const float *__restrict__ slack = pr.slack;
+    const int Nq = pr.Nq, Np = pr.Np, Np_pad = pr.Np_pad;
+    int32_t *__restrict__ rec = pr.rec;
+    int32_t *__restrict__ heavy_cnt = pr.heavy_cnt;
+    int32_t *__restrict__ heavy_list = pr.heavy_list;
+    uint16_t *__restrict__ cpart = pr.cpart;
+    uint8_t *__restrict__ ctag = pr.ctag;
     // [buffer][K-chunk][entry] -> 16 bytes.  Entry 17*bt + c holds tile bt, result column c: the
     // operand reads (16 columns of one tile) are consecutive and the staging stores (8 tiles of
     // one column, 272 bytes apart) fall in distinct banks; the read address is a per-lane base
     // plus a compile-time offset.  K-chunk 3 is all zeros on the query side and is not stored.
     __shared__ bf16x8 stage[2][3][SC_ROWPAD * SC_TPS];
     __shared__ float colbuf[COLS ? SC_GROUPS : 1][16][CP_PAD];
-    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs, so the ids of one
-    // XCD are mapped onto one contiguous range of (frame, row block) items; each XCD's L2 then
-    // holds the packed targets of about T/8 frames instead of every frame
-    const int nwg = gridDim.x;
-    int wgx, t;
-    {
-        const unsigned total = (unsigned)nwg * gridDim.y;
-        const unsigned id = blockIdx.x + (unsigned)nwg * blockIdx.y;
-        const unsigned c = id % 8u, k = id / 8u, per = total / 8u, rem = total % 8u;
-        const unsigned item = c * per + (c < rem ? c : rem) + k;
-        t = (int)(item / (unsigned)nwg);
-        wgx = (int)(item % (unsigned)nwg);
-    }
+    const int nwg = blk.gx, wgx = blk.x, t = blk.y;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4;   // K-chunk of the operands; row group of the result
@@ -442,7 +469,7 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(
     }
 
     // row certificate and candidate records; the 16 lanes of a group share one row per (a, r)
-    const float npm = npmax[t];
+    const float npm = pr.npmax[t];
     const unsigned long long gmask = 0xFFFFull << (16 * g);
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
@@ -486,6 +513,25 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(
         }
 }
 
+// Direct launch, in an XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs, so
+// the hardware ids of one XCD are mapped onto one contiguous range of (frame, row block) items and
+// each XCD's L2 holds the packed targets of about T/8 frames instead of every frame.
+template <bool COLS>
+__global__ __launch_bounds__(SC_THREADS) void k_screen(ScreenParams p) {
+    Blk b;
+    b.gx = gridDim.x;
+    b.gy = gridDim.y;
+    b.gz = 1;
+    b.z = 0;
+    const unsigned total = (unsigned)gridDim.x * gridDim.y;
+    const unsigned id = blockIdx.x + (unsigned)gridDim.x * blockIdx.y;
+    const unsigned c = id % 8u, k = id / 8u, per = total / 8u, rem = total % 8u;
+    const unsigned item = c * per + (c < rem ? c : rem) + k;
+    b.y = (int)(item / gridDim.x);
+    b.x = (int)(item % gridDim.x);
+    screen_body<COLS>(p, b);
+}
+
 // Column merge: per target b_j, the CMAXC workgroups with the smallest partial minima (kept sorted
 // by insertion, which is rare after the first few workgroups) and the next value; candidates are
 // the workgroups passing the certificate.  Record per target: n (or -1 = heavy) and up to CMAXC
@@ -511,15 +557,28 @@ __device__ __forceinline__ void colmerge_insert(float (&bv)[CMAXC + 1], int (&bw
     }
 }
 
-__global__ __launch_bounds__(256) void k_colmerge(const float *__restrict__ P, int Np, int Np_pad,
-                                                  int nwg, const uint16_t *__restrict__ cpart,
-                                                  const uint8_t *__restrict__ ctag,
-                                                  const float *__restrict__ nqmax,
-                                                  int32_t *__restrict__ crec,
-                                                  int32_t *__restrict__ heavy_cnt,
-                                                  int32_t *__restrict__ heavy_list) {
-    const int t = blockIdx.y;
-    const int j0 = (blockIdx.x * 256 + threadIdx.x) * CM_TPT;
+struct ColmergeParams {
+    const float *P;
+    const uint16_t *cpart;
+    const uint8_t *ctag;
+    const float *nqmax;
+    int32_t *crec;
+    int32_t *heavy_cnt;
+    int32_t *heavy_list;
+    int Np, Np_pad, nwg;
+};
+
+__device__ __forceinline__ void colmerge_body(const ColmergeParams &pr, const Blk &blk) {
+    const float *__restrict__ P = pr.P;
+    const int Np = pr.Np, Np_pad = pr.Np_pad, nwg = pr.nwg;
+    const uint16_t *__restrict__ cpart = pr.cpart;
+    const uint8_t *__restrict__ ctag = pr.ctag;
+    const float *__restrict__ nqmax = pr.nqmax;
+    int32_t *__restrict__ crec = pr.crec;
+    int32_t *__restrict__ heavy_cnt = pr.heavy_cnt;
+    int32_t *__restrict__ heavy_list = pr.heavy_list;
+    const int t = blk.y;
+    const int j0 = (blk.x * 256 + threadIdx.x) * CM_TPT;
     if (j0 >= Np) return;
     const float inf = __builtin_inff();
     float bv[CM_TPT][CMAXC + 1];
@@ -567,6 +626,8 @@ __global__ __launch_bounds__(256) void k_colmerge(const float *__restrict__ P, i
     }
 }
 
+__global__ __launch_bounds__(256) void k_colmerge(ColmergeParams p) { colmerge_body(p, grid_blk()); }
+
 __device__ __forceinline__ float canon_d2(float qx, float qy, float qz, const float *p) {
     const float dx = qx - p[0];
     const float dy = qy - p[1];
@@ -613,21 +674,33 @@ __device__ __forceinline__ void flush_stats(unsigned *cnt, unsigned long long *s
 // Row refine (a -> b): candidate slot groups of light rows; heavy rows are left to the exact
 // kernel.  A team of 16 lanes takes one query; each 64-target step gives every lane 4 consecutive
 // targets (48 contiguous bytes).
-__global__ __launch_bounds__(RF_THREADS) void k_refine(const float *__restrict__ Q, int Nq,
-                                                       const float *__restrict__ P, int Np,
-                                                       const int32_t *__restrict__ rec,
-                                                       int32_t *__restrict__ idx,
-                                                       float *__restrict__ dist,
-                                                       unsigned long long *__restrict__ stats) {
+struct RefineParams {
+    const float *Q;  // queries (rows a for the row refine, targets b for the column refine)
+    const float *P;  // points searched (b, or a)
+    const int32_t *rec;
+    int32_t *idx;
+    float *dist;
+    unsigned long long *stats;
+    int Nq, Np;
+};
+
+__device__ __forceinline__ void refine_body(const RefineParams &pr, const Blk &blk) {
+    const float *__restrict__ Q = pr.Q;
+    const float *__restrict__ P = pr.P;
+    const int Nq = pr.Nq, Np = pr.Np;
+    const int32_t *__restrict__ rec = pr.rec;
+    int32_t *__restrict__ idx = pr.idx;
+    float *__restrict__ dist = pr.dist;
+    unsigned long long *__restrict__ stats = pr.stats;
     __shared__ unsigned cnt[2];
     if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
     __syncthreads();
-    const int t = blockIdx.y;
+    const int t = blk.y;
     const int team = threadIdx.x / RF_TEAM, tl = threadIdx.x % RF_TEAM;
     const float *Pt = P + (size_t)t * Np * 3;
     unsigned my_cand = 0, my_heavy = 0;
     for (int qq = 0; qq < RF_QUERIES / RF_TEAMS; ++qq) {
-        const int i = blockIdx.x * RF_QUERIES + qq * RF_TEAMS + team;
+        const int i = blk.x * RF_QUERIES + qq * RF_TEAMS + team;
         const int32_t *rr = rec + ((size_t)t * Nq + min(i, Nq - 1)) * REC_INTS;
         const int n = (i < Nq) ? rr[0] : -2;
         float qx = 0.f, qy = 0.f, qz = 0.f;
@@ -672,27 +745,31 @@ __global__ __launch_bounds__(RF_THREADS) void k_refine(const float *__restrict__
             my_heavy += n < 0 ? 1u : 0u;
         }
     }
-    flush_stats(cnt, stats, min(RF_QUERIES, Nq - (int)blockIdx.x * RF_QUERIES), my_cand,
+    flush_stats(cnt, stats, min(RF_QUERIES, Nq - blk.x * RF_QUERIES), my_cand,
                 my_heavy, tl);
 }
 
+__global__ __launch_bounds__(RF_THREADS) void k_refine(RefineParams p) { refine_body(p, grid_blk()); }
+
 // Column refine (b -> a): each candidate workgroup contributes its winning row group (16 rows:
 // one per lane) or, when flagged ambiguous, all of its rows.
-__global__ __launch_bounds__(RF_THREADS) void k_colrefine(const float *__restrict__ A, int Na,
-                                                          const float *__restrict__ B, int Nb,
-                                                          const int32_t *__restrict__ crec,
-                                                          int32_t *__restrict__ idx,
-                                                          float *__restrict__ dist,
-                                                          unsigned long long *__restrict__ stats) {
+__device__ __forceinline__ void colrefine_body(const RefineParams &pr, const Blk &blk) {
+    const float *__restrict__ B = pr.Q;
+    const float *__restrict__ A = pr.P;
+    const int Nb = pr.Nq, Na = pr.Np;
+    const int32_t *__restrict__ crec = pr.rec;
+    int32_t *__restrict__ idx = pr.idx;
+    float *__restrict__ dist = pr.dist;
+    unsigned long long *__restrict__ stats = pr.stats;
     __shared__ unsigned cnt[2];
     if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
     __syncthreads();
-    const int t = blockIdx.y;
+    const int t = blk.y;
     const int team = threadIdx.x / RF_TEAM, tl = threadIdx.x % RF_TEAM;
     const float *At = A + (size_t)t * Na * 3;
     unsigned my_cand = 0, my_heavy = 0;
     for (int qq = 0; qq < RF_QUERIES / RF_TEAMS; ++qq) {
-        const int j = blockIdx.x * RF_QUERIES + qq * RF_TEAMS + team;
+        const int j = blk.x * RF_QUERIES + qq * RF_TEAMS + team;
         const int32_t *rr = crec + ((size_t)t * Nb + min(j, Nb - 1)) * CREC_INTS;
         const int n = (j < Nb) ? rr[0] : -2;
         float qx = 0.f, qy = 0.f, qz = 0.f;
@@ -740,8 +817,12 @@ __global__ __launch_bounds__(RF_THREADS) void k_colrefine(const float *__restric
             my_heavy += n < 0 ? 1u : 0u;
         }
     }
-    flush_stats(cnt, stats, min(RF_QUERIES, Nb - (int)blockIdx.x * RF_QUERIES), my_cand,
+    flush_stats(cnt, stats, min(RF_QUERIES, Nb - blk.x * RF_QUERIES), my_cand,
                 my_heavy, tl);
+}
+
+__global__ __launch_bounds__(RF_THREADS) void k_colrefine(RefineParams p) {
+    colrefine_body(p, grid_blk());
 }
 
 }  // namespace
@@ -787,27 +868,93 @@ void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int
     uint8_t *ctag = ar.take<uint8_t>((size_t)T * nwg * Nb_pad);
     char *exact_scratch = ar.take<char>(
         std::max(nn_exact_list_scratch_bytes(T, Na, Nb), nn_exact_list_scratch_bytes(T, Nb, Na)));
-    hipLaunchKernelGGL(k_norm_max, dim3(T), dim3(256), 0, s, b, Nb, nbmax, hcnt_a);
-    hipLaunchKernelGGL(k_norm_max, dim3(T), dim3(256), 0, s, a, Na, namax, hcnt_b);
-    hipLaunchKernelGGL(k_pack_targets, dim3(Nb_pad / 256, T), dim3(256), 0, s, b, Nb, Nb_pad,
-                       namax, packed, slack);
+    NormMaxParams nm;
+    nm.P = b;
+    nm.Np = Nb;
+    nm.out = nbmax;
+    nm.heavy_cnt = hcnt_a;
+    dispatch(KT_NORM_MAX, k_norm_max, dim3(T), 256, nm, s);
+    nm.P = a;
+    nm.Np = Na;
+    nm.out = namax;
+    nm.heavy_cnt = hcnt_b;
+    dispatch(KT_NORM_MAX, k_norm_max, dim3(T), 256, nm, s);
+    PackParams pk;
+    pk.P = b;
+    pk.nqmax = namax;
+    pk.packed = packed;
+    pk.slack = slack;
+    pk.Np = Nb;
+    pk.Np_pad = Nb_pad;
+    dispatch(KT_PACK, k_pack_targets, dim3(Nb_pad / 256, T), 256, pk, s);
     {
         ProfScope ps(prof, 0, s);
-        hipLaunchKernelGGL(k_screen<true>, dim3(nwg, T), dim3(SC_THREADS), 0, s, a, Na, packed,
-                           slack, Nb, Nb_pad, nbmax, rec, hcnt_a, hlist_a, cpart, ctag);
+        ScreenParams sp;
+        sp.Q = a;
+        sp.packed = packed;
+        sp.slack = slack;
+        sp.npmax = nbmax;
+        sp.rec = rec;
+        sp.heavy_cnt = hcnt_a;
+        sp.heavy_list = hlist_a;
+        sp.cpart = cpart;
+        sp.ctag = ctag;
+        sp.Nq = Na;
+        sp.Np = Nb;
+        sp.Np_pad = Nb_pad;
+        dispatch(KT_SCREEN, k_screen<true>, dim3(nwg, T), SC_THREADS, sp, s);
     }
     {
         ProfScope ps(prof, 1, s);
-        hipLaunchKernelGGL(k_refine, dim3((Na + RF_QUERIES - 1) / RF_QUERIES, T),
-                           dim3(RF_THREADS), 0, s, a, Na, b, Nb, rec, idx_a, dist_a, stats);
-        hipLaunchKernelGGL(k_colmerge, dim3((Nb + 256 * CM_TPT - 1) / (256 * CM_TPT), T),
-                           dim3(256), 0, s, b, Nb, Nb_pad, nwg, cpart, ctag, namax, crec, hcnt_b,
-                           hlist_b);
-        hipLaunchKernelGGL(k_colrefine, dim3((Nb + RF_QUERIES - 1) / RF_QUERIES, T),
-                           dim3(RF_THREADS), 0, s, a, Na, b, Nb, crec, idx_b, dist_b, stats);
+        RefineParams rp;
+        rp.Q = a;
+        rp.P = b;
+        rp.rec = rec;
+        rp.idx = idx_a;
+        rp.dist = dist_a;
+        rp.stats = stats;
+        rp.Nq = Na;
+        rp.Np = Nb;
+        dispatch(KT_REFINE, k_refine, dim3((Na + RF_QUERIES - 1) / RF_QUERIES, T), RF_THREADS, rp,
+                 s);
+        ColmergeParams cm;
+        cm.P = b;
+        cm.cpart = cpart;
+        cm.ctag = ctag;
+        cm.nqmax = namax;
+        cm.crec = crec;
+        cm.heavy_cnt = hcnt_b;
+        cm.heavy_list = hlist_b;
+        cm.Np = Nb;
+        cm.Np_pad = Nb_pad;
+        cm.nwg = nwg;
+        dispatch(KT_COLMERGE, k_colmerge, dim3((Nb + 256 * CM_TPT - 1) / (256 * CM_TPT), T), 256,
+                 cm, s);
+        RefineParams cr;
+        cr.Q = b;
+        cr.P = a;
+        cr.rec = crec;
+        cr.idx = idx_b;
+        cr.dist = dist_b;
+        cr.stats = stats;
+        cr.Nq = Nb;
+        cr.Np = Na;
+        dispatch(KT_COLREFINE, k_colrefine, dim3((Nb + RF_QUERIES - 1) / RF_QUERIES, T),
+                 RF_THREADS, cr, s);
         launch_nn_exact_list(a, Na, b, Nb, T, hlist_a, hcnt_a, idx_a, dist_a, exact_scratch, s);
         launch_nn_exact_list(b, Nb, a, Na, T, hlist_b, hcnt_b, idx_b, dist_b, exact_scratch, s);
     }
+}
+
+void register_screen_kernels(BatchedKernel *table) {
+    table[KT_NORM_MAX] = batched_kernel<NormMaxParams, norm_max_body, 256, 512>();
+    table[KT_PACK] = batched_kernel<PackParams, pack_body, 256, 1024>();
+    // two screen workgroups per compute unit fit the batched kernel's registers (forcing three
+    // spills registers and measured slower)
+    table[KT_SCREEN] = batched_kernel<ScreenParams, screen_body<true>, SC_THREADS, 512>();
+    table[KT_REFINE] = batched_kernel<RefineParams, refine_body, RF_THREADS, 2048>();
+    table[KT_COLMERGE] = batched_kernel<ColmergeParams, colmerge_body, 256, 1024>();
+    table[KT_COLREFINE] = batched_kernel<RefineParams, colrefine_body, RF_THREADS, 2048>();
 }
 
 }  // namespace dc

@@ -12,7 +12,7 @@
 //                offset[digit][block] + rank, which preserves the input order among equal keys.
 // No atomics anywhere, so the permutation is the same on every run.  Keys outside [0, limit] are
 // clamped to limit (they sort last).
-#include "dc_internal.h"
+#include "batch.h"
 
 namespace dc {
 namespace {
@@ -52,11 +52,21 @@ __device__ __forceinline__ void read_item(const SortIO &io, size_t o, int e, int
     val = io.src_vals ? io.src_vals[o] : e;
 }
 
-__global__ __launch_bounds__(SB_THREADS) void k_ss_hist(SortIO io, int N, int shift, int nblk,
-                                                        int32_t *__restrict__ counts) {
+struct SortPassParams {
+    SortIO io;
+    int32_t *counts;  // per (frame, digit, block) counts, then their exclusive offsets
+    int32_t *dst_keys;
+    int32_t *dst_vals;
+    int N, shift, nblk;
+};
+
+__device__ __forceinline__ void ss_hist_body(const SortPassParams &pr, const Blk &b) {
+    const SortIO io = pr.io;
+    const int N = pr.N, shift = pr.shift, nblk = pr.nblk;
+    int32_t *__restrict__ counts = pr.counts;
     __shared__ int whist[SB_WAVES][BINS];
     __shared__ int total[BINS];
-    const int t = blockIdx.y, blk = blockIdx.x;
+    const int t = b.y, blk = b.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     total[threadIdx.x] = 0;
@@ -79,14 +89,19 @@ __global__ __launch_bounds__(SB_THREADS) void k_ss_hist(SortIO io, int N, int sh
     counts[((size_t)t * BINS + threadIdx.x) * nblk + blk] = total[threadIdx.x];
 }
 
+__global__ __launch_bounds__(SB_THREADS) void k_ss_hist(SortPassParams p) {
+    ss_hist_body(p, grid_blk());
+}
+
 // exclusive prefix over (digit, block) of one frame, in place: each thread sums a contiguous run,
 // the runs' totals are scanned across the workgroup (in-wave shuffles, then the 16 wave totals),
 // and each thread rewrites its run from its exclusive start
 constexpr int SCAN_THREADS = 1024;
-__global__ __launch_bounds__(SCAN_THREADS) void k_ss_scan(int32_t *__restrict__ counts, int nblk) {
+__device__ __forceinline__ void ss_scan_body(const SortPassParams &pr, const Blk &b) {
     __shared__ int wsum[SCAN_THREADS / 64];
-    const int t = blockIdx.x;
-    int32_t *c = counts + (size_t)t * BINS * nblk;
+    const int nblk = pr.nblk;
+    const int t = b.x;
+    int32_t *c = pr.counts + (size_t)t * BINS * nblk;
     const int n = BINS * nblk;
     const int per = (n + SCAN_THREADS - 1) / SCAN_THREADS;
     const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
@@ -111,13 +126,19 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_ss_scan(int32_t *__restrict__ 
     }
 }
 
-__global__ __launch_bounds__(SB_THREADS) void k_ss_scatter(SortIO io, int N, int shift, int nblk,
-                                                           const int32_t *__restrict__ offsets,
-                                                           int32_t *__restrict__ dst_keys,
-                                                           int32_t *__restrict__ dst_vals) {
+__global__ __launch_bounds__(SCAN_THREADS) void k_ss_scan(SortPassParams p) {
+    ss_scan_body(p, grid_blk());
+}
+
+__device__ __forceinline__ void ss_scatter_body(const SortPassParams &pr, const Blk &b) {
+    const SortIO io = pr.io;
+    const int N = pr.N, shift = pr.shift, nblk = pr.nblk;
+    const int32_t *__restrict__ offsets = pr.counts;
+    int32_t *__restrict__ dst_keys = pr.dst_keys;
+    int32_t *__restrict__ dst_vals = pr.dst_vals;
     __shared__ int whist[SB_WAVES][BINS];
     __shared__ int running[BINS];
-    const int t = blockIdx.y, blk = blockIdx.x;
+    const int t = b.y, blk = b.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     running[threadIdx.x] = offsets[((size_t)t * BINS + threadIdx.x) * nblk + blk];
@@ -150,6 +171,10 @@ __global__ __launch_bounds__(SB_THREADS) void k_ss_scatter(SortIO io, int N, int
         }
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(SB_THREADS) void k_ss_scatter(SortPassParams p) {
+    ss_scatter_body(p, grid_blk());
 }
 
 static_assert(SB_THREADS == BINS, "one thread per digit bin");
@@ -188,11 +213,24 @@ void launch_segsort(const int32_t *keys, int T, int N, int key_limit, int32_t *o
         io.src_vals = p == 0 ? nullptr : tv[(p - 1) & 1];
         int32_t *dk = (p == passes - 1) ? out_keys : tk[p & 1];
         int32_t *dv = (p == passes - 1) ? out_vals : tv[p & 1];
-        hipLaunchKernelGGL(k_ss_hist, grid, dim3(SB_THREADS), 0, s, io, N, 8 * p, nblk, counts);
-        hipLaunchKernelGGL(k_ss_scan, dim3(T), dim3(SCAN_THREADS), 0, s, counts, nblk);
-        hipLaunchKernelGGL(k_ss_scatter, grid, dim3(SB_THREADS), 0, s, io, N, 8 * p, nblk, counts,
-                           dk, dv);
+        SortPassParams sp;
+        sp.io = io;
+        sp.counts = counts;
+        sp.dst_keys = dk;
+        sp.dst_vals = dv;
+        sp.N = N;
+        sp.shift = 8 * p;
+        sp.nblk = nblk;
+        dispatch(KT_SS_HIST, k_ss_hist, grid, SB_THREADS, sp, s);
+        dispatch(KT_SS_SCAN, k_ss_scan, dim3(T), SCAN_THREADS, sp, s);
+        dispatch(KT_SS_SCATTER, k_ss_scatter, grid, SB_THREADS, sp, s);
     }
+}
+
+void register_sort_kernels(BatchedKernel *table) {
+    table[KT_SS_HIST] = batched_kernel<SortPassParams, ss_hist_body, SB_THREADS, 1024>();
+    table[KT_SS_SCAN] = batched_kernel<SortPassParams, ss_scan_body, SCAN_THREADS, 256>();
+    table[KT_SS_SCATTER] = batched_kernel<SortPassParams, ss_scatter_body, SB_THREADS, 1024>();
 }
 
 }  // namespace dc

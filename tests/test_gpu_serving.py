@@ -56,6 +56,35 @@ def test_serving_matches_direct_calls(precision):
     srv.close()
 
 
+def test_batched_options_match_direct_calls():
+    """One burst mixing both precisions, both reductions, frame weights, requests without a
+    gradient and exact searches with 1, 4 and 8 queries per lane: every request is batched with
+    the others and still equals its direct calls bit for bit."""
+    p = gpu()
+    from paper_2204_03139_amd.serving import Server
+    say("[serving] batched options")
+    srv = Server(hbm_budget_bytes=4 << 30)
+    cases = []
+    for k in range(10):
+        prec, red, want = k % 2, (k // 2) % 2, k % 3 != 2
+        Na = [900, 5000, 17000][k % 3]
+        q = _request(20 + k, T=2, Na=Na, Nb=[700, 4500, 16500][(k + 1) % 3])
+        fw = np.linspace(0.5, 1.5, 2).astype(np.float32) if k % 4 == 1 else None
+        cases.append((q, prec, red, want, fw))
+    tickets = [srv.submit(q["verts"], q["faces"], q["obs"], q["Na"], q["seed"], prec, red, fw,
+                          want_grad=want) for q, prec, red, want, fw in cases]
+    for (q, prec, red, want, fw), tk in zip(cases, tickets):
+        st, loss, grad, _ = srv.wait(tk)
+        assert st == 0
+        dl, dg = _direct(p, q, prec, red, fw)
+        assert np.array_equal(loss.view(np.uint64), dl.view(np.uint64))
+        if want:
+            assert np.array_equal(grad.view(np.uint32), dg.view(np.uint32))
+        else:
+            assert grad is None
+    srv.close()
+
+
 def test_alone_equals_mixed():
     """Request 0 run alone, then again while 15 others are in flight in a random order."""
     p = gpu()
