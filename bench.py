@@ -33,8 +33,8 @@ SCREEN_ISSUE_CEILING = CUS * SIMDS_PER_CU * PEAK_CLOCK_HZ / (5 * 4) * 256
 # HBM bytes of one k_screen launch on this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled
 # by a plain-copy calibration (profiles/k_screen_grid100_65536pts_100frames_counters.md); valid
 # only for the screen source they were measured on.
-SCREEN_TRAFFIC = dict(source_sha256="6b0dbc8aa442858eb6d68631eaf8ff8b3bdc9d8c99d7be0a832ece9a8f03785a",
-                      bytes=2675521991 + 210001616)
+SCREEN_TRAFFIC = dict(source_sha256="02c109651ccc15252dad00b1d3bd2b965c84a7da043cd85ee91610304547549a",
+                      bytes=2868224735 + 5243528224)
 
 
 def _screen_traffic():
@@ -61,14 +61,17 @@ def _args():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving leg (256 Poisson requests, p50/p99 latency)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving leg")
+    ap.add_argument("--no-eq2", action="store_true",
+                    help="skip the unidirectional (Eq. 2) leg reported under paths")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one plain device-to-device copy of MIB mebibytes (to scale "
                          "hardware byte counters) and exit")
     return ap.parse_args()
 
 
-def run_path(p, torch, w, precision, steps, warmup):
-    """Time `steps` full steps of one precision path; returns (ms_per_step, kernel_times)."""
+def run_path(p, torch, w, precision, steps, warmup, reduction=0):
+    """Time `steps` full steps of one precision path; returns (ms_per_step, kernel_times).  With
+    the unidirectional reduction (Eq. 2) only the a -> b direction is searched."""
     ctx = p.default_context(0)
     T, V, Na, Nb = w["T"], w["V"], w["Na"], w["Nb"]
     dev = torch.device("cuda", 0)
@@ -79,18 +82,21 @@ def run_path(p, torch, w, precision, steps, warmup):
     pts = torch.empty((T, Na, 3), dtype=torch.float32, device=dev)
     fi = torch.empty((T, Na), dtype=torch.int32, device=dev)
     ba = torch.empty((T, Na, 3), dtype=torch.float32, device=dev)
-    fwd = dict(dist_a=torch.empty((T, Na), device=dev), idx_a=torch.empty((T, Na), dtype=torch.int32,
-                                                                          device=dev),
-               dist_b=torch.empty((T, Nb), device=dev), idx_b=torch.empty((T, Nb), dtype=torch.int32,
-                                                                          device=dev),
+    both = reduction == 0
+    fwd = dict(dist_a=torch.empty((T, Na), device=dev),
+               idx_a=torch.empty((T, Na), dtype=torch.int32, device=dev),
+               dist_b=torch.empty((T, Nb), device=dev) if both else None,
+               idx_b=torch.empty((T, Nb), dtype=torch.int32, device=dev) if both else None,
                loss=torch.empty(T, dtype=torch.float64, device=dev))
     ga = torch.empty((T, Na, 3), dtype=torch.float32, device=dev)
     gv = torch.empty((T, V, 3), dtype=torch.float32, device=dev)
 
     def step():
         p.sample_surface(verts, faces, Na, seed=w["seed"], out=(pts, fi, ba), ctx=ctx)
-        p.chamfer_fwd(pts, obs, precision=precision, out=fwd, ctx=ctx)
-        p.chamfer_bwd(ones, pts, obs, fwd["idx_a"], fwd["idx_b"], out=(ga, None), ctx=ctx)
+        p.chamfer_fwd(pts, obs, precision=precision, reduction=reduction, out=fwd, ctx=ctx,
+                      b_side=both)
+        p.chamfer_bwd(ones, pts, obs, fwd["idx_a"], fwd["idx_b"], reduction=reduction,
+                      out=(ga, None), ctx=ctx)
         p.sample_surface_bwd(ga, faces, fi, ba, V, out=gv, ctx=ctx)
 
     for _ in range(warmup):
@@ -245,10 +251,14 @@ def main():
     pairs = float(T) * Na * Nb
     paths = {}
     todo = {"fp32": [0], "bf16": [1], "both": [0, 1]}[a.precision]
-    for prec in todo:
-        name = "fp32" if prec == 0 else "bf16_refine"
+    # the headline is the bidirectional loss (Eq. 1); the unidirectional loss the paper optimises
+    # (Eq. 2, one search direction) is reported beside it for the fastest precision
+    runs = [("fp32" if prec == 0 else "bf16_refine", prec, 0) for prec in todo]
+    if not a.no_eq2:
+        runs.append(("fp32_eq2" if max(todo) == 0 else "bf16_refine_eq2", max(todo), 1))
+    for name, prec, red in runs:
         try:
-            ms, kt, stats, loss = run_path(p, torch, w, prec, a.steps, a.warmup)
+            ms, kt, stats, loss = run_path(p, torch, w, prec, a.steps, a.warmup, reduction=red)
         except p.DCError as e:
             paths[name] = dict(error=str(e))
             continue
@@ -263,7 +273,7 @@ def main():
                            all_pairs_avg_launch_ms=avg,
                            all_pairs_pairs_per_s=per_launch_pairs / (avg * 1e-3) if avg else None,
                            loss_sum=loss, screen_stats=stats)
-    ok = {k: v for k, v in paths.items() if "error" not in v}
+    ok = {k: v for k, v in paths.items() if "error" not in v and not k.endswith("_eq2")}
     if not ok:
         print(json.dumps(dict(metric=METRIC, error=paths)))
         sys.exit(1)

@@ -119,14 +119,17 @@ int dc_sample_surface_bwd(dc_ctx *ctx, const float *grad_points, const int32_t *
  *   reduction DC_RED_BIDIR_MEAN (Eq. 1) or DC_RED_SIM2REAL_SUM (Eq. 2)
  *   frame_w   device float [T] or NULL (all ones): weight w_t of frame t
  *   dist_a, idx_a  device float/int32 [T,Na] out: min over b, and its index
- *   dist_b, idx_b  device float/int32 [T,Nb] out: min over a, and its index
+ *   dist_b, idx_b  device float/int32 [T,Nb] out: min over a, and its index; with
+ *             DC_RED_SIM2REAL_SUM both may be NULL (together): then only the a -> b direction
+ *             is searched, which is all that Eq. 2 and its gradient to a need
  *   loss      device double [T] out: loss[t] = w_t (alpha sum_i dist_a + beta sum_j dist_b),
  *             alpha = 1/Na, beta = 1/Nb for Eq. 1; alpha = 1, beta = 0 for Eq. 2.
  * The neighbour of a point is decided by the canonical float squared distance
  *   d = fma(dz, dz, fma(dy, dy, dx*dx)), dx = ax - bx rounded to float,
- * ties going to the smallest index; dist_* hold that float d.  Both directions are always
- * computed (the backward of Eq. 1 needs idx_b); the loss sums the float distances in double.
- * Errors: DC_ERR_INVALID, DC_ERR_HIP, DC_ERR_NOMEM, DC_ERR_BUDGET. */
+ * ties going to the smallest index; dist_* hold that float d.  The loss sums the float distances
+ * in double.
+ * Errors: DC_ERR_INVALID (also: only one of dist_b / idx_b NULL, or NULL with Eq. 1), DC_ERR_HIP,
+ * DC_ERR_NOMEM, DC_ERR_BUDGET. */
 int dc_chamfer_fwd(dc_ctx *ctx, const float *a, const float *b, int T, int Na, int Nb,
                    int precision, int reduction, const float *frame_w, float *dist_a,
                    int32_t *idx_a, float *dist_b, int32_t *idx_b, double *loss, void *stream);
@@ -137,7 +140,8 @@ int dc_chamfer_fwd(dc_ctx *ctx, const float *a, const float *b, int T, int Na, i
  *   grad_b[t,j] = g_t w_t ( 2 beta (b_j - a_{idx_b[j]}) + 2 alpha sum_{i: idx_a[i]=j} (b_j - a_i) )
  * The sums over j (resp. i) run in increasing index order after a stable, atomic-free sort by
  * neighbour index, so results are bitwise reproducible.
- *   grad_loss device double [T]; a, b, idx_a, idx_b, frame_w as in dc_chamfer_fwd;
+ *   grad_loss device double [T]; a, b, idx_a, idx_b, frame_w as in dc_chamfer_fwd (idx_b is not
+ *   read with DC_RED_SIM2REAL_SUM, where beta = 0, and may then be NULL);
  *   grad_a device float [T,Na,3] out (overwritten); grad_b device float [T,Nb,3] or NULL.
  * Errors: DC_ERR_INVALID, DC_ERR_HIP, DC_ERR_NOMEM, DC_ERR_BUDGET. */
 int dc_chamfer_bwd(dc_ctx *ctx, const double *grad_loss, const float *a, const float *b,

@@ -232,8 +232,9 @@ def sample_surface_bwd(grad_points, faces, face_idx, bary, V: int, out=None, ctx
 
 
 def chamfer_fwd(a, b, precision: int = DC_PREC_FP32, reduction: int = DC_RED_BIDIR_MEAN,
-                frame_w=None, out=None, ctx=None, stream=None):
-    """dc_chamfer_fwd: returns dict(dist_a, idx_a, dist_b, idx_b, loss)."""
+                frame_w=None, out=None, ctx=None, stream=None, b_side: bool = True):
+    """dc_chamfer_fwd: returns dict(dist_a, idx_a, dist_b, idx_b, loss).  With the
+    unidirectional reduction, b_side=False searches only a -> b (dist_b, idx_b are None)."""
     ctx = ctx or default_context(a.device.index)
     T, Na, _ = a.shape
     Nb = b.shape[1]
@@ -241,8 +242,8 @@ def chamfer_fwd(a, b, precision: int = DC_PREC_FP32, reduction: int = DC_RED_BID
     if out is None:
         out = dict(dist_a=torch.empty((T, Na), dtype=torch.float32, device=dev),
                    idx_a=torch.empty((T, Na), dtype=torch.int32, device=dev),
-                   dist_b=torch.empty((T, Nb), dtype=torch.float32, device=dev),
-                   idx_b=torch.empty((T, Nb), dtype=torch.int32, device=dev),
+                   dist_b=torch.empty((T, Nb), dtype=torch.float32, device=dev) if b_side else None,
+                   idx_b=torch.empty((T, Nb), dtype=torch.int32, device=dev) if b_side else None,
                    loss=torch.empty((T,), dtype=torch.float64, device=dev))
     rc = load().dc_chamfer_fwd(
         ctx.handle, _ptr(a, torch.float32, (T, Na, 3), "a"), _ptr(b, torch.float32, (T, Nb, 3), "b"),

@@ -1,8 +1,9 @@
 """torch.autograd.Function over the C ABI: sampling (Eq. 3) + Chamfer (Eq. 1/2) forward, and the
 backward through the saved neighbours and Eq. 4 to the mesh vertices.
 
-The forward saves the face choice, barycentric weights, sampled points and both neighbour index
-arrays; the backward never recomputes them.
+The forward saves the face choice, barycentric weights, sampled points and the neighbour index
+arrays (only a -> b for the unidirectional loss, which needs nothing else); the backward never
+recomputes them.
 """
 from __future__ import annotations
 
@@ -24,10 +25,14 @@ class DiffCloudChamfer(torch.autograd.Function):
         v = verts.detach().contiguous()
         obs = observed.detach().contiguous()
         points, face_idx, bary = _lib.sample_surface(v, faces, n_sim, seed=seed, uniforms=uniforms)
+        # the unidirectional loss (Eq. 2) needs only the a -> b search
+        b_side = reduction != _lib.DC_RED_SIM2REAL_SUM
         out = _lib.chamfer_fwd(points, obs, precision=precision, reduction=reduction,
-                               frame_w=frame_w)
-        ctx.save_for_backward(faces, obs, points, face_idx, bary, out["idx_a"], out["idx_b"],
+                               frame_w=frame_w, b_side=b_side)
+        idx_b = out["idx_b"] if b_side else torch.empty(0, dtype=torch.int32)
+        ctx.save_for_backward(faces, obs, points, face_idx, bary, out["idx_a"], idx_b,
                               frame_w if frame_w is not None else torch.empty(0))
+        ctx.b_side = b_side
         ctx.V = v.shape[1]
         ctx.reduction = reduction
         ctx.has_w = frame_w is not None
@@ -40,7 +45,8 @@ class DiffCloudChamfer(torch.autograd.Function):
         fw = fw if ctx.has_w else None
         want_b = ctx.needs_input_grad[2]
         ga, gb = _lib.chamfer_bwd(grad_loss.detach().to(torch.float64).contiguous(), points, obs,
-                                  idx_a, idx_b, reduction=ctx.reduction, frame_w=fw, want_b=want_b)
+                                  idx_a, idx_b if ctx.b_side else None, reduction=ctx.reduction,
+                                  frame_w=fw, want_b=want_b)
         gv = _lib.sample_surface_bwd(ga, faces, face_idx, bary, ctx.V)
         return gv, None, gb, None, None, None, None, None, None
 

@@ -145,6 +145,7 @@ int enqueue_chamfer_fwd(dc_ctx *prof, const float *a, const float *b, int T, int
                         int precision, int reduction, const float *frame_w, float *dist_a,
                         int32_t *idx_a, float *dist_b, int32_t *idx_b, double *loss,
                         char *scratch, unsigned long long *stats, hipStream_t s) {
+    // idx_b == NULL: the unidirectional loss (Eq. 2) needs only the a -> b direction
     if (precision == DC_PREC_BF16_REFINE) {
         launch_chamfer_screened(a, Na, b, Nb, T, idx_a, dist_a, idx_b, dist_b, scratch, stats,
                                 prof, s);
@@ -153,7 +154,7 @@ int enqueue_chamfer_fwd(dc_ctx *prof, const float *a, const float *b, int T, int
             ProfScope ps(prof, 0, s);
             launch_nn_exact_ws(a, Na, b, Nb, T, idx_a, dist_a, scratch, s);
         }
-        {
+        if (idx_b) {
             ProfScope ps(prof, 0, s);
             launch_nn_exact_ws(b, Nb, a, Na, T, idx_b, dist_b, scratch, s);
         }
@@ -341,8 +342,14 @@ int dc_chamfer_fwd(dc_ctx *ctx, const float *a, const float *b, int T, int Na, i
                    int precision, int reduction, const float *frame_w, float *dist_a,
                    int32_t *idx_a, float *dist_b, int32_t *idx_b, double *loss, void *stream) {
     clear_error();
-    if (!ctx || !a || !b || !dist_a || !idx_a || !dist_b || !idx_b || !loss) {
+    if (!ctx || !a || !b || !dist_a || !idx_a || !loss) {
         set_error("dc_chamfer_fwd: NULL argument");
+        return DC_ERR_INVALID;
+    }
+    if ((dist_b == nullptr) != (idx_b == nullptr) ||
+        (!idx_b && reduction != DC_RED_SIM2REAL_SUM)) {
+        set_error("dc_chamfer_fwd: dist_b and idx_b may be NULL (together) only for the "
+                  "unidirectional reduction");
         return DC_ERR_INVALID;
     }
     if (precision != DC_PREC_FP32 && precision != DC_PREC_BF16_REFINE) {
@@ -374,8 +381,12 @@ int dc_chamfer_bwd(dc_ctx *ctx, const double *grad_loss, const float *a, const f
                    int reduction, const float *frame_w, float *grad_a, float *grad_b,
                    void *stream) {
     clear_error();
-    if (!ctx || !grad_loss || !a || !b || !idx_a || !idx_b || !grad_a) {
+    if (!ctx || !grad_loss || !a || !b || !idx_a || !grad_a) {
         set_error("dc_chamfer_bwd: NULL argument");
+        return DC_ERR_INVALID;
+    }
+    if (!idx_b && reduction != DC_RED_SIM2REAL_SUM) {
+        set_error("dc_chamfer_bwd: idx_b may be NULL only for the unidirectional reduction");
         return DC_ERR_INVALID;
     }
     if (reduction != DC_RED_BIDIR_MEAN && reduction != DC_RED_SIM2REAL_SUM) {

@@ -58,8 +58,10 @@ __device__ __forceinline__ void chamfer_bwd_body(const ChamferBwdParams &pr, con
     const float *yt = Y + (size_t)t * Ny * 3;
     const float x0 = xt[3 * (size_t)i], x1 = xt[3 * (size_t)i + 1], x2 = xt[3 * (size_t)i + 2];
     float g0 = 0.f, g1 = 0.f, g2 = 0.f;
-    const int jn = nn_x[(size_t)t * Nx + i];
-    if (cs != 0.f && (unsigned)jn < (unsigned)Ny) {  // indices outside [0, Ny) contribute nothing
+    // the own-neighbour term exists only when cs != 0 (nn_x may be NULL otherwise: the b side of
+    // the unidirectional loss has no neighbour indices)
+    const int jn = (cs != 0.f) ? nn_x[(size_t)t * Nx + i] : -1;
+    if ((unsigned)jn < (unsigned)Ny) {  // indices outside [0, Ny) contribute nothing
         const int j = jn;
         g0 = cs * (x0 - yt[3 * (size_t)j]);
         g1 = cs * (x1 - yt[3 * (size_t)j + 1]);

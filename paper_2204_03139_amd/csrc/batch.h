@@ -44,6 +44,7 @@ enum KernelType : int {
     KT_NORM_MAX,
     KT_PACK,
     KT_SCREEN,
+    KT_SCREEN_ROWS,
     KT_REFINE,
     KT_COLMERGE,
     KT_COLREFINE,

@@ -96,9 +96,10 @@ void fill_f64(double *p, int n, double v, hipStream_t s) {
         KT_SS_SCAN, KT_SS_SCATTER, KT_SS_HIST, KT_SS_SCAN, KT_SS_SCATTER
 const int PROGRAM[] = {
     KT_FILL_U32,  KT_AREA_CDF, KT_SAMPLE,                                      // sampling
-    KT_NORM_MAX,  KT_NORM_MAX, KT_PACK,     KT_SCREEN, KT_REFINE, KT_COLMERGE,  // screen
-    KT_COLREFINE, KT_NN8,      KT_NN4,      KT_NN1,    KT_NN_MERGE,            // exact a -> b
-    KT_NN8,       KT_NN4,      KT_NN1,      KT_NN_MERGE,                       // exact b -> a
+    KT_NORM_MAX,  KT_NORM_MAX, KT_PACK,     KT_SCREEN, KT_SCREEN_ROWS, KT_REFINE,  // screen
+    KT_NN8,       KT_NN4,      KT_NN1,      KT_NN_MERGE,   // exact a -> b (or its heavy rows)
+    KT_COLMERGE,  KT_COLREFINE,                            // screen, columns
+    KT_NN8,       KT_NN4,      KT_NN1,      KT_NN_MERGE,   // exact b -> a (or its heavy columns)
     KT_LOSS,      KT_FILL_F64, SORT_PASSES, KT_CHAMFER_BWD,                    // Chamfer bwd
     SORT_PASSES,  KT_BOUNDS,   SORT_PASSES, KT_BOUNDS,  KT_FACE_GRAD, KT_VERTEX_GRAD};
 #undef SORT_PASSES
@@ -185,13 +186,15 @@ int issue_request(const Req *r, const Layout &L, unsigned long long *stats) {
     int rc = enqueue_sample(nullptr, L.verts, L.faces, T, V, F, Na, r->seed, nullptr, L.pts,
                             L.fidx, L.bary, sar, L.status, s);
     if (rc) return rc;
+    // the unidirectional loss needs neither the b -> a search nor its indices
+    const bool cols = r->reduction != DC_RED_SIM2REAL_SUM;
     rc = enqueue_chamfer_fwd(nullptr, L.pts, L.obs, T, Na, Nb, r->precision, r->reduction,
-                             r->has_w ? L.fw : nullptr, L.da, L.ia, L.db, L.ib, L.loss, L.scratch,
-                             stats, s);
+                             r->has_w ? L.fw : nullptr, L.da, L.ia, cols ? L.db : nullptr,
+                             cols ? L.ib : nullptr, L.loss, L.scratch, stats, s);
     if (rc) return rc;
     if (r->want_grad) {
         fill_f64(L.gl, T, 1.0, s);
-        launch_chamfer_bwd(L.gl, L.pts, L.obs, L.ia, L.ib, T, Na, Nb, r->reduction,
+        launch_chamfer_bwd(L.gl, L.pts, L.obs, L.ia, cols ? L.ib : nullptr, T, Na, Nb, r->reduction,
                            r->has_w ? L.fw : nullptr, L.gpts, nullptr, L.scratch, s);
         launch_sample_bwd(L.gpts, L.faces, L.fidx, L.bary, T, V, F, Na, L.gverts, L.scratch, s);
     }

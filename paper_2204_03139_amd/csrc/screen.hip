@@ -887,6 +887,8 @@ void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int
     pk.Np = Nb;
     pk.Np_pad = Nb_pad;
     dispatch(KT_PACK, k_pack_targets, dim3(Nb_pad / 256, T), 256, pk, s);
+    // without b outputs (the unidirectional loss) only the row direction is screened
+    const bool cols = idx_b != nullptr;
     {
         ProfScope ps(prof, 0, s);
         ScreenParams sp;
@@ -902,7 +904,10 @@ void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int
         sp.Nq = Na;
         sp.Np = Nb;
         sp.Np_pad = Nb_pad;
-        dispatch(KT_SCREEN, k_screen<true>, dim3(nwg, T), SC_THREADS, sp, s);
+        if (cols)
+            dispatch(KT_SCREEN, k_screen<true>, dim3(nwg, T), SC_THREADS, sp, s);
+        else
+            dispatch(KT_SCREEN_ROWS, k_screen<false>, dim3(nwg, T), SC_THREADS, sp, s);
     }
     {
         ProfScope ps(prof, 1, s);
@@ -917,6 +922,8 @@ void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int
         rp.Np = Nb;
         dispatch(KT_REFINE, k_refine, dim3((Na + RF_QUERIES - 1) / RF_QUERIES, T), RF_THREADS, rp,
                  s);
+        launch_nn_exact_list(a, Na, b, Nb, T, hlist_a, hcnt_a, idx_a, dist_a, exact_scratch, s);
+        if (!cols) return;
         ColmergeParams cm;
         cm.P = b;
         cm.cpart = cpart;
@@ -941,7 +948,6 @@ void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int
         cr.Np = Na;
         dispatch(KT_COLREFINE, k_colrefine, dim3((Nb + RF_QUERIES - 1) / RF_QUERIES, T),
                  RF_THREADS, cr, s);
-        launch_nn_exact_list(a, Na, b, Nb, T, hlist_a, hcnt_a, idx_a, dist_a, exact_scratch, s);
         launch_nn_exact_list(b, Nb, a, Na, T, hlist_b, hcnt_b, idx_b, dist_b, exact_scratch, s);
     }
 }
@@ -952,6 +958,7 @@ void register_screen_kernels(BatchedKernel *table) {
     // two screen workgroups per compute unit fit the batched kernel's registers (forcing three
     // spills registers and measured slower)
     table[KT_SCREEN] = batched_kernel<ScreenParams, screen_body<true>, SC_THREADS, 512>();
+    table[KT_SCREEN_ROWS] = batched_kernel<ScreenParams, screen_body<false>, SC_THREADS, 768>();
     table[KT_REFINE] = batched_kernel<RefineParams, refine_body, RF_THREADS, 2048>();
     table[KT_COLMERGE] = batched_kernel<ColmergeParams, colmerge_body, 256, 1024>();
     table[KT_COLREFINE] = batched_kernel<RefineParams, colrefine_body, RF_THREADS, 2048>();

@@ -81,3 +81,21 @@ def test_autograd_saves_indices_and_skips_recompute():
     kt = ctx.kernel_times(reset=True)
     assert kt["all_pairs"][1] == 0 and kt["backward"][1] == 4
     assert torch.equal(g1, g2)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_autograd_unidirectional_loss(precision):
+    """Eq. 2 (the loss the paper optimises) through the Function: only a -> b is searched, and the
+    vertex gradient matches the oracle's analytic gradient of the summed Eq. 2 loss."""
+    p = gpu()
+    w = gen.workload(3)
+    verts = dev(w["verts"]).requires_grad_(True)
+    faces, obs = dev(w["faces"]), dev(w["observed"])
+    loss = p.diffcloud_loss(verts, faces, obs, w["Na"], seed=w["seed"], precision=precision,
+                            reduction=1)
+    loss.backward()
+    pts, fi, ba = oracle.sample_surface(w["verts"], faces=w["faces"], N=w["Na"], seed=w["seed"])
+    ogv, ogva, och = oracle.full_gradient(w["verts"], w["faces"], w["observed"], fi, ba, pts,
+                                          reduction=1)
+    assert abs(loss.item() - och["loss"].sum()) <= 1e-5 * och["loss"].sum()
+    assert_grad(host(verts.grad), ogv, ogva, what="Eq. 2 autograd vs oracle")

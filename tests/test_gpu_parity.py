@@ -184,6 +184,49 @@ def test_loss_reductions_and_weights(reduction, precision):
     _check_chamfer(g, o)
 
 
+@pytest.mark.parametrize("case", ["cfg1", "cfg2-3frames", "ragged-1000x4097", "slices-2x20000"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_unidirectional_fast_path(case, precision):
+    """Eq. 2 with the b outputs omitted searches only a -> b (the bf16 path runs its row-only
+    screen): idx_a / dist_a equal the oracle bit for bit, the loss matches, and both equal the
+    bidirectional call's; the gradient to a needs no idx_b."""
+    p = gpu()
+    A, B = CHAMFER_CASES[case]()
+    say(f"[chamfer] unidirectional {case} precision={precision}")
+    w = np.linspace(0.5, 1.5, A.shape[0]).astype(np.float32)
+    g1 = p.chamfer_fwd(dev(A), dev(B), precision=precision, reduction=1, frame_w=dev(w),
+                       b_side=False)
+    g2 = p.chamfer_fwd(dev(A), dev(B), precision=precision, reduction=1, frame_w=dev(w))
+    gl = torch.full((A.shape[0],), 2.0, dtype=torch.float64, device="cuda")
+    ga1, gb1 = p.chamfer_bwd(gl, dev(A), dev(B), g1["idx_a"], None, reduction=1, frame_w=dev(w),
+                             want_b=True)
+    ga2, gb2 = p.chamfer_bwd(gl, dev(A), dev(B), g2["idx_a"], g2["idx_b"], reduction=1,
+                             frame_w=dev(w), want_b=True)
+    torch.cuda.synchronize()
+    assert g1["idx_b"] is None and g1["dist_b"] is None
+    o = oracle.chamfer(A, B, 1, w)
+    assert np.array_equal(host(g1["idx_a"]), o["idx_a"])
+    assert np.array_equal(host(g1["dist_a"]).view(np.uint32), o["d32a"].view(np.uint32))
+    assert_rel(host(g1["loss"]), o["loss"], 1e-5, "loss")
+    assert np.array_equal(host(g1["loss"]).view(np.uint64), host(g2["loss"]).view(np.uint64))
+    assert torch.equal(ga1, ga2) and torch.equal(gb1, gb2)
+    og = oracle.chamfer_grad(A, B, o["idx_a"], o["idx_b"], 1, w, np.full(A.shape[0], 2.0),
+                             want_b=True)
+    assert_grad(host(ga1), og["ga"], og["ga_abs"], what="grad a")
+    assert_grad(host(gb1), og["gb"], og["gb_abs"], what="grad b")
+
+
+def test_unidirectional_argument_checks():
+    p = gpu()
+    A = dev(np.zeros((1, 8, 3), np.float32))
+    with pytest.raises(p.DCError):  # Eq. 1 needs the b side
+        p.chamfer_fwd(A, A, reduction=0, b_side=False)
+    ia = torch.zeros((1, 8), dtype=torch.int32, device="cuda")
+    gl = torch.ones(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(p.DCError):
+        p.chamfer_bwd(gl, A, A, ia, None, reduction=0)
+
+
 def test_screen_candidates_are_few():
     """The bf16 screen's certificate must leave only a handful of candidate groups per query and
     rarely fall back to an exhaustive search (otherwise the screen would be pointless)."""
