@@ -118,19 +118,25 @@ def run_path(p, torch, w, precision, steps, warmup, reduction=0):
     ctx.sync()
     stats = ctx.stats()
     loss = fwd["loss"].sum().item()
-    return ms, kt, stats, loss
+    outs = dict(points=pts, idx_a=fwd["idx_a"], dist_a=fwd["dist_a"], idx_b=fwd["idx_b"],
+                dist_b=fwd["dist_b"], loss=fwd["loss"], grad_verts=gv)
+    return ms, kt, stats, loss, outs
 
 
-def cpu_baseline(w, seconds):
+def cpu_baseline(w, seconds, gpu=None):
     """Time the oracle (as it stands) on a bounded sample of the workload: whole frames in order
     (sampling, both nearest-neighbour directions searched exhaustively, the gradient formulas)
-    until about `seconds` of wall time; report point pairs per second."""
+    until about `seconds` of wall time; report point pairs per second.  Afterwards (untimed) the
+    GPU results of the reported path on the same frames are compared with the oracle's: points
+    and neighbour indices exactly, distances and losses against the double-precision twins,
+    vertex gradients relative to the sum of absolute contributions."""
     import oracle
     threads = oracle.max_threads()
     faces = w["faces"]
     Na, Nb = w["Na"], w["Nb"]
     pairs = 0.0
     frames = 0
+    kept = []
     t0 = time.perf_counter()
     for t in range(w["T"]):
         pts, fi, ba = oracle.sample_surface(w["verts"][t:t + 1], faces, Na,
@@ -140,13 +146,35 @@ def cpu_baseline(w, seconds):
         oracle.sample_grad(g["ga"], faces, fi, ba, w["V"])
         pairs += float(Na) * Nb
         frames += 1
+        kept.append((pts, fi, ba, ch, g))
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
-    return dict(value=pairs / dt, unit="point-pairs/s", cores=threads, kind="oracle",
+    base = dict(value=pairs / dt, unit="point-pairs/s", cores=threads, kind="oracle",
                 sample=f"the first {frames} of {w['T']} frames of the workload, each fully "
                        f"processed (sampling, exhaustive nearest neighbours both ways, gradients): "
                        f"{pairs:.3e} pairs in {dt:.1f} s on {threads} threads")
+    if gpu is None:
+        return base, None
+    h = {k: v[:frames].cpu().numpy() for k, v in gpu.items() if v is not None}
+    acc = dict(frames=frames, point_mismatches=0, idx_a_mismatches=0, idx_b_mismatches=0,
+               dist_max_rel_err_vs_f64=0.0, loss_max_rel_err=0.0, grad_max_err_rel_to_abs_sum=0.0)
+    for t, (pts, fi, ba, ch, g) in enumerate(kept):
+        acc["point_mismatches"] += int((h["points"][t].view(np.uint32)
+                                        != pts[0].view(np.uint32)).any(axis=-1).sum())
+        acc["idx_a_mismatches"] += int((h["idx_a"][t] != ch["idx_a"][0]).sum())
+        acc["idx_b_mismatches"] += int((h["idx_b"][t] != ch["idx_b"][0]).sum())
+        for d, d64 in ((h["dist_a"][t], ch["d64a"][0]), (h["dist_b"][t], ch["d64b"][0])):
+            nz = d64 > 0
+            rel = np.abs(d[nz] - d64[nz]) / d64[nz]
+            acc["dist_max_rel_err_vs_f64"] = max(acc["dist_max_rel_err_vs_f64"], float(rel.max()))
+        acc["loss_max_rel_err"] = max(acc["loss_max_rel_err"],
+                                      float(abs(h["loss"][t] - ch["loss"][0]) / ch["loss"][0]))
+        gv, gva = oracle.sample_grad(g["ga"], faces, fi, ba, w["V"], g["ga_abs"])
+        err = np.abs(h["grad_verts"][t] - gv[0]) / np.maximum(gva[0], 1e-300)
+        acc["grad_max_err_rel_to_abs_sum"] = max(acc["grad_max_err_rel_to_abs_sum"],
+                                                 float(err.max()))
+    return base, acc
 
 
 def _frame_words(oracle, seed, t, N):
@@ -250,6 +278,7 @@ def main():
     T, Na, Nb = w["T"], w["Na"], w["Nb"]
     pairs = float(T) * Na * Nb
     paths = {}
+    gpu_outs = {}
     todo = {"fp32": [0], "bf16": [1], "both": [0, 1]}[a.precision]
     # the headline is the bidirectional loss (Eq. 1); the unidirectional loss the paper optimises
     # (Eq. 2, one search direction) is reported beside it for the fastest precision
@@ -258,7 +287,10 @@ def main():
         runs.append(("fp32_eq2" if max(todo) == 0 else "bf16_refine_eq2", max(todo), 1))
     for name, prec, red in runs:
         try:
-            ms, kt, stats, loss = run_path(p, torch, w, prec, a.steps, a.warmup, reduction=red)
+            ms, kt, stats, loss, outs = run_path(p, torch, w, prec, a.steps, a.warmup,
+                                                 reduction=red)
+            if red == 0:
+                gpu_outs[name] = outs
         except p.DCError as e:
             paths[name] = dict(error=str(e))
             continue
@@ -318,7 +350,8 @@ def main():
     if not a.no_serving:
         line["serving"] = run_serving(p, torch)
     if a.cpu_seconds > 0:
-        line["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
+        line["cpu_baseline"], line["accuracy_vs_oracle"] = cpu_baseline(
+            w, a.cpu_seconds, {k: v for k, v in gpu_outs.items() if k == best}.get(best))
     print(json.dumps(line), flush=True)
 
 
