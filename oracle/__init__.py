@@ -55,8 +55,8 @@ def lib():
         L.orc_pick_face.restype = _i
         L.orc_barycentric.argtypes = [_f32p, _f32p, _f32p, ctypes.c_uint32, ctypes.c_uint32,
                                       _f32p, _f32p]
-        L.orc_sample_surface.argtypes = [_f32p, _i32p, _i, _i, _i, _i, _u32p, _f32p, _i32p,
-                                         _f32p, _vp, _vp]
+        L.orc_sample_surface.argtypes = [_f32p, _i32p, _i, _i, _i, _i, _u32p, _vp, ctypes.c_long,
+                                         _f32p, _i32p, _f32p, _vp, _vp]
         L.orc_sample_surface.restype = _i
         L.orc_nearest.argtypes = [_f32p, _i, _f32p, _i, _i32p, _f32p, _f64p, _i]
         L.orc_chamfer.argtypes = [_f32p, _f32p, _i, _i, _i, _i, _vp, _i32p, _f32p, _f64p, _i32p,
@@ -139,8 +139,10 @@ def barycentric(p1, p2, p3, w_r1: int, w_r2: int):
 
 
 def sample_surface(verts, faces, N: int, words=None, seed: int | None = None,
-                   return_cdf: bool = False):
-    """Area-weighted sampling of N points per frame: returns points, face_idx, bary."""
+                   return_cdf: bool = False, face_mask=None):
+    """Area-weighted sampling of N points per frame: returns points, face_idx, bary.
+    face_mask (optional, [F] or [T,F], nonzero = may be drawn) restricts the draws to a subset of
+    faces, each keeping its area weight (Sec. IV: occlusion heuristic, cloth-only clouds)."""
     v = _c(verts, np.float32)
     if v.ndim == 2:
         v = v[None]
@@ -155,7 +157,14 @@ def sample_surface(verts, faces, N: int, words=None, seed: int | None = None,
     ba = np.zeros((T, N, 3), np.float32)
     A = np.zeros((T, F), np.float64)
     C = np.zeros((T, F), np.float64)
-    rc = lib().orc_sample_surface(v, f, T, V, F, N, w, pts, fi, ba, _ptr(A), _ptr(C))
+    m, stride = None, 0
+    if face_mask is not None:
+        m = np.ascontiguousarray(face_mask, np.uint8)
+        if m.shape not in ((F,), (T, F)):
+            raise ValueError("face_mask must be [F] or [T,F]")
+        stride = F if m.ndim == 2 else 0
+    rc = lib().orc_sample_surface(v, f, T, V, F, N, w, _ptr(m), stride, pts, fi, ba, _ptr(A),
+                                  _ptr(C))
     if rc != 0:
         raise OracleError(f"sample_surface: status {rc}")
     if return_cdf:

@@ -153,9 +153,13 @@ void orc_barycentric(const float *p1, const float *p2, const float *p3, uint32_t
 }
 
 /* Sample N points per frame from a [T,V,3] mesh trajectory with fixed faces [F,3]. */
+/* mask (optional): nonzero = the face may be drawn.  A face outside the subset takes part with
+ * area 0, so it is never chosen (the subset sampling of Sec. IV: occlusion, cloth-only clouds).
+ * mask_stride 0 shares one [F] mask across frames; F gives one mask row per frame. */
 int orc_sample_surface(const float *verts, const int32_t *faces, int T, int V, int F, int N,
-                       const uint32_t *words, float *points, int32_t *face_idx, float *bary,
-                       double *areas_out, double *cdf_out) {
+                       const uint32_t *words, const uint8_t *mask, long mask_stride,
+                       float *points, int32_t *face_idx, float *bary, double *areas_out,
+                       double *cdf_out) {
     if (T <= 0 || V <= 0 || F <= 0 || N <= 0) return ORC_ERR_INVALID;
     double *A = (double *)malloc(sizeof(double) * (size_t)F);
     double *C = (double *)malloc(sizeof(double) * (size_t)F);
@@ -164,6 +168,9 @@ int orc_sample_surface(const float *verts, const int32_t *faces, int T, int V, i
         const float *vt = verts + (size_t)t * V * 3;
         int rc = orc_face_areas(vt, faces, V, F, A);
         if (rc != ORC_OK) { status = rc; break; }
+        if (mask)
+            for (int f = 0; f < F; ++f)
+                if (!mask[(size_t)t * mask_stride + f]) A[f] = 0.0;
         rc = orc_area_cdf(A, F, C);
         if (areas_out) memcpy(areas_out + (size_t)t * F, A, sizeof(double) * F);
         if (cdf_out) memcpy(cdf_out + (size_t)t * F, C, sizeof(double) * F);

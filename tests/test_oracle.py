@@ -132,6 +132,70 @@ def test_sampler_matches_brute_force():
             assert list(map(float, ba[t, i])) == b
 
 
+def test_masked_sampler_matches_brute_force():
+    """Subset sampling (Sec. IV): faces outside the mask take part with area 0.  Checked against
+    exact brute force on the masked areas, for a shared [F] mask and a per-frame [T,F] mask that
+    leaves runs of consecutive excluded faces."""
+    verts, faces = gen.trajectory(5, 2, 5)
+    F = len(faces)
+    words = gen.sim_uniform_words(2, 60, 6)
+    shared = (np.arange(F) % 3 != 1).astype(np.uint8)
+    per_frame = np.stack([(np.arange(F) // 4) % 2 == t for t in range(2)]).astype(np.uint8)
+    for mask in (shared, per_frame):
+        pts, fi, ba, A, C = oracle.sample_surface(verts, faces, 60, words=words, return_cdf=True,
+                                                  face_mask=mask)
+        for t in range(2):
+            m = mask if mask.ndim == 1 else mask[t]
+            areas = [brute.tri_area(*(verts[t][faces[f][c]] for c in range(3))) if m[f] else 0.0
+                     for f in range(F)]
+            assert np.array_equal(np.array(areas), A[t])
+            assert not np.any(m[fi[t]] == 0)  # never an excluded face
+            for i in range(60):
+                w = [int(x) for x in words[t, i]]
+                f = brute.pick_face(areas, w[0], w[1])
+                assert f == fi[t, i]
+                x, b = brute.barycentric(*(verts[t][faces[f][c]] for c in range(3)), w[2], w[3])
+                assert list(map(float, pts[t, i])) == x
+
+
+def test_masked_face_choice_hand_example():
+    """Areas (1, 2, 3) with the middle face excluded: the CDF is (1, 1, 4), so r = 1/4 (target
+    exactly 1) must skip the excluded face and pick face 2; r just below 1/4 picks face 0."""
+    verts = np.array([[0, 0, 0], [1, 0, 0], [0, 2, 0],      # area 1
+                      [0, 0, 1], [2, 0, 1], [0, 2, 1],      # area 2
+                      [0, 0, 2], [3, 0, 2], [0, 2, 2]],     # area 3
+                     np.float32)
+    faces = np.array([[0, 1, 2], [3, 4, 5], [6, 7, 8]], np.int32)
+    # r = (w >> 11) 2^-53 for the 64-bit word w = (hi << 32) | lo
+    quarter = (1 << 51) << 11              # r = 2^51 2^-53 = 1/4
+    below = ((1 << 51) - 1) << 11          # one 53-bit step below 1/4
+    words = np.zeros((1, 2, 4), np.uint32)
+    for i, w in enumerate((quarter, below)):
+        words[0, i, 0] = w & 0xFFFFFFFF
+        words[0, i, 1] = w >> 32
+    _, fi, _, A, C = oracle.sample_surface(verts, faces, 2, words=words, return_cdf=True,
+                                           face_mask=np.array([1, 0, 1], np.uint8))
+    assert list(A[0]) == [1.0, 0.0, 3.0] and list(C[0]) == [1.0, 1.0, 4.0]
+    assert list(fi[0]) == [2, 0]
+
+
+def test_masked_sampler_statistics_and_empty_mask():
+    from scipy import stats
+    verts, faces = gen.trajectory(8, 1, 7, sag=0.0)
+    F = len(faces)
+    # upper half of the cloth (y > 0), as in the occlusion heuristic of the fold scenario
+    upper = (verts[0][faces][:, :, 1].mean(axis=1) > 0).astype(np.uint8)
+    N = 100_000
+    _, fi, _ = oracle.sample_surface(verts, faces, N, seed=77, face_mask=upper)
+    A = oracle.face_areas(verts[0], faces) * upper
+    counts = np.bincount(fi[0], minlength=F)
+    assert counts[upper == 0].sum() == 0
+    keep = upper == 1
+    assert stats.chisquare(counts[keep], A[keep] / A.sum() * N).pvalue > 1e-4
+    with pytest.raises(oracle.OracleError):  # nothing left to draw from: zero total area
+        oracle.sample_surface(verts, faces, 4, seed=1, face_mask=np.zeros(F, np.uint8))
+
+
 def test_sqrt_words_exhaustive_sample():
     # every r1 word maps through a correctly rounded float square root; spot-check a spread
     # of the 2^24 levels against the exact-rational rounding
