@@ -99,6 +99,20 @@ int dc_sample_surface(dc_ctx *ctx, const float *verts, const int32_t *faces, int
                       int N, uint64_t seed, const uint32_t *uniforms, float *points,
                       int32_t *face_idx, float *bary, void *stream);
 
+/* dc_sample_surface restricted to a subset of the faces (the subset sampling of Sec. IV: the
+ * occlusion heuristic that samples only the visible part of the cloth, cloth-only clouds of a
+ * scene, biased subsets that mimic partial observations).
+ *   face_mask      device uint8, nonzero = the face may be drawn: [F] shared by all frames
+ *                  (mask_per_frame = 0) or [T,F] one row per frame (mask_per_frame = 1)
+ * A face outside the subset takes part with A_f = 0 in the running sum, so it is never drawn and
+ * the other faces keep their area weights; everything else is as in dc_sample_surface.  A frame
+ * whose subset has zero total area is reported by dc_sync() like any degenerate frame.
+ * Errors: as dc_sample_surface; DC_ERR_INVALID also for a NULL mask or mask_per_frame not 0/1. */
+int dc_sample_surface_masked(dc_ctx *ctx, const float *verts, const int32_t *faces, int T, int V,
+                             int F, int N, uint64_t seed, const uint32_t *uniforms,
+                             const uint8_t *face_mask, int mask_per_frame, float *points,
+                             int32_t *face_idx, float *bary, void *stream);
+
 /* Backward of dc_sample_surface through Eq. 4 (dx_i/dp_{i,c} = bary_c(i) I):
  *   grad_verts[t,v] = sum over points i of frame t and corners c with faces[face_idx[t,i]][c]==v
  *                     of bary[t,i,c] * grad_points[t,i].

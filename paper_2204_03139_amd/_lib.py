@@ -34,6 +34,7 @@ STATUS_NAMES = {0: "DC_OK", 1: "DC_PENDING", -1: "DC_ERR_INVALID", -2: "DC_ERR_N
 
 # every symbol the public header declares
 EXPORTS = ["dc_create", "dc_destroy", "dc_last_error", "dc_sync", "dc_sample_surface",
+           "dc_sample_surface_masked",
            "dc_sample_surface_bwd", "dc_chamfer_fwd", "dc_chamfer_bwd", "dc_get_stats",
            "dc_submit", "dc_poll", "dc_version", "dc_debug_fail_allocs", "dc_profile",
            "dc_get_kernel_times", "dc_request_bytes"]
@@ -89,6 +90,7 @@ def load():
     L.dc_last_error.restype = ctypes.c_char_p
     L.dc_sync.argtypes = [vp, vp]
     L.dc_sample_surface.argtypes = [vp, vp, vp, i, i, i, i, u64, vp, vp, vp, vp, vp]
+    L.dc_sample_surface_masked.argtypes = [vp, vp, vp, i, i, i, i, u64, vp, vp, i, vp, vp, vp, vp]
     L.dc_sample_surface_bwd.argtypes = [vp, vp, vp, vp, vp, i, i, i, i, vp, vp]
     L.dc_chamfer_fwd.argtypes = [vp, vp, vp, i, i, i, i, i, vp, vp, vp, vp, vp, vp, vp]
     L.dc_chamfer_bwd.argtypes = [vp, vp, vp, vp, vp, vp, i, i, i, i, vp, vp, vp, vp]
@@ -193,8 +195,9 @@ def default_context(device: int | None = None) -> Context:
 
 
 def sample_surface(verts, faces, N: int, seed: int = 0, uniforms=None, out=None, ctx=None,
-                   stream=None):
-    """dc_sample_surface: returns (points [T,N,3], face_idx [T,N], bary [T,N,3])."""
+                   stream=None, face_mask=None):
+    """dc_sample_surface: returns (points [T,N,3], face_idx [T,N], bary [T,N,3]).  face_mask
+    (uint8 [F] or [T,F], nonzero = may be drawn) selects dc_sample_surface_masked."""
     ctx = ctx or default_context(verts.device.index)
     T, V, _ = verts.shape
     F = faces.shape[0]
@@ -204,14 +207,20 @@ def sample_surface(verts, faces, N: int, seed: int = 0, uniforms=None, out=None,
         bary = torch.empty((T, N, 3), dtype=torch.float32, device=verts.device)
     else:
         points, face_idx, bary = out
-    rc = load().dc_sample_surface(
-        ctx.handle, _ptr(verts, torch.float32, (T, V, 3), "verts"),
-        _ptr(faces, torch.int32, (F, 3), "faces"), T, V, F, N, seed & (2**64 - 1),
-        _words_ptr(uniforms, (T, N, 4)),
-        _ptr(points, torch.float32, (T, N, 3), "points"),
-        _ptr(face_idx, torch.int32, (T, N), "face_idx"),
-        _ptr(bary, torch.float32, (T, N, 3), "bary"), _stream(stream))
-    _check(rc, "dc_sample_surface")
+    outs = (_ptr(points, torch.float32, (T, N, 3), "points"),
+            _ptr(face_idx, torch.int32, (T, N), "face_idx"),
+            _ptr(bary, torch.float32, (T, N, 3), "bary"), _stream(stream))
+    ins = (ctx.handle, _ptr(verts, torch.float32, (T, V, 3), "verts"),
+           _ptr(faces, torch.int32, (F, 3), "faces"), T, V, F, N, seed & (2**64 - 1),
+           _words_ptr(uniforms, (T, N, 4)))
+    if face_mask is None:
+        rc = load().dc_sample_surface(*ins, *outs)
+        _check(rc, "dc_sample_surface")
+    else:
+        per_frame = face_mask.dim() == 2
+        m = _ptr(face_mask, torch.uint8, (T, F) if per_frame else (F,), "face_mask")
+        rc = load().dc_sample_surface_masked(*ins, m, int(per_frame), *outs)
+        _check(rc, "dc_sample_surface_masked")
     return points, face_idx, bary
 
 

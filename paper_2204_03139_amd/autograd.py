@@ -15,16 +15,17 @@ from . import _lib
 class DiffCloudChamfer(torch.autograd.Function):
     """loss[t] for a mesh trajectory verts [T,V,3] against an observed cloud [T,Nb,3].
 
-    apply(verts, faces, observed, n_sim, seed, precision, reduction, frame_w, uniforms)
+    apply(verts, faces, observed, n_sim, seed, precision, reduction, frame_w, uniforms, face_mask)
     returns the per-frame loss [T] (float64).  Gradients flow to verts (and to observed when it
-    requires grad)."""
+    requires grad).  face_mask (uint8 [F] or [T,F]) samples only a subset of the faces."""
 
     @staticmethod
     def forward(ctx, verts, faces, observed, n_sim, seed=0, precision=_lib.DC_PREC_FP32,
-                reduction=_lib.DC_RED_BIDIR_MEAN, frame_w=None, uniforms=None):
+                reduction=_lib.DC_RED_BIDIR_MEAN, frame_w=None, uniforms=None, face_mask=None):
         v = verts.detach().contiguous()
         obs = observed.detach().contiguous()
-        points, face_idx, bary = _lib.sample_surface(v, faces, n_sim, seed=seed, uniforms=uniforms)
+        points, face_idx, bary = _lib.sample_surface(v, faces, n_sim, seed=seed, uniforms=uniforms,
+                                                     face_mask=face_mask)
         # the unidirectional loss (Eq. 2) needs only the a -> b search
         b_side = reduction != _lib.DC_RED_SIM2REAL_SUM
         out = _lib.chamfer_fwd(points, obs, precision=precision, reduction=reduction,
@@ -48,11 +49,11 @@ class DiffCloudChamfer(torch.autograd.Function):
                                   idx_a, idx_b if ctx.b_side else None, reduction=ctx.reduction,
                                   frame_w=fw, want_b=want_b)
         gv = _lib.sample_surface_bwd(ga, faces, face_idx, bary, ctx.V)
-        return gv, None, gb, None, None, None, None, None, None
+        return gv, None, gb, None, None, None, None, None, None, None
 
 
 def diffcloud_loss(verts, faces, observed, n_sim, seed=0, precision=_lib.DC_PREC_FP32,
-                   reduction=_lib.DC_RED_BIDIR_MEAN, frame_w=None, uniforms=None):
+                   reduction=_lib.DC_RED_BIDIR_MEAN, frame_w=None, uniforms=None, face_mask=None):
     """Sum over frames of the per-frame loss (a scalar, float64)."""
     return DiffCloudChamfer.apply(verts, faces, observed, n_sim, seed, precision, reduction,
-                                  frame_w, uniforms).sum()
+                                  frame_w, uniforms, face_mask).sum()

@@ -126,13 +126,14 @@ ProfScope::~ProfScope() {
 }
 
 int enqueue_sample(dc_ctx *prof, const float *verts, const int32_t *faces, int T, int V, int F,
-                   int N, uint64_t seed, const uint32_t *uniforms, float *points,
-                   int32_t *face_idx, float *bary, Arena &ar, unsigned *status, hipStream_t s) {
+                   int N, uint64_t seed, const uint32_t *uniforms, const uint8_t *mask,
+                   int mask_per_frame, float *points, int32_t *face_idx, float *bary, Arena &ar,
+                   unsigned *status, hipStream_t s) {
     double *cdf = ar.take<double>((size_t)T * F);
     int32_t *lastpos = ar.take<int32_t>((size_t)T);
     ProfScope ps(prof, 2, s);
-    launch_sample(verts, faces, T, V, F, N, seed, uniforms, points, face_idx, bary, cdf, lastpos,
-                  status, s);
+    launch_sample(verts, faces, T, V, F, N, seed, uniforms, mask, mask_per_frame, points,
+                  face_idx, bary, cdf, lastpos, status, s);
     return launched("sample_surface launch");
 }
 
@@ -299,9 +300,10 @@ int dc_debug_fail_allocs(dc_ctx *ctx, int n) {
     return DC_OK;
 }
 
-int dc_sample_surface(dc_ctx *ctx, const float *verts, const int32_t *faces, int T, int V, int F,
-                      int N, uint64_t seed, const uint32_t *uniforms, float *points,
-                      int32_t *face_idx, float *bary, void *stream) {
+static int sample_surface_impl(dc_ctx *ctx, const float *verts, const int32_t *faces, int T,
+                               int V, int F, int N, uint64_t seed, const uint32_t *uniforms,
+                               const uint8_t *mask, int mask_per_frame, float *points,
+                               int32_t *face_idx, float *bary, void *stream) {
     clear_error();
     if (!ctx || !verts || !faces || !points || !face_idx || !bary) {
         set_error("dc_sample_surface: NULL argument");
@@ -313,8 +315,29 @@ int dc_sample_surface(dc_ctx *ctx, const float *verts, const int32_t *faces, int
     std::lock_guard<std::mutex> g(ctx->mu);
     rc = arena_reserve(ctx, sample_scratch_bytes(T, F));
     if (rc) return rc;
-    return enqueue_sample(ctx, verts, faces, T, V, F, N, seed, uniforms, points, face_idx, bary,
-                          ctx->arena, ctx->d_status, static_cast<hipStream_t>(stream));
+    return enqueue_sample(ctx, verts, faces, T, V, F, N, seed, uniforms, mask, mask_per_frame,
+                          points, face_idx, bary, ctx->arena, ctx->d_status,
+                          static_cast<hipStream_t>(stream));
+}
+
+int dc_sample_surface(dc_ctx *ctx, const float *verts, const int32_t *faces, int T, int V, int F,
+                      int N, uint64_t seed, const uint32_t *uniforms, float *points,
+                      int32_t *face_idx, float *bary, void *stream) {
+    return sample_surface_impl(ctx, verts, faces, T, V, F, N, seed, uniforms, nullptr, 0, points,
+                               face_idx, bary, stream);
+}
+
+int dc_sample_surface_masked(dc_ctx *ctx, const float *verts, const int32_t *faces, int T, int V,
+                             int F, int N, uint64_t seed, const uint32_t *uniforms,
+                             const uint8_t *face_mask, int mask_per_frame, float *points,
+                             int32_t *face_idx, float *bary, void *stream) {
+    if (!face_mask || (mask_per_frame != 0 && mask_per_frame != 1)) {
+        clear_error();
+        set_error("dc_sample_surface_masked: NULL face_mask or mask_per_frame not 0/1");
+        return DC_ERR_INVALID;
+    }
+    return sample_surface_impl(ctx, verts, faces, T, V, F, N, seed, uniforms, face_mask,
+                               mask_per_frame, points, face_idx, bary, stream);
 }
 
 int dc_sample_surface_bwd(dc_ctx *ctx, const float *grad_points, const int32_t *faces,

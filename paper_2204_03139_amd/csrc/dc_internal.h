@@ -99,9 +99,9 @@ struct ProfScope {
 // sampling
 size_t sample_scratch_bytes(int T, int F);
 void launch_sample(const float *verts, const int32_t *faces, int T, int V, int F, int N,
-                   uint64_t seed, const uint32_t *uniforms, float *points, int32_t *face_idx,
-                   float *bary, double *cdf_scratch, int32_t *lastpos_scratch, unsigned *status,
-                   hipStream_t s);
+                   uint64_t seed, const uint32_t *uniforms, const uint8_t *mask, int mask_per_frame,
+                   float *points, int32_t *face_idx, float *bary, double *cdf_scratch,
+                   int32_t *lastpos_scratch, unsigned *status, hipStream_t s);
 
 // exact fp32 nearest neighbours: for each query of Q[t] the index of its nearest point in P[t]
 size_t nn_exact_scratch_bytes(int T, int Nq, int Np);
@@ -148,8 +148,9 @@ void launch_sample_bwd(const float *grad_points, const int32_t *faces, const int
 // composite enqueues shared by the direct calls and the serving loop
 // `prof` is the context whose profiling records the launches, or NULL
 int enqueue_sample(dc_ctx *prof, const float *verts, const int32_t *faces, int T, int V, int F,
-                   int N, uint64_t seed, const uint32_t *uniforms, float *points,
-                   int32_t *face_idx, float *bary, Arena &ar, unsigned *status, hipStream_t s);
+                   int N, uint64_t seed, const uint32_t *uniforms, const uint8_t *mask,
+                   int mask_per_frame, float *points, int32_t *face_idx, float *bary, Arena &ar,
+                   unsigned *status, hipStream_t s);
 size_t chamfer_fwd_scratch_bytes(int T, int Na, int Nb, int precision);
 int enqueue_chamfer_fwd(dc_ctx *prof, const float *a, const float *b, int T, int Na, int Nb,
                         int precision,

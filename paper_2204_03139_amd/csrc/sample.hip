@@ -37,6 +37,8 @@ __device__ __forceinline__ double tri_area_f64(const float *p1, const float *p2,
 struct AreaCdfParams {
     const float *verts;
     const int32_t *faces;
+    const uint8_t *mask;  // optional: nonzero = the face may be drawn (row t at t * mask_stride)
+    size_t mask_stride;
     int V, F;
     double *cdf;
     int32_t *lastpos;
@@ -65,11 +67,14 @@ __device__ __forceinline__ void area_cdf_body(const AreaCdfParams &p, const Blk 
         for (int k = threadIdx.x; k < n; k += AC_THREADS) {
             const int32_t *fv = faces + 3 * (size_t)(base + k);
             double a = 0.0;
-            if (face_ok(fv, V))
+            if (face_ok(fv, V)) {
                 a = tri_area_f64(vt + 3 * (size_t)fv[0], vt + 3 * (size_t)fv[1],
                                  vt + 3 * (size_t)fv[2]);
-            else
+                // a face outside the subset takes part with area 0: it is never drawn
+                if (p.mask && !p.mask[(size_t)t * p.mask_stride + base + k]) a = 0.0;
+            } else {
                 bad = 1;
+            }
             area[k] = a;
             last = (a > 0.0) ? base + k : last;
         }
@@ -230,12 +235,14 @@ size_t sample_scratch_bytes(int T, int F) {
 }
 
 void launch_sample(const float *verts, const int32_t *faces, int T, int V, int F, int N,
-                   uint64_t seed, const uint32_t *uniforms, float *points, int32_t *face_idx,
-                   float *bary, double *cdf_scratch, int32_t *lastpos_scratch, unsigned *status,
-                   hipStream_t s) {
+                   uint64_t seed, const uint32_t *uniforms, const uint8_t *mask, int mask_per_frame,
+                   float *points, int32_t *face_idx, float *bary, double *cdf_scratch,
+                   int32_t *lastpos_scratch, unsigned *status, hipStream_t s) {
     AreaCdfParams ap;
     ap.verts = verts;
     ap.faces = faces;
+    ap.mask = mask;
+    ap.mask_stride = mask_per_frame ? (size_t)F : 0;
     ap.V = V;
     ap.F = F;
     ap.cdf = cdf_scratch;

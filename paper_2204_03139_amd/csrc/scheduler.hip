@@ -183,8 +183,8 @@ int issue_request(const Req *r, const Layout &L, unsigned long long *stats) {
     Arena sar;
     sar.base = L.scratch;
     sar.cap = r->bytes;
-    int rc = enqueue_sample(nullptr, L.verts, L.faces, T, V, F, Na, r->seed, nullptr, L.pts,
-                            L.fidx, L.bary, sar, L.status, s);
+    int rc = enqueue_sample(nullptr, L.verts, L.faces, T, V, F, Na, r->seed, nullptr, nullptr, 0,
+                            L.pts, L.fidx, L.bary, sar, L.status, s);
     if (rc) return rc;
     // the unidirectional loss needs neither the b -> a search nor its indices
     const bool cols = r->reduction != DC_RED_SIM2REAL_SUM;

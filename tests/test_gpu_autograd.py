@@ -99,3 +99,26 @@ def test_autograd_unidirectional_loss(precision):
                                           reduction=1)
     assert abs(loss.item() - och["loss"].sum()) <= 1e-5 * och["loss"].sum()
     assert_grad(host(verts.grad), ogv, ogva, what="Eq. 2 autograd vs oracle")
+
+
+def test_autograd_masked_sampling():
+    """Subset sampling through the Function: only faces of the mask receive points, so vertices
+    touching no sampled face get exactly zero gradient; the gradient matches the oracle's."""
+    p = gpu()
+    w = gen.workload(3)
+    faces_np = w["faces"]
+    mask = (w["verts"][0][faces_np][:, :, 1].mean(axis=1) > 0).astype(np.uint8)
+    verts = dev(w["verts"]).requires_grad_(True)
+    faces, obs = dev(faces_np), dev(w["observed"])
+    loss = p.diffcloud_loss(verts, faces, obs, w["Na"], seed=w["seed"], precision=1,
+                            face_mask=torch.from_numpy(mask).to("cuda"))
+    loss.backward()
+    pts, fi, ba = oracle.sample_surface(w["verts"], faces=faces_np, N=w["Na"], seed=w["seed"],
+                                        face_mask=mask)
+    ogv, ogva, och = oracle.full_gradient(w["verts"], faces_np, w["observed"], fi, ba, pts)
+    assert abs(loss.item() - och["loss"].sum()) <= 1e-5 * och["loss"].sum()
+    g = host(verts.grad)
+    assert_grad(g, ogv, ogva, what="masked autograd vs oracle")
+    touched = np.zeros(w["V"], bool)
+    touched[faces_np[mask == 1].ravel()] = True
+    assert np.all(g[:, ~touched] == 0)

@@ -46,6 +46,56 @@ def test_sample_parity(case):
     assert np.array_equal(gb.view(np.uint32), ob.view(np.uint32))
 
 
+@pytest.mark.parametrize("mode", ["shared-upper-half", "per-frame-runs", "philox-shared"])
+def test_masked_sample_parity(mode):
+    """Subset sampling: points, weights and faces bit-exact against the oracle with the same mask;
+    no point lands on an excluded face."""
+    p = gpu()
+    say(f"[sample] masked {mode}")
+    w = gen.workload(2, T=3)
+    verts, faces, N = w["verts"], w["faces"], w["Na"]
+    F = len(faces)
+    if mode == "per-frame-runs":  # runs of 37 consecutive excluded faces, shifted per frame
+        mask = np.stack([((np.arange(F) + 11 * t) // 37) % 2 for t in range(3)]).astype(np.uint8)
+    else:  # the upper half of the cloth, as in the occlusion heuristic of the fold scenario
+        mask = (verts[0][faces][:, :, 1].mean(axis=1) > 0).astype(np.uint8)
+    words = None if mode == "philox-shared" else w["words"]
+    vt, ft = dev(verts), dev(faces)
+    m = torch.from_numpy(mask).to("cuda")
+    if words is None:
+        g = p.sample_surface(vt, ft, N, seed=w["seed"], face_mask=m)
+        o = oracle.sample_surface(verts, faces, N, seed=w["seed"], face_mask=mask)
+    else:
+        g = p.sample_surface(vt, ft, N, uniforms=dev(words.view(np.int32)), face_mask=m)
+        o = oracle.sample_surface(verts, faces, N, words=words, face_mask=mask)
+    gp, gf, gb = (host(x) for x in g)
+    assert np.array_equal(gf, o[1])
+    assert np.array_equal(gp.view(np.uint32), o[0].view(np.uint32))
+    assert np.array_equal(gb.view(np.uint32), o[2].view(np.uint32))
+    rows = mask if mask.ndim == 2 else np.broadcast_to(mask, (3, F))
+    assert all(np.all(rows[t][gf[t]] == 1) for t in range(3))
+
+
+def test_masked_sample_empty_subset_and_arguments():
+    p = gpu()
+    ctx = p.Context(0)
+    verts, faces = gen.trajectory(6, 2, 3)
+    F = len(faces)
+    mask = np.ones((2, F), np.uint8)
+    mask[1] = 0  # frame 1 has nothing to draw from
+    pts, fi, _ = p.sample_surface(dev(verts), dev(faces), 16, seed=3, ctx=ctx,
+                                  face_mask=torch.from_numpy(mask).to("cuda"))
+    with pytest.raises(p.DCError) as e:
+        ctx.sync()
+    assert e.value.code == -5
+    fi = host(fi)
+    assert np.all(fi[1] == -1) and np.all(fi[0] >= 0)
+    with pytest.raises(ValueError):  # wrong mask shape
+        p.sample_surface(dev(verts), dev(faces), 16, ctx=ctx,
+                         face_mask=torch.ones(F + 1, dtype=torch.uint8, device="cuda"))
+    ctx.close()
+
+
 def test_sqrt_all_levels():
     """Every one of the 2^24 values of r1 goes through a correctly rounded square root: with
     r2 = 0 the weight v equals s = sqrt(r1) exactly, compared with the host's IEEE sqrt."""
