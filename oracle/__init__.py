@@ -58,6 +58,10 @@ def lib():
         L.orc_sample_surface.argtypes = [_f32p, _i32p, _i, _i, _i, _i, _u32p, _vp, ctypes.c_long,
                                          _f32p, _i32p, _f32p, _vp, _vp]
         L.orc_sample_surface.restype = _i
+        L.orc_rigid_pose.argtypes = [_f64p, _f32p, _i32p, _i, _i, _i, _f64p]
+        L.orc_rigid_pose.restype = _i
+        L.orc_rigid_pose_grad.argtypes = [_f64p, _f32p, _i32p, _f32p, _i, _i, _i, _f64p, _vp]
+        L.orc_rigid_pose_grad.restype = _i
         L.orc_nearest.argtypes = [_f32p, _i, _f32p, _i, _i32p, _f32p, _f64p, _i]
         L.orc_chamfer.argtypes = [_f32p, _f32p, _i, _i, _i, _i, _vp, _i32p, _f32p, _f64p, _i32p,
                                   _f32p, _f64p, _f64p, _i]
@@ -318,3 +322,33 @@ def fd_gradient(verts, faces, observed, face_idx, bary, coords, h=1e-4, reductio
         fdz[n] = (lpz - lmz) / (2 * h)
         moved[n] = not (np.array_equal(iap, iam) and np.array_equal(ibp, ibm))
     return fd, fdz, moved
+
+
+# ------------------------------------------------------------------ rigid bodies (Sec. III-C)
+def rigid_pose(q, p0, body_start, V: int | None = None):
+    """Vertices [T,V,3] (double) of rigid bodies at poses q [T,B,6] = (t, phi, theta, psi):
+    p = Rz(psi) Ry(theta) Rx(phi) p0 + t for the vertices [body_start[b], body_start[b+1])."""
+    qq = _c(q, np.float64)
+    T, B, _ = qq.shape
+    pp = _c(p0, np.float32)
+    V = pp.shape[0] if V is None else V
+    out = np.zeros((T, V, 3), np.float64)
+    rc = lib().orc_rigid_pose(qq, pp, _c(body_start, np.int32), T, B, V, out)
+    if rc != 0:
+        raise OracleError(f"rigid_pose: status {rc}")
+    return out
+
+
+def rigid_pose_grad(q, p0, body_start, grad_verts):
+    """Pose gradient [T,B,6] = sum over each body's vertices of J^T g, and its abs-sum."""
+    qq = _c(q, np.float64)
+    T, B, _ = qq.shape
+    g = _c(grad_verts, np.float32)
+    V = g.shape[1]
+    gq = np.zeros((T, B, 6), np.float64)
+    ga = np.zeros((T, B, 6), np.float64)
+    rc = lib().orc_rigid_pose_grad(qq, _c(p0, np.float32), _c(body_start, np.int32), g, T, B, V,
+                                   gq, _ptr(ga))
+    if rc != 0:
+        raise OracleError(f"rigid_pose_grad: status {rc}")
+    return gq, ga

@@ -438,3 +438,102 @@ int orc_max_threads(void) {
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------ rigid bodies (Sec. III-C) */
+/* A rigid mesh vertex with body-frame coordinate p0 sits at p = [r] p0 + t for the pose
+ * q = (t_x, t_y, t_z, phi, theta, psi).  [r] is read as the rotation Rz(psi) Ry(theta) Rx(phi)
+ * (roll phi about x first, then pitch theta about y, then yaw psi about z).  Body b owns the
+ * vertices [body_start[b], body_start[b+1]). */
+static void mat3_mul(const double A[9], const double B[9], double C[9]) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += A[3 * i + k] * B[3 * k + j];
+            C[3 * i + j] = s;
+        }
+}
+
+/* R and its three partial derivatives dR/dphi, dR/dtheta, dR/dpsi (row-major 3x3 each) */
+static void euler_zyx(double phi, double theta, double psi, double R[9], double dR[3][9]) {
+    const double cf = cos(phi), sf = sin(phi), ct = cos(theta), st = sin(theta);
+    const double cp = cos(psi), sp = sin(psi);
+    const double Rx[9] = {1, 0, 0, 0, cf, -sf, 0, sf, cf};
+    const double Ry[9] = {ct, 0, st, 0, 1, 0, -st, 0, ct};
+    const double Rz[9] = {cp, -sp, 0, sp, cp, 0, 0, 0, 1};
+    const double dRx[9] = {0, 0, 0, 0, -sf, -cf, 0, cf, -sf};
+    const double dRy[9] = {-st, 0, ct, 0, 0, 0, -ct, 0, -st};
+    const double dRz[9] = {-sp, -cp, 0, cp, -sp, 0, 0, 0, 0};
+    double M[9];
+    mat3_mul(Rz, Ry, M);
+    mat3_mul(M, Rx, R);
+    mat3_mul(M, dRx, dR[0]);
+    mat3_mul(Rz, dRy, M);
+    mat3_mul(M, Rx, dR[1]);
+    mat3_mul(dRz, Ry, M);
+    mat3_mul(M, Rx, dR[2]);
+}
+
+static int bodies_ok(const int32_t *body_start, int B, int V) {
+    for (int b = 0; b < B; ++b)
+        if (body_start[b] < 0 || body_start[b] > body_start[b + 1] || body_start[b + 1] > V)
+            return 0;
+    return 1;
+}
+
+/* verts[t, v] = R(q_tb) p0[v] + t(q_tb) for the vertices of every body b, in double */
+int orc_rigid_pose(const double *q, const float *p0, const int32_t *body_start, int T, int B,
+                   int V, double *verts) {
+    if (!bodies_ok(body_start, B, V)) return ORC_ERR_INVALID;
+    for (int t = 0; t < T; ++t)
+        for (int b = 0; b < B; ++b) {
+            const double *qb = q + ((size_t)t * B + b) * 6;
+            double R[9], dR[3][9];
+            euler_zyx(qb[3], qb[4], qb[5], R, dR);
+            for (int v = body_start[b]; v < body_start[b + 1]; ++v)
+                for (int i = 0; i < 3; ++i) {
+                    double x = qb[i];
+                    for (int j = 0; j < 3; ++j) x += R[3 * i + j] * (double)p0[3 * (size_t)v + j];
+                    verts[((size_t)t * V + v) * 3 + i] = x;
+                }
+        }
+    return ORC_OK;
+}
+
+/* grad_q[t, b] = sum over the vertices v of body b of J_v^T g[t, v], J_v = dp_v/dq the 3x6
+ * Jacobian [ I | dR/dphi p0 | dR/dtheta p0 | dR/dpsi p0 ]; gq_abs (optional) sums the absolute
+ * values of the terms. */
+int orc_rigid_pose_grad(const double *q, const float *p0, const int32_t *body_start,
+                        const float *gverts, int T, int B, int V, double *gq, double *gq_abs) {
+    if (!bodies_ok(body_start, B, V)) return ORC_ERR_INVALID;
+    for (int t = 0; t < T; ++t)
+        for (int b = 0; b < B; ++b) {
+            const double *qb = q + ((size_t)t * B + b) * 6;
+            double R[9], dR[3][9];
+            euler_zyx(qb[3], qb[4], qb[5], R, dR);
+            double acc[6] = {0, 0, 0, 0, 0, 0}, aabs[6] = {0, 0, 0, 0, 0, 0};
+            for (int v = body_start[b]; v < body_start[b + 1]; ++v) {
+                const float *g = gverts + ((size_t)t * V + v) * 3;
+                const float *pv = p0 + 3 * (size_t)v;
+                double J[3][6];
+                for (int i = 0; i < 3; ++i) {
+                    for (int k = 0; k < 3; ++k) J[i][k] = (i == k) ? 1.0 : 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        double s = 0.0;
+                        for (int j = 0; j < 3; ++j) s += dR[a][3 * i + j] * (double)pv[j];
+                        J[i][3 + a] = s;
+                    }
+                }
+                for (int k = 0; k < 6; ++k)
+                    for (int i = 0; i < 3; ++i) {
+                        const double term = J[i][k] * (double)g[i];
+                        acc[k] += term;
+                        aabs[k] += fabs(term);
+                    }
+            }
+            for (int k = 0; k < 6; ++k) {
+                gq[((size_t)t * B + b) * 6 + k] = acc[k];
+                if (gq_abs) gq_abs[((size_t)t * B + b) * 6 + k] = aabs[k];
+            }
+        }
+    return ORC_OK;
+}

@@ -358,3 +358,69 @@ def test_vertex_gradient_matches_central_differences():
     assert np.all(np.abs(an - fdz) <= 1e-5 * scale + 1e-9)
     ok = ~moved
     assert np.all(np.abs(an[ok] - fd[ok]) <= 1e-5 * scale[ok] + 1e-9)
+
+
+# ----------------------------------------------------------------- rigid bodies (Sec. III-C)
+def test_rigid_rotation_matches_library_and_textbook():
+    """[r] is Rz(psi) Ry(theta) Rx(phi): the images of the unit vectors are the columns of
+    scipy's intrinsic 'ZYX' rotation, and quarter turns map axes as the textbook says."""
+    from scipy.spatial.transform import Rotation
+    p0 = np.eye(3, dtype=np.float32)
+    starts = np.array([0, 3], np.int32)
+    r = np.random.default_rng(5)
+    for _ in range(20):
+        phi, theta, psi = r.uniform(-np.pi, np.pi, 3)
+        q = np.array([[[0, 0, 0, phi, theta, psi]]])
+        cols = oracle.rigid_pose(q, p0, starts)[0]          # row j = R e_j
+        R = Rotation.from_euler("ZYX", [psi, theta, phi]).as_matrix()
+        assert np.allclose(cols.T, R, atol=1e-14)
+    h = np.pi / 2
+    ex, ey, ez = np.eye(3)
+    img = lambda ang, v: oracle.rigid_pose(np.array([[[0, 0, 0, *ang]]]),
+                                           v[None].astype(np.float32), np.array([0, 1], np.int32))[0, 0]
+    assert np.allclose(img((h, 0, 0), ey), ez, atol=1e-15)   # roll about x
+    assert np.allclose(img((0, h, 0), ez), ex, atol=1e-15)   # pitch about y
+    assert np.allclose(img((0, 0, h), ex), ey, atol=1e-15)   # yaw about z
+    # translation only
+    t = oracle.rigid_pose(np.array([[[0.5, -1, 2, 0, 0, 0]]]), p0, starts)[0]
+    assert np.array_equal(t, np.eye(3) + [0.5, -1, 2])
+
+
+def test_rigid_pose_gradient_central_differences():
+    """dL/dq for L(q) = sum_v g_v . p_v(q) against double central differences, two frames and
+    three bodies covering part of the vertex range."""
+    r = np.random.default_rng(8)
+    V = 40
+    p0 = r.normal(size=(V, 3)).astype(np.float32)
+    starts = np.array([2, 15, 15, 33], np.int32)   # bodies of 13, 0 and 18 vertices
+    q = r.uniform(-1, 1, (2, 3, 6))
+    g = r.normal(size=(2, V, 3)).astype(np.float32)
+    gq, ga = oracle.rigid_pose_grad(q, p0, starts, g)
+    h = 1e-6
+    for t in range(2):
+        for b in range(3):
+            for k in range(6):
+                qp, qm = q.copy(), q.copy()
+                qp[t, b, k] += h
+                qm[t, b, k] -= h
+                Lp = (oracle.rigid_pose(qp, p0, starts, V)[t] * g[t]).sum()
+                Lm = (oracle.rigid_pose(qm, p0, starts, V)[t] * g[t]).sum()
+                fd = (Lp - Lm) / (2 * h)
+                assert abs(fd - gq[t, b, k]) <= 1e-7 * max(1.0, ga[t, b, k])
+    assert np.all(gq[:, 1] == 0)                   # the empty body
+
+
+def test_rigid_pose_gradient_special_cases():
+    """A uniform gradient c on a body centred at its origin gives n c for the translation and
+    zero for the angles; bad body ranges are rejected."""
+    r = np.random.default_rng(9)
+    half = r.normal(size=(15, 3)).astype(np.float32)
+    p0 = np.concatenate([half, -half])            # points in +- pairs: an exact zero sum
+    starts = np.array([0, 30], np.int32)
+    c = np.array([0.25, -0.5, 2.0], np.float32)
+    g = np.broadcast_to(c, (1, 30, 3)).copy()
+    gq, ga = oracle.rigid_pose_grad(r.uniform(-1, 1, (1, 1, 6)), p0, starts, g)
+    assert np.allclose(gq[0, 0, :3], 30 * c, rtol=1e-12)
+    assert np.all(np.abs(gq[0, 0, 3:]) <= 1e-12 * ga[0, 0, 3:].max())
+    with pytest.raises(oracle.OracleError):
+        oracle.rigid_pose_grad(np.zeros((1, 1, 6)), p0, np.array([5, 3], np.int32), g)
