@@ -163,6 +163,29 @@ int dc_chamfer_bwd(dc_ctx *ctx, const double *grad_loss, const float *a, const f
                    int reduction, const float *frame_w, float *grad_a, float *grad_b,
                    void *stream);
 
+/* ------------------------------------------------------------------ rigid bodies, Sec. III-C */
+/* World vertices of rigid meshes from their 6-DoF poses: a vertex with body-frame coordinate p0
+ * sits at p = [r] p0 + t, q = (t_x, t_y, t_z, phi, theta, psi), [r] = Rz(psi) Ry(theta) Rx(phi).
+ *   q          device double [T,B,6]  pose of body b at frame t
+ *   p0         device float [V,3]     body-frame coordinates
+ *   body_start device int32 [B+1]     body b owns the vertices [body_start[b], body_start[b+1])
+ *   verts      device float [T,V,3]   out: the bodies' vertices (computed in double, rounded once
+ *              to float); vertices owned by no body are left untouched (deformables of a scene)
+ * A range outside [0, V] or decreasing is reported by dc_sync() as DC_ERR_INVALID.
+ * Errors: DC_ERR_INVALID (argument), DC_ERR_HIP. */
+int dc_rigid_pose(dc_ctx *ctx, const double *q, const float *p0, const int32_t *body_start,
+                  int T, int B, int V, float *verts, void *stream);
+
+/* Chain rule from vertex gradients to the poses (the Jacobian of p = f(q), Sec. III-C):
+ *   grad_q[t,b] = sum over the vertices v of body b of J_v^T grad_verts[t,v],
+ *   J_v = [ I | dR/dphi p0_v | dR/dtheta p0_v | dR/dpsi p0_v ]  (3 x 6),
+ * summed in double in a fixed order (bitwise reproducible, no atomics).
+ *   grad_verts device float [T,V,3]; grad_q device double [T,B,6] out (overwritten).
+ * Errors: as dc_rigid_pose. */
+int dc_rigid_pose_bwd(dc_ctx *ctx, const double *q, const float *p0, const int32_t *body_start,
+                      const float *grad_verts, int T, int B, int V, double *grad_q,
+                      void *stream);
+
 /* Counters of the bf16 screen since the context was created (read after dc_sync):
  *   queries    nearest-neighbour queries answered by the screened search
  *   candidates candidate groups re-evaluated exactly

@@ -34,7 +34,7 @@ STATUS_NAMES = {0: "DC_OK", 1: "DC_PENDING", -1: "DC_ERR_INVALID", -2: "DC_ERR_N
 
 # every symbol the public header declares
 EXPORTS = ["dc_create", "dc_destroy", "dc_last_error", "dc_sync", "dc_sample_surface",
-           "dc_sample_surface_masked",
+           "dc_sample_surface_masked", "dc_rigid_pose", "dc_rigid_pose_bwd",
            "dc_sample_surface_bwd", "dc_chamfer_fwd", "dc_chamfer_bwd", "dc_get_stats",
            "dc_submit", "dc_poll", "dc_version", "dc_debug_fail_allocs", "dc_profile",
            "dc_get_kernel_times", "dc_request_bytes"]
@@ -91,6 +91,8 @@ def load():
     L.dc_sync.argtypes = [vp, vp]
     L.dc_sample_surface.argtypes = [vp, vp, vp, i, i, i, i, u64, vp, vp, vp, vp, vp]
     L.dc_sample_surface_masked.argtypes = [vp, vp, vp, i, i, i, i, u64, vp, vp, i, vp, vp, vp, vp]
+    L.dc_rigid_pose.argtypes = [vp, vp, vp, vp, i, i, i, vp, vp]
+    L.dc_rigid_pose_bwd.argtypes = [vp, vp, vp, vp, vp, i, i, i, vp, vp]
     L.dc_sample_surface_bwd.argtypes = [vp, vp, vp, vp, vp, i, i, i, i, vp, vp]
     L.dc_chamfer_fwd.argtypes = [vp, vp, vp, i, i, i, i, i, vp, vp, vp, vp, vp, vp, vp]
     L.dc_chamfer_bwd.argtypes = [vp, vp, vp, vp, vp, vp, i, i, i, i, vp, vp, vp, vp]
@@ -286,3 +288,33 @@ def chamfer_bwd(grad_loss, a, b, idx_a, idx_b, reduction: int = DC_RED_BIDIR_MEA
         _ptr(gb, torch.float32, (T, Nb, 3), "grad_b"), _stream(stream))
     _check(rc, "dc_chamfer_bwd")
     return ga, gb
+
+
+def rigid_pose(q, p0, body_start, out=None, ctx=None, stream=None):
+    """dc_rigid_pose: vertices [T,V,3] of rigid bodies at poses q [T,B,6] (float64).  Vertices
+    owned by no body keep the values of `out` (uninitialised when out is None)."""
+    ctx = ctx or default_context(q.device.index)
+    T, B, _ = q.shape
+    V = p0.shape[0]
+    verts = out if out is not None else torch.empty((T, V, 3), dtype=torch.float32, device=q.device)
+    rc = load().dc_rigid_pose(
+        ctx.handle, _ptr(q, torch.float64, (T, B, 6), "q"), _ptr(p0, torch.float32, (V, 3), "p0"),
+        _ptr(body_start, torch.int32, (B + 1,), "body_start"), T, B, V,
+        _ptr(verts, torch.float32, (T, V, 3), "verts"), _stream(stream))
+    _check(rc, "dc_rigid_pose")
+    return verts
+
+
+def rigid_pose_bwd(q, p0, body_start, grad_verts, out=None, ctx=None, stream=None):
+    """dc_rigid_pose_bwd: the pose gradient [T,B,6] (float64)."""
+    ctx = ctx or default_context(q.device.index)
+    T, B, _ = q.shape
+    V = p0.shape[0]
+    gq = out if out is not None else torch.empty((T, B, 6), dtype=torch.float64, device=q.device)
+    rc = load().dc_rigid_pose_bwd(
+        ctx.handle, _ptr(q, torch.float64, (T, B, 6), "q"), _ptr(p0, torch.float32, (V, 3), "p0"),
+        _ptr(body_start, torch.int32, (B + 1,), "body_start"),
+        _ptr(grad_verts, torch.float32, (T, V, 3), "grad_verts"), T, B, V,
+        _ptr(gq, torch.float64, (T, B, 6), "grad_q"), _stream(stream))
+    _check(rc, "dc_rigid_pose_bwd")
+    return gq

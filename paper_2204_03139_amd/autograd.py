@@ -57,3 +57,30 @@ def diffcloud_loss(verts, faces, observed, n_sim, seed=0, precision=_lib.DC_PREC
     """Sum over frames of the per-frame loss (a scalar, float64)."""
     return DiffCloudChamfer.apply(verts, faces, observed, n_sim, seed, precision, reduction,
                                   frame_w, uniforms, face_mask).sum()
+
+
+class RigidPose(torch.autograd.Function):
+    """verts [T,V,3] of rigid meshes from poses q [T,B,6] (Sec. III-C): apply(q, p0, body_start,
+    base) with base [T,V,3] supplying the vertices owned by no body (or None).  The backward is
+    the chain rule J^T g per body; base receives the gradient of the vertices it supplies."""
+
+    @staticmethod
+    def forward(ctx, q, p0, body_start, base=None):
+        out = base.detach().clone().contiguous() if base is not None else None
+        verts = _lib.rigid_pose(q.detach().contiguous(), p0, body_start, out=out)
+        ctx.save_for_backward(q.detach(), p0, body_start)
+        ctx.has_base = base is not None
+        return verts
+
+    @staticmethod
+    def backward(ctx, grad_verts):
+        q, p0, body_start = ctx.saved_tensors
+        g = grad_verts.detach().to(torch.float32).contiguous()
+        gq = _lib.rigid_pose_bwd(q, p0, body_start, g)
+        gbase = None
+        if ctx.has_base:
+            owned = torch.zeros(g.shape[1], dtype=torch.bool, device=g.device)
+            for s, e in zip(body_start[:-1].tolist(), body_start[1:].tolist()):
+                owned[s:e] = True
+            gbase = g.masked_fill(owned[None, :, None], 0.0)
+        return gq.to(q.dtype), None, None, gbase

@@ -240,6 +240,10 @@ int dc_sync(dc_ctx *ctx, void *stream) {
         set_error("a face index lies outside [0, V)");
         return DC_ERR_INVALID;
     }
+    if (st & ST_BAD_INDEX) {
+        set_error("a body's vertex range lies outside [0, V] or is decreasing");
+        return DC_ERR_INVALID;
+    }
     if (st & ST_DEGENERATE) {
         set_error("a frame has zero or non-finite total surface area");
         return DC_ERR_DEGENERATE;
@@ -427,6 +431,40 @@ int dc_chamfer_bwd(dc_ctx *ctx, const double *grad_loss, const float *a, const f
     launch_chamfer_bwd(grad_loss, a, b, idx_a, idx_b, T, Na, Nb, reduction, frame_w, grad_a,
                        grad_b, ctx->arena.take<char>(need), static_cast<hipStream_t>(stream));
     return launched("chamfer_bwd launch");
+}
+
+int dc_rigid_pose(dc_ctx *ctx, const double *q, const float *p0, const int32_t *body_start,
+                  int T, int B, int V, float *verts, void *stream) {
+    clear_error();
+    if (!ctx || !q || !p0 || !body_start || !verts) {
+        set_error("dc_rigid_pose: NULL argument");
+        return DC_ERR_INVALID;
+    }
+    int rc = check_dims(T, {B, V});
+    if (rc) return rc;
+    DC_HIP(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> g(ctx->mu);
+    launch_rigid_fwd(q, p0, body_start, T, B, V, verts, ctx->d_status,
+                     static_cast<hipStream_t>(stream));
+    return launched("rigid_pose launch");
+}
+
+int dc_rigid_pose_bwd(dc_ctx *ctx, const double *q, const float *p0, const int32_t *body_start,
+                      const float *grad_verts, int T, int B, int V, double *grad_q,
+                      void *stream) {
+    clear_error();
+    if (!ctx || !q || !p0 || !body_start || !grad_verts || !grad_q) {
+        set_error("dc_rigid_pose_bwd: NULL argument");
+        return DC_ERR_INVALID;
+    }
+    int rc = check_dims(T, {B, V});
+    if (rc) return rc;
+    DC_HIP(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ProfScope ps(ctx, 3, static_cast<hipStream_t>(stream));
+    launch_rigid_bwd(q, p0, body_start, grad_verts, T, B, V, grad_q, ctx->d_status,
+                     static_cast<hipStream_t>(stream));
+    return launched("rigid_pose_bwd launch");
 }
 
 int dc_submit(dc_ctx *ctx, const dc_request *req, dc_result *out, uint64_t *ticket) {

@@ -25,7 +25,7 @@ int hip_fail(hipError_t e, const char *what);  // records the message, returns D
     } while (0)
 
 // bits of the sticky device status word
-enum : unsigned { ST_DEGENERATE = 1u, ST_BAD_FACE = 2u };
+enum : unsigned { ST_DEGENERATE = 1u, ST_BAD_FACE = 2u, ST_BAD_INDEX = 4u };
 
 // ---------------------------------------------------------------- scratch arena
 // A grow-only device buffer carved into 256-byte aligned pieces per call.  Growing frees the old
@@ -144,6 +144,13 @@ size_t sample_bwd_scratch_bytes(int T, int V, int F, int N);
 void launch_sample_bwd(const float *grad_points, const int32_t *faces, const int32_t *face_idx,
                        const float *bary, int T, int V, int F, int N, float *grad_verts,
                        char *scratch, hipStream_t s);
+
+// rigid bodies: vertices from 6-DoF poses, and the pose gradient
+void launch_rigid_fwd(const double *q, const float *p0, const int32_t *body_start, int T, int B,
+                      int V, float *verts, unsigned *status, hipStream_t s);
+void launch_rigid_bwd(const double *q, const float *p0, const int32_t *body_start,
+                      const float *grad_verts, int T, int B, int V, double *grad_q,
+                      unsigned *status, hipStream_t s);
 
 // composite enqueues shared by the direct calls and the serving loop
 // `prof` is the context whose profiling records the launches, or NULL
