@@ -198,7 +198,7 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_nn_merge(NNMergeParams p) {
     nn_merge_body(p, grid_blk());
 }
 
-constexpr int LOSS_THREADS = 256;
+constexpr int LOSS_THREADS = 1024;
 
 struct LossParams {
     const float *da;
@@ -218,9 +218,22 @@ __device__ __forceinline__ void loss_body(const LossParams &p, const Blk &blk) {
     __shared__ double sa[LOSS_THREADS], sb[LOSS_THREADS];
     const int t = blk.x;
     double xa = 0.0, xb = 0.0;
-    for (int i = threadIdx.x; i < Na; i += LOSS_THREADS) xa += (double)da[(size_t)t * Na + i];
-    if (beta != 0.0)
-        for (int j = threadIdx.x; j < Nb; j += LOSS_THREADS) xb += (double)db[(size_t)t * Nb + j];
+    // four independent partial sums per thread keep several loads in flight; they are added in
+    // a fixed order, as is the tree below, so the result is the same on every run
+    auto sum4 = [](const float *x, int n) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int i = threadIdx.x;
+        for (; i + 3 * LOSS_THREADS < n; i += 4 * LOSS_THREADS) {
+            s0 += (double)x[i];
+            s1 += (double)x[i + LOSS_THREADS];
+            s2 += (double)x[i + 2 * LOSS_THREADS];
+            s3 += (double)x[i + 3 * LOSS_THREADS];
+        }
+        for (; i < n; i += LOSS_THREADS) s0 += (double)x[i];
+        return (s0 + s1) + (s2 + s3);
+    };
+    xa = sum4(da + (size_t)t * Na, Na);
+    if (beta != 0.0) xb = sum4(db + (size_t)t * Nb, Nb);
     sa[threadIdx.x] = xa;
     sb[threadIdx.x] = xb;
     __syncthreads();
@@ -357,7 +370,7 @@ void register_nn_kernels(BatchedKernel *table) {
     table[KT_NN4] = batched_kernel<NNParams, nn_exact_body<4>, NN_THREADS, 2048>();
     table[KT_NN8] = batched_kernel<NNParams, nn_exact_body<8>, NN_THREADS, 2048>();
     table[KT_NN_MERGE] = batched_kernel<NNMergeParams, nn_merge_body, MERGE_THREADS, 512>();
-    table[KT_LOSS] = batched_kernel<LossParams, loss_body, LOSS_THREADS, 512>();
+    table[KT_LOSS] = batched_kernel<LossParams, loss_body, LOSS_THREADS, 256>();
 }
 
 }  // namespace dc

@@ -164,28 +164,33 @@ struct NormMaxParams {
     int Np;
 };
 
+constexpr int NM_THREADS = 1024;
+
 __device__ __forceinline__ void norm_max_body(const NormMaxParams &pr, const Blk &blk) {
     const float *__restrict__ P = pr.P;
     const int Np = pr.Np;
     float *__restrict__ out = pr.out;
     int32_t *__restrict__ heavy_cnt = pr.heavy_cnt;
-    __shared__ float red[256];
+    __shared__ float red[NM_THREADS / 64];
     const int t = blk.x;
     if (threadIdx.x == 0) heavy_cnt[t] = 0;
     const float *pt = P + (size_t)t * Np * 3;
     float m = 0.f;
-    for (int j = threadIdx.x; j < Np; j += 256)
+    for (int j = threadIdx.x; j < Np; j += NM_THREADS)
         m = fmaxf(m, norm2(pt[3 * (size_t)j], pt[3 * (size_t)j + 1], pt[3 * (size_t)j + 2]));
-    red[threadIdx.x] = m;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + h]);
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < NM_THREADS / 64; ++w) m = fmaxf(m, red[w]);
+        out[t] = m;
     }
-    if (threadIdx.x == 0) out[t] = red[0];
 }
 
-__global__ __launch_bounds__(256) void k_norm_max(NormMaxParams p) { norm_max_body(p, grid_blk()); }
+__global__ __launch_bounds__(NM_THREADS) void k_norm_max(NormMaxParams p) {
+    norm_max_body(p, grid_blk());
+}
 
 // Certificate threshold: every index whose canonical float distance can equal the minimum has a
 // screened value <= threshold(m, nq, nmax), where m is the query's screened minimum, nq its squared
@@ -591,13 +596,24 @@ __device__ __forceinline__ void colmerge_body(const ColmergeParams &pr, const Bl
             bw[u][k] = -1;
         }
     const uint16_t *base = cpart + (size_t)t * nwg * Np_pad + j0;
-    for (int w = 0; w < nwg; ++w) {
-        const uint2 v = *reinterpret_cast<const uint2 *>(base + (size_t)w * Np_pad);
+    auto merge4 = [&](const uint2 v, int w) {
         colmerge_insert(bv[0], bw[0], __uint_as_float(v.x << 16), w);
         colmerge_insert(bv[1], bw[1], __uint_as_float(v.x & 0xFFFF0000u), w);
         colmerge_insert(bv[2], bw[2], __uint_as_float(v.y << 16), w);
         colmerge_insert(bv[3], bw[3], __uint_as_float(v.y & 0xFFFF0000u), w);
+    };
+    // eight workgroups' partials in flight at a time: the loads are issued before the inserts
+    constexpr int CM_BATCH = 8;
+    int w = 0;
+    for (; w + CM_BATCH <= nwg; w += CM_BATCH) {
+        uint2 v[CM_BATCH];
+#pragma unroll
+        for (int k = 0; k < CM_BATCH; ++k)
+            v[k] = *reinterpret_cast<const uint2 *>(base + (size_t)(w + k) * Np_pad);
+#pragma unroll
+        for (int k = 0; k < CM_BATCH; ++k) merge4(v[k], w + k);
     }
+    for (; w < nwg; ++w) merge4(*reinterpret_cast<const uint2 *>(base + (size_t)w * Np_pad), w);
     const float nqm = nqmax[t];
 #pragma unroll
     for (int u = 0; u < CM_TPT; ++u) {
@@ -873,12 +889,12 @@ void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int
     nm.Np = Nb;
     nm.out = nbmax;
     nm.heavy_cnt = hcnt_a;
-    dispatch(KT_NORM_MAX, k_norm_max, dim3(T), 256, nm, s);
+    dispatch(KT_NORM_MAX, k_norm_max, dim3(T), NM_THREADS, nm, s);
     nm.P = a;
     nm.Np = Na;
     nm.out = namax;
     nm.heavy_cnt = hcnt_b;
-    dispatch(KT_NORM_MAX, k_norm_max, dim3(T), 256, nm, s);
+    dispatch(KT_NORM_MAX, k_norm_max, dim3(T), NM_THREADS, nm, s);
     PackParams pk;
     pk.P = b;
     pk.nqmax = namax;
@@ -953,7 +969,7 @@ void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int
 }
 
 void register_screen_kernels(BatchedKernel *table) {
-    table[KT_NORM_MAX] = batched_kernel<NormMaxParams, norm_max_body, 256, 512>();
+    table[KT_NORM_MAX] = batched_kernel<NormMaxParams, norm_max_body, NM_THREADS, 256>();
     table[KT_PACK] = batched_kernel<PackParams, pack_body, 256, 1024>();
     // two screen workgroups per compute unit fit the batched kernel's registers (forcing three
     // spills registers and measured slower)
