@@ -541,10 +541,10 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(ScreenParams p) {
 // by insertion, which is rare after the first few workgroups) and the next value; candidates are
 // the workgroups passing the certificate.  Record per target: n (or -1 = heavy) and up to CMAXC
 // entries (workgroup << 8 | tag).
-constexpr int CMAXC = 6;
+constexpr int CMAXC = 12;
 constexpr int CREC_INTS = 1 + CMAXC + 1;
 
-constexpr int CM_TPT = 4;  // targets per thread in the column merge (one 8-byte load each)
+constexpr int CM_TPT = 2;  // targets per thread in the column merge (even: 16-bit pairs per load)
 
 __device__ __forceinline__ void colmerge_insert(float (&bv)[CMAXC + 1], int (&bw)[CMAXC + 1],
                                                 float v, int w) {
@@ -564,6 +564,7 @@ __device__ __forceinline__ void colmerge_insert(float (&bv)[CMAXC + 1], int (&bw
 
 struct ColmergeParams {
     const float *P;
+    const float *slack;  // per-target affine threshold slack (k_pack_targets)
     const uint16_t *cpart;
     const uint8_t *ctag;
     const float *nqmax;
@@ -596,24 +597,41 @@ __device__ __forceinline__ void colmerge_body(const ColmergeParams &pr, const Bl
             bw[u][k] = -1;
         }
     const uint16_t *base = cpart + (size_t)t * nwg * Np_pad + j0;
-    auto merge4 = [&](const uint2 v, int w) {
-        colmerge_insert(bv[0], bw[0], __uint_as_float(v.x << 16), w);
-        colmerge_insert(bv[1], bw[1], __uint_as_float(v.x & 0xFFFF0000u), w);
-        colmerge_insert(bv[2], bw[2], __uint_as_float(v.y << 16), w);
-        colmerge_insert(bv[3], bw[3], __uint_as_float(v.y & 0xFFFF0000u), w);
+    // a partial can only be a candidate if it lies within the (affine, never smaller) threshold of
+    // the smallest partial seen so far: the rest are skipped with one compare
+    float thr[CM_TPT], slk[CM_TPT];
+#pragma unroll
+    for (int u = 0; u < CM_TPT; ++u) {
+        thr[u] = inf;
+        slk[u] = pr.slack[(size_t)t * Np_pad + j0 + u];
+    }
+    auto consider = [&](int u, float v, int w) {
+        if (v <= thr[u]) {
+            colmerge_insert(bv[u], bw[u], v, w);
+            thr[u] = threshold_affine(bf16_step_up(bv[u][0]), slk[u]);
+        }
+    };
+    // CM_TPT consecutive 16-bit partials of one workgroup as one load
+    typedef unsigned __attribute__((ext_vector_type(CM_TPT / 2))) WordT;
+    auto mergeT = [&](const WordT v, int w) {
+#pragma unroll
+        for (int h = 0; h < CM_TPT / 2; ++h) {
+            consider(2 * h, __uint_as_float(v[h] << 16), w);
+            consider(2 * h + 1, __uint_as_float(v[h] & 0xFFFF0000u), w);
+        }
     };
     // eight workgroups' partials in flight at a time: the loads are issued before the inserts
     constexpr int CM_BATCH = 8;
     int w = 0;
     for (; w + CM_BATCH <= nwg; w += CM_BATCH) {
-        uint2 v[CM_BATCH];
+        WordT v[CM_BATCH];
 #pragma unroll
         for (int k = 0; k < CM_BATCH; ++k)
-            v[k] = *reinterpret_cast<const uint2 *>(base + (size_t)(w + k) * Np_pad);
+            v[k] = *reinterpret_cast<const WordT *>(base + (size_t)(w + k) * Np_pad);
 #pragma unroll
-        for (int k = 0; k < CM_BATCH; ++k) merge4(v[k], w + k);
+        for (int k = 0; k < CM_BATCH; ++k) mergeT(v[k], w + k);
     }
-    for (; w < nwg; ++w) merge4(*reinterpret_cast<const uint2 *>(base + (size_t)w * Np_pad), w);
+    for (; w < nwg; ++w) mergeT(*reinterpret_cast<const WordT *>(base + (size_t)w * Np_pad), w);
     const float nqm = nqmax[t];
 #pragma unroll
     for (int u = 0; u < CM_TPT; ++u) {
@@ -942,6 +960,7 @@ void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int
         if (!cols) return;
         ColmergeParams cm;
         cm.P = b;
+        cm.slack = slack;
         cm.cpart = cpart;
         cm.ctag = ctag;
         cm.nqmax = namax;
