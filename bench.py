@@ -33,8 +33,8 @@ SCREEN_ISSUE_CEILING = CUS * SIMDS_PER_CU * PEAK_CLOCK_HZ / (5 * 4) * 256
 # HBM bytes of one k_screen launch on this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled
 # by a plain-copy calibration (profiles/k_screen_grid100_65536pts_100frames_counters.md); valid
 # only for the screen source they were measured on.
-SCREEN_TRAFFIC = dict(source_sha256="02c109651ccc15252dad00b1d3bd2b965c84a7da043cd85ee91610304547549a",
-                      bytes=2868224735 + 5243528224)
+SCREEN_TRAFFIC = dict(source_sha256="ed49105ad6500b7f2346a0731a76cae18bece5537e655a38b89209668df2ee28",
+                      bytes=2868097191 + 5243433288)
 
 
 def _screen_traffic():
