@@ -537,30 +537,17 @@ __global__ __launch_bounds__(SC_THREADS) void k_screen(ScreenParams p) {
     screen_body<COLS>(p, b);
 }
 
-// Column merge: per target b_j, the CMAXC workgroups with the smallest partial minima (kept sorted
-// by insertion, which is rare after the first few workgroups) and the next value; candidates are
-// the workgroups passing the certificate.  Record per target: n (or -1 = heavy) and up to CMAXC
-// entries (workgroup << 8 | tag).
+// Column merge: per target b_j, a running minimum over the workgroup partials and the list of
+// workgroups whose partial passed the (affine, never smaller) threshold of the minimum seen so far;
+// at the end the list is filtered by the certificate at the final minimum.  Candidates are the
+// workgroups passing it; more than CMAXC makes the target heavy.  Record per target: n (or -1 =
+// heavy) and up to CMAXC entries (workgroup << 8 | tag).
 constexpr int CMAXC = 12;
 constexpr int CREC_INTS = 1 + CMAXC + 1;
 
-constexpr int CM_TPT = 2;  // targets per thread in the column merge (even: 16-bit pairs per load)
-
-__device__ __forceinline__ void colmerge_insert(float (&bv)[CMAXC + 1], int (&bw)[CMAXC + 1],
-                                                float v, int w) {
-    if (v < bv[CMAXC]) {
-#pragma unroll
-        for (int k = 0; k <= CMAXC; ++k) {
-            const bool lt = v < bv[k];
-            const float tv = bv[k];
-            const int tw = bw[k];
-            bv[k] = lt ? v : tv;
-            bw[k] = lt ? w : tw;
-            v = lt ? tv : v;
-            w = lt ? tw : w;
-        }
-    }
-}
+constexpr int CM_TPT = 2;    // targets per thread: one 32-bit word of two 16-bit partials
+constexpr int CM_CAP = 16;   // pending list entries per target, in LDS
+constexpr int CM_THREADS = 256;
 
 struct ColmergeParams {
     const float *P;
@@ -583,55 +570,75 @@ __device__ __forceinline__ void colmerge_body(const ColmergeParams &pr, const Bl
     int32_t *__restrict__ crec = pr.crec;
     int32_t *__restrict__ heavy_cnt = pr.heavy_cnt;
     int32_t *__restrict__ heavy_list = pr.heavy_list;
+    // pending entries (workgroup << 16) | 16-bit partial; point counts are at most 2^24, so there
+    // are at most 2^16 row workgroups
+    __shared__ uint32_t pend[CM_CAP][CM_TPT][CM_THREADS];
     const int t = blk.y;
-    const int j0 = (blk.x * 256 + threadIdx.x) * CM_TPT;
+    const int tid = threadIdx.x;
+    const int j0 = (blk.x * CM_THREADS + tid) * CM_TPT;
     if (j0 >= Np) return;
     const float inf = __builtin_inff();
-    float bv[CM_TPT][CMAXC + 1];
-    int bw[CM_TPT][CMAXC + 1];
-#pragma unroll
-    for (int u = 0; u < CM_TPT; ++u)
-#pragma unroll
-        for (int k = 0; k <= CMAXC; ++k) {
-            bv[u][k] = inf;
-            bw[u][k] = -1;
-        }
-    const uint16_t *base = cpart + (size_t)t * nwg * Np_pad + j0;
-    // a partial can only be a candidate if it lies within the (affine, never smaller) threshold of
-    // the smallest partial seen so far: the rest are skipped with one compare
-    float thr[CM_TPT], slk[CM_TPT];
+    float best[CM_TPT], thr[CM_TPT], slk[CM_TPT];
+    int cnt[CM_TPT];
+    bool over[CM_TPT];
 #pragma unroll
     for (int u = 0; u < CM_TPT; ++u) {
+        best[u] = inf;
         thr[u] = inf;
+        cnt[u] = 0;
+        over[u] = false;
         slk[u] = pr.slack[(size_t)t * Np_pad + j0 + u];
     }
-    auto consider = [&](int u, float v, int w) {
+    const uint16_t *frame = cpart + (size_t)t * nwg * Np_pad;
+    // a partial passing the threshold of the running minimum goes on the list; the rest are
+    // skipped with one compare.  A full list drops the entries the current threshold excludes;
+    // if none can be dropped the target is made heavy (always correct: it is searched exhaustively).
+    auto consider = [&](int u, unsigned bits, int w) {
+        const float v = __uint_as_float(bits << 16);
         if (v <= thr[u]) {
-            colmerge_insert(bv[u], bw[u], v, w);
-            thr[u] = threshold_affine(bf16_step_up(bv[u][0]), slk[u]);
+            if (cnt[u] == CM_CAP) {
+                int n = 0;
+#pragma unroll 1
+                for (int k = 0; k < CM_CAP; ++k) {
+                    const uint32_t e = pend[k][u][tid];
+                    if (__uint_as_float(e << 16) <= thr[u]) pend[n++][u][tid] = e;
+                }
+                cnt[u] = n;
+                if (n == CM_CAP) {
+                    over[u] = true;
+                    thr[u] = -inf;
+                    return;
+                }
+            }
+            pend[cnt[u]++][u][tid] = ((uint32_t)w << 16) | bits;
+            best[u] = fminf(best[u], v);
+            thr[u] = threshold_affine(bf16_step_up(best[u]), slk[u]);
         }
     };
-    // CM_TPT consecutive 16-bit partials of one workgroup as one load
-    typedef unsigned __attribute__((ext_vector_type(CM_TPT / 2))) WordT;
-    auto mergeT = [&](const WordT v, int w) {
-#pragma unroll
-        for (int h = 0; h < CM_TPT / 2; ++h) {
-            consider(2 * h, __uint_as_float(v[h] << 16), w);
-            consider(2 * h + 1, __uint_as_float(v[h] & 0xFFFF0000u), w);
-        }
+    // the two 16-bit partials of one workgroup for this thread's targets, as one word
+    auto merge2 = [&](unsigned v, int w) {
+        consider(0, v & 0xFFFFu, w);
+        consider(1, v >> 16, w);
     };
-    // eight workgroups' partials in flight at a time: the loads are issued before the inserts
+    // eight workgroups' partials in flight at a time: the loads are issued before the compares.
+    // Each batch reads through a buffer resource based at its first row, so a load's address is
+    // the uniform row offset (scalar) plus the lane's offset: no per-lane 64-bit address math.
     constexpr int CM_BATCH = 8;
+    const unsigned row_bytes = (unsigned)Np_pad * 2u;
+    const unsigned lane_bytes = (unsigned)j0 * 2u;
     int w = 0;
     for (; w + CM_BATCH <= nwg; w += CM_BATCH) {
-        WordT v[CM_BATCH];
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(frame + (size_t)w * Np_pad), 0, (int)(row_bytes * CM_BATCH), 0x00020000);
+        unsigned v[CM_BATCH];
 #pragma unroll
         for (int k = 0; k < CM_BATCH; ++k)
-            v[k] = *reinterpret_cast<const WordT *>(base + (size_t)(w + k) * Np_pad);
+            v[k] = __builtin_amdgcn_raw_buffer_load_b32(rs, lane_bytes, k * row_bytes, 0);
 #pragma unroll
-        for (int k = 0; k < CM_BATCH; ++k) mergeT(v[k], w + k);
+        for (int k = 0; k < CM_BATCH; ++k) merge2(v[k], w + k);
     }
-    for (; w < nwg; ++w) mergeT(*reinterpret_cast<const WordT *>(base + (size_t)w * Np_pad), w);
+    for (; w < nwg; ++w)
+        merge2(*reinterpret_cast<const unsigned *>(frame + (size_t)w * Np_pad + j0), w);
     const float nqm = nqmax[t];
 #pragma unroll
     for (int u = 0; u < CM_TPT; ++u) {
@@ -641,26 +648,34 @@ __device__ __forceinline__ void colmerge_body(const ColmergeParams &pr, const Bl
         const float np = norm2(pj[0], pj[1], pj[2]);
         // the partials are lower bounds within one bf16 step; the threshold is taken at an upper
         // bound of the true minimum, and a workgroup is kept when its lower bound passes it
-        const float theta = threshold(bf16_step_up(bv[u][0]), np, nqm);
-        const bool finite = __builtin_isfinite(bv[u][0]) && __builtin_isfinite(theta) &&
-                            __builtin_isfinite(nqm) && bw[u][0] >= 0;
+        const float theta = threshold(bf16_step_up(best[u]), np, nqm);
+        const bool finite = __builtin_isfinite(best[u]) && __builtin_isfinite(theta) &&
+                            __builtin_isfinite(nqm);
         int32_t *rr = crec + ((size_t)t * Np + j) * CREC_INTS;
-        if (!finite || bv[u][CMAXC] <= theta) {
+        int n = 0;
+        if (finite && !over[u]) {
+#pragma unroll 1
+            for (int k = 0; k < cnt[u]; ++k) {
+                const uint32_t e = pend[k][u][tid];
+                if (__uint_as_float(e << 16) <= theta) {
+                    const int wk = (int)(e >> 16);
+                    if (n < CMAXC)
+                        rr[1 + n] = (wk << 8) | ctag[((size_t)t * nwg + wk) * Np_pad + j];
+                    ++n;
+                }
+            }
+        }
+        if (!finite || over[u] || n > CMAXC) {
             rr[0] = -1;
             const int pos = atomicAdd(&heavy_cnt[t], 1);
             heavy_list[(size_t)t * Np + pos] = j;
             continue;
         }
-        int n = 0;
-#pragma unroll
-        for (int k = 0; k < CMAXC; ++k)
-            if (bw[u][k] >= 0 && bv[u][k] <= theta)
-                rr[1 + n++] = (bw[u][k] << 8) | ctag[((size_t)t * nwg + bw[u][k]) * Np_pad + j];
         rr[0] = n;
     }
 }
 
-__global__ __launch_bounds__(256) void k_colmerge(ColmergeParams p) { colmerge_body(p, grid_blk()); }
+__global__ __launch_bounds__(CM_THREADS) void k_colmerge(ColmergeParams p) { colmerge_body(p, grid_blk()); }
 
 __device__ __forceinline__ float canon_d2(float qx, float qy, float qz, const float *p) {
     const float dx = qx - p[0];
@@ -970,8 +985,8 @@ void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int
         cm.Np = Nb;
         cm.Np_pad = Nb_pad;
         cm.nwg = nwg;
-        dispatch(KT_COLMERGE, k_colmerge, dim3((Nb + 256 * CM_TPT - 1) / (256 * CM_TPT), T), 256,
-                 cm, s);
+        dispatch(KT_COLMERGE, k_colmerge,
+                 dim3((Nb + CM_THREADS * CM_TPT - 1) / (CM_THREADS * CM_TPT), T), CM_THREADS, cm, s);
         RefineParams cr;
         cr.Q = b;
         cr.P = a;
@@ -995,7 +1010,7 @@ void register_screen_kernels(BatchedKernel *table) {
     table[KT_SCREEN] = batched_kernel<ScreenParams, screen_body<true>, SC_THREADS, 512>();
     table[KT_SCREEN_ROWS] = batched_kernel<ScreenParams, screen_body<false>, SC_THREADS, 768>();
     table[KT_REFINE] = batched_kernel<RefineParams, refine_body, RF_THREADS, 2048>();
-    table[KT_COLMERGE] = batched_kernel<ColmergeParams, colmerge_body, 256, 1024>();
+    table[KT_COLMERGE] = batched_kernel<ColmergeParams, colmerge_body, CM_THREADS, 1024>();
     table[KT_COLREFINE] = batched_kernel<RefineParams, colrefine_body, RF_THREADS, 2048>();
 }
 

@@ -222,6 +222,55 @@ def test_chamfer_ties_and_identity(precision):
     _check_chamfer(g, o)
 
 
+def _periodic_rows(n_rows, period=37, seed=41):
+    """Rows repeating `period` points: every 256-row workgroup holds the same points, so each
+    target's column partials tie exactly across all workgroups."""
+    r = np.random.default_rng(seed)
+    P = r.uniform(-.5, .5, (period, 3)).astype(np.float32)
+    A = P[np.arange(n_rows) % period][None]
+    B = r.uniform(-.5, .5, (1, 500, 3)).astype(np.float32)
+    return A, B
+
+
+def _descending_rows(seed=43):
+    """32 workgroups of 256 rows; target 0 (the origin) has one near row per workgroup at a
+    squared distance that falls by 0.15% per workgroup, the other rows lie on a sphere of radius
+    2.  The column merge keeps every near row on its list as it arrives and must drop the early
+    ones once they leave the threshold of the falling minimum."""
+    r = np.random.default_rng(seed)
+    u = r.normal(size=(8192, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    A = 2.0 * u
+    for w in range(32):
+        A[256 * w + 5] = np.sqrt(0.1 * (1 - 0.0015 * w)) * u[256 * w + 5]
+    B = r.uniform(-.5, .5, (1, 100, 3))
+    B[0, 0] = 0.0
+    return A[None].astype(np.float32), B.astype(np.float32)
+
+
+COLUMN_MERGE_CASES = {
+    "ties-32-workgroups": lambda: _periodic_rows(32 * 256),   # list overflows: heavy
+    "ties-14-workgroups": lambda: _periodic_rows(14 * 256),   # 14 candidates > 12: heavy
+    "ties-12-workgroups": lambda: _periodic_rows(12 * 256),   # 12 candidates, full rescans
+    "descending-minimum": _descending_rows,                   # stale list entries dropped
+}
+
+
+@pytest.mark.parametrize("case", list(COLUMN_MERGE_CASES))
+@pytest.mark.parametrize("precision", [0, 1])
+def test_column_merge_ties_and_list_overflow(case, precision):
+    """Targets whose nearest rows tie (or nearly tie) across many row workgroups: the column
+    direction must still give the exact argmin with the smallest-index rule, whether the target
+    stays light, exceeds the candidate limit or overflows the merge's list."""
+    p = gpu()
+    say(f"[chamfer] column merge {case} precision={precision}")
+    A, B = COLUMN_MERGE_CASES[case]()
+    g, o = _chamfer_both(p, A, B, precision=precision)
+    _check_chamfer(g, o)
+    if case.startswith("ties"):
+        assert np.all(g["idx_b"] < 37)
+
+
 @pytest.mark.parametrize("reduction", [0, 1])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_loss_reductions_and_weights(reduction, precision):
