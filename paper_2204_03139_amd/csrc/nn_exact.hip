@@ -40,6 +40,63 @@ struct NNParams {
     int Nq, Np, slice_len;
 };
 
+// A short query list (the screen's heavy queries): one wave per query, its 64 lanes striding
+// over the slice, so a handful of queries still keeps every lane busy.  The result is the one the
+// lane-per-query search gives: the smallest index among the minimal distances (fminf order: NaN
+// distances never win), and when no distance is below infinity, the first index of the first
+// 64-target sub-tile whose distance is infinite, or the slice's first index.
+constexpr int NN_SHORT_LIST = 128;
+
+__device__ __noinline__ void short_list_search(const NNParams &pr, int t, int z, int nq_live,
+                                               int j_begin, int j_end) {
+    const int Nq = pr.Nq, Np = pr.Np;
+    const float *Qt = pr.Q + (size_t)t * Nq * 3;
+    const float *Pt = pr.P + (size_t)t * Np * 3;
+    const int lane = threadIdx.x & 63;
+    const float inf = __builtin_inff();
+    for (int k = threadIdx.x >> 6; k < nq_live; k += NN_THREADS / 64) {
+        const int qi = pr.qlist[(size_t)t * Nq + k];
+        const float qx = Qt[3 * (size_t)qi], qy = Qt[3 * (size_t)qi + 1],
+                    qz = Qt[3 * (size_t)qi + 2];
+        float best = inf;
+        int bj = 0x7fffffff;
+        for (int j = j_begin + lane; j < j_end; j += 64) {
+            const float *p = Pt + 3 * (size_t)j;
+            const float d = canon_d2(qx, qy, qz, p[0], p[1], p[2]);
+            if (d < best) {  // a lane's indices increase: strict-less keeps its first minimum
+                best = d;
+                bj = j;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const float ob = __shfl_xor(best, off, 64);
+            const int oj = __shfl_xor(bj, off, 64);
+            if (ob < best || (ob == best && oj < bj)) {
+                best = ob;
+                bj = oj;
+            }
+        }
+        if (!(best < inf)) {  // nothing finite: the first infinite distance of the first sub-tile
+            const int j = j_begin + lane;
+            bool hit = false;
+            if (j < min(j_begin + NN_SUB, j_end)) {
+                const float *p = Pt + 3 * (size_t)j;
+                hit = canon_d2(qx, qy, qz, p[0], p[1], p[2]) == inf;
+            }
+            const unsigned long long m = __ballot(hit);
+            bj = m ? j_begin + (int)__builtin_ctzll(m) : j_begin;
+            best = inf;
+        }
+        if (lane == 0) {
+            const size_t o = pr.slice_stride ? (size_t)z * pr.slice_stride + (size_t)t * Nq + k
+                                             : (size_t)t * Nq + qi;
+            pr.idx[o] = bj;
+            pr.dist[o] = best;
+        }
+    }
+}
+
 template <int QPT>
 __device__ __forceinline__ void nn_exact_body(const NNParams &pr, const Blk &blk) {
     const float *__restrict__ Q = pr.Q;
@@ -58,10 +115,16 @@ __device__ __forceinline__ void nn_exact_body(const NNParams &pr, const Blk &blk
     const float *Pt = P + (size_t)t * Np * 3;
     const int j_begin = z * slice_len;
     const int j_end = min(Np, j_begin + slice_len);
+    if (QPT == 1 && qlist && nq_live <= NN_SHORT_LIST) {
+        if (blk.x == 0) short_list_search(pr, t, z, nq_live, j_begin, j_end);
+        return;
+    }
     // the list of a frame is short and its length only known on the device: each workgroup
     // walks query blocks x, x + gx, ... of its logical grid (one step without a list)
     for (int qb = blk.x; qb * NN_THREADS * QPT < nq_live; qb += blk.gx) {
     const int q0 = qb * NN_THREADS * QPT + threadIdx.x;
+    // a wave whose queries all lie past the list end only helps stage the tiles
+    const bool wave_live = qb * NN_THREADS * QPT + (int)(threadIdx.x & ~63u) < nq_live;
 
     float qx[QPT], qy[QPT], qz[QPT], best[QPT];
     int bsub[QPT];
@@ -85,6 +148,7 @@ __device__ __forceinline__ void nn_exact_body(const NNParams &pr, const Blk &blk
             tile[j] = make_float4(p[0], p[1], p[2], 0.f);
         }
         __syncthreads();
+        if (!wave_live) continue;
         int s0 = 0;
         for (; s0 + NN_SUB <= n; s0 += NN_SUB) {
             float m[QPT];

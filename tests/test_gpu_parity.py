@@ -271,6 +271,68 @@ def test_column_merge_ties_and_list_overflow(case, precision):
         assert np.all(g["idx_b"] < 37)
 
 
+def _few_heavy(n, seed):
+    """n x n points with a few queries the screen cannot settle in either direction: one row
+    point repeated in every 256-row workgroup (so the targets near it tie across all of them)
+    and one target point repeated in 16 different slot groups (so the rows near it have more
+    candidate groups than the screen keeps)."""
+    r = np.random.default_rng(seed)
+    A = r.uniform(-.5, .5, (1, n, 3)).astype(np.float32)
+    B = r.uniform(-.5, .5, (1, n, 3)).astype(np.float32)
+    X = np.array([0.11, -0.23, 0.05], np.float32)
+    Y = np.array([-0.31, 0.17, -0.12], np.float32)
+    A[0, 7::256] = X
+    B[0, 5:5 + 2048 * 16:2048][: (n - 5 + 2047) // 2048] = Y
+    B[0, 10:15] = X + r.normal(scale=1e-3, size=(5, 3)).astype(np.float32)
+    A[0, 10:15] = Y + r.normal(scale=1e-3, size=(5, 3)).astype(np.float32)
+    return A, B
+
+
+@pytest.mark.parametrize("n", [6000, 20000])
+def test_short_heavy_lists(n):
+    """A handful of heavy rows and columns per frame go to the one-wave-per-query search (with
+    target slices at 20,000 points, without at 6,000): exact against the oracle, and bitwise equal
+    to the exhaustive fp32 path."""
+    p = gpu()
+    say(f"[chamfer] short heavy lists n={n}")
+    A, B = _few_heavy(n, 51)
+    ctx = p.Context(0)
+    g = p.chamfer_fwd(dev(A), dev(B), precision=1, ctx=ctx)
+    ctx.sync()
+    st = ctx.stats()
+    say(f"[chamfer] {st}")
+    assert 0 < st["fallbacks"] <= 64
+    ctx.close()
+    g = {k: host(v) for k, v in g.items()}
+    o = oracle.chamfer(A, B, 0, None)
+    _check_chamfer(g, o)
+
+
+def test_non_finite_points_follow_the_exhaustive_path():
+    """Rows or targets at NaN or at a distance whose square overflows are heavy for the screen:
+    the bf16 path returns exactly what the exhaustive fp32 path returns (indices and distances,
+    bit for bit), whichever list search handles them."""
+    p = gpu()
+    say("[chamfer] non-finite points")
+    r = np.random.default_rng(61)
+    for n, bad in ((3000, 3), (20000, 3), (20000, 300)):
+        A = r.uniform(-.5, .5, (1, n, 3)).astype(np.float32)
+        B = r.uniform(-.5, .5, (1, n, 3)).astype(np.float32)
+        rows = r.choice(n, bad, replace=False)
+        cols = r.choice(n, bad, replace=False)
+        A[0, rows[0::2]] = np.nan
+        A[0, rows[1::2], 0] = 3e30
+        B[0, cols[0::2], 1] = np.nan
+        B[0, cols[1::2]] = -2e30
+        g0 = {k: host(v) for k, v in p.chamfer_fwd(dev(A), dev(B), precision=0).items()}
+        g1 = {k: host(v) for k, v in p.chamfer_fwd(dev(A), dev(B), precision=1).items()}
+        torch.cuda.synchronize()
+        for k in ("idx_a", "idx_b", "dist_a", "dist_b"):
+            assert np.array_equal(g0[k].view(np.uint32), g1[k].view(np.uint32)), (n, bad, k)
+        for k in ("idx_a", "idx_b"):
+            assert g1[k].min() >= 0 and g1[k].max() < n
+
+
 @pytest.mark.parametrize("reduction", [0, 1])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_loss_reductions_and_weights(reduction, precision):
