@@ -14,10 +14,11 @@
 //     targets are laid out so that, inside each chunk of SC_CHUNK, result column c holds a
 //     contiguous run of SC_RUN targets (a "slot group"); the kernel keeps the two best slot
 //     groups and the third-best value per (lane, row);
-//   columns (b -> a): each lane folds its 16 rows of a tile into one value per (row group, b_j);
-//     after each stage the workgroup reduces its 16 row groups per b_j in LDS and writes the
-//     workgroup's minimum, the winning row group and an "ambiguous" flag (a second group within
-//     the certificate margin) to a per-workgroup partial array.
+//   columns (b -> a): each lane folds its 16 rows of a tile into one value per b_j; a lane swap
+//     pairs lane groups g and g + 2 (32 rows: a "row group"), and after the next stage's
+//     barrier the workgroup reduces its 8 row groups per b_j in LDS and writes the workgroup's
+//     minimum, the winning row group and an "ambiguous" flag (a second group within the
+//     certificate margin) to a per-workgroup partial array.
 // Certificate: every bf16 split is exact and every bf16 product is exact in fp32, so
 // |s_ij - d_ij| <= C (|a_i|^2 + |b_j|^2) (at most 24 fp32 roundings at 2^-23 on a sum of absolute
 // products <= 2.02 (|a|^2+|b|^2), plus dropped split products and float norms).  The canonical
@@ -277,7 +278,10 @@ __device__ __forceinline__ float bf16_step_up(float x) {
     return x + fabsf(x) * (0.0078125f + 1e-6f) + SCREEN_TAU;
 }
 
-constexpr int SC_GROUPS = SC_WAVES * 4;  // row groups per workgroup: (wave, lane group g)
+// Column row groups per workgroup: (wave, h), h in {0, 1}, holding the rows 16a + 4g + r of the
+// wave with g in {h, h + 2}: lane groups g and g + 2 see the same result columns, and one lane
+// swap pairs their partial minima up.
+constexpr int SC_GROUPS = SC_WAVES * 2;
 constexpr int CP_PAD = SC_TPS + 1;       // column partial buffer: [group][column][tile], padded
 
 struct ScreenParams {
@@ -310,7 +314,9 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
     // one column, 272 bytes apart) fall in distinct banks; the read address is a per-lane base
     // plus a compile-time offset.  K-chunk 3 is all zeros on the query side and is not stored.
     __shared__ bf16x8 stage[2][3][SC_ROWPAD * SC_TPS];
-    __shared__ float colbuf[COLS ? SC_GROUPS : 1][16][CP_PAD];
+    // double-buffered by stage parity: the partials of stage s are reduced after the barrier of
+    // stage s + 1, so one barrier per stage orders both buffers
+    __shared__ float colbuf[COLS ? 2 : 1][COLS ? SC_GROUPS : 1][16][CP_PAD];
     const int nwg = blk.gx, wgx = blk.x, t = blk.y;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -374,6 +380,34 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
         q[u][2] = src[2];
     }
     const int gk = (g == 3) ? 0 : g;
+    // reduce the workgroup's row groups per target of stage sm and write its partial
+    auto merge_stage = [&](int sm) {
+        const int cb = sm & 1;
+#pragma unroll
+        for (int u = 0; u < SC_PER_THREAD; ++u) {
+            const int e = threadIdx.x + u * SC_THREADS;
+            const int c = e / SC_TPS, btl = e % SC_TPS;
+            const int j = target_of(sm, u);
+            float best = inf, second = inf;
+            int bg = 0;
+#pragma unroll
+            for (int k = 0; k < SC_GROUPS; ++k) {
+                const float v = colbuf[COLS ? cb : 0][COLS ? k : 0][c][btl];
+                second = __builtin_amdgcn_fmed3f(v, best, second);  // best <= second
+                bg = v < best ? k : bg;
+                best = fminf(best, v);
+            }
+            if (j < Np) {
+                // another row group within the margin of this group's best: the merge must
+                // rescan every row of the workgroup for this target
+                const float th = threshold_affine(best, slack[(size_t)t * Np_pad + j]);
+                const bool amb = !(second > th + fabsf(th) * 1e-6f);
+                const size_t o = ((size_t)t * nwg + wgx) * Np_pad + j;
+                cpart[o] = lower_bf16_bits(best);
+                ctag[o] = (uint8_t)(bg | (amb ? 0x80 : 0));
+            }
+        }
+    };
     for (int st = 0; st < nstage; ++st) {
         const int buf = st & 1;
 #pragma unroll
@@ -392,6 +426,7 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
             }
         }
         __syncthreads();
+        if (COLS && st > 0) merge_stage(st - 1);
         // lanes of K-group 3 hold an all-zero query operand, so any finite staged operand gives
         // them zero products: they read K-chunk 0 instead of a stored zero chunk
         const bf16x8 *sb = &stage[buf][gk][col];
@@ -419,8 +454,13 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
                 }
             }
             if (COLS) {
-                colbuf[COLS ? wave * 4 + g : 0][col][bt] = cm0;
-                colbuf[COLS ? wave * 4 + g : 0][col][bt + 1] = cm1;
+                // rows 2-3 of cm0 trade places with rows 0-1 of cm1, so lane group g ends up
+                // with the minimum over groups g and g + 2 (mod 4) of tile bt + (g >> 1)
+                const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(cm0),
+                                                                 __float_as_uint(cm1), false,
+                                                                 false);
+                const float v = fminf(__uint_as_float(sw[0]), __uint_as_float(sw[1]));
+                colbuf[COLS ? (st & 1) : 0][COLS ? wave * 2 + (g & 1) : 0][col][bt + (g >> 1)] = v;
             }
         }
         if ((st + 1) % SPC == 0) {  // end of a tracking chunk
@@ -442,35 +482,10 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
                     m[a][r] = inf;
                 }
         }
-        if (COLS) {
-            // reduce the workgroup's row groups per target of this stage; the next stage's
-            // barrier orders these reads before the buffer is written again
-            __syncthreads();
-#pragma unroll
-            for (int u = 0; u < SC_PER_THREAD; ++u) {
-                const int e = threadIdx.x + u * SC_THREADS;
-                const int c = e / SC_TPS, btl = e % SC_TPS;
-                const int j = target_of(st, u);
-                float best = inf, second = inf;
-                int bg = 0;
-#pragma unroll
-                for (int k = 0; k < SC_GROUPS; ++k) {
-                    const float v = colbuf[COLS ? k : 0][c][btl];
-                    second = __builtin_amdgcn_fmed3f(v, best, second);  // best <= second
-                    bg = v < best ? k : bg;
-                    best = fminf(best, v);
-                }
-                if (j < Np) {
-                    // another row group within the margin of this group's best: the merge must
-                    // rescan every row of the workgroup for this target
-                    const float th = threshold_affine(best, slack[(size_t)t * Np_pad + j]);
-                    const bool amb = !(second > th + fabsf(th) * 1e-6f);
-                    const size_t o = ((size_t)t * nwg + wgx) * Np_pad + j;
-                    cpart[o] = lower_bf16_bits(best);
-                    ctag[o] = (uint8_t)(bg | (amb ? 0x80 : 0));
-                }
-            }
-        }
+    }
+    if (COLS) {  // the last stage's partials
+        __syncthreads();
+        merge_stage(nstage - 1);
     }
 
     // row certificate and candidate records; the 16 lanes of a group share one row per (a, r)
@@ -833,19 +848,21 @@ __device__ __forceinline__ void colrefine_body(const RefineParams &pr, const Blk
         for (int e = 0; e < n; ++e) {
             const int code = rr[1 + e];
             const int wg = code >> 8, grp = code & 0x7f;
-            const int wv = grp >> 2, gg = grp & 3;
+            const int wv = grp >> 1, h = grp & 1;
             if (code & 0x80) {  // ambiguous: every row of the workgroup
                 for (int k = 0; k < SC_ROWS / RF_TEAM; ++k) {
                     const int i = wg * SC_ROWS + k * RF_TEAM + tl;
                     if (i < Na) lex_min(best, bi, canon_d2(qx, qy, qz, At + 3 * (size_t)i), i);
                 }
-            } else {  // the row group: rows 16a + 4g + r of its wave, lane tl = 4a + r
+            } else {  // the row group: rows 16a + 4g + r of its wave, g in {h, h + 2}
+                constexpr int PER_G = SC_ATILES * 4;
 #pragma unroll
-                for (int k = 0; k < (SC_ATILES * 4 + RF_TEAM - 1) / RF_TEAM; ++k) {
+                for (int k = 0; k < (2 * PER_G + RF_TEAM - 1) / RF_TEAM; ++k) {
                     const int ar = k * RF_TEAM + tl;
-                    if (ar < SC_ATILES * 4) {
-                        const int i = wg * SC_ROWS + wv * (SC_ATILES * 16) + 16 * (ar >> 2) +
-                                      4 * gg + (ar & 3);
+                    if (ar < 2 * PER_G) {
+                        const int gg = h + 2 * (ar / PER_G), rem = ar % PER_G;
+                        const int i = wg * SC_ROWS + wv * (SC_ATILES * 16) + 16 * (rem >> 2) +
+                                      4 * gg + (rem & 3);
                         if (i < Na)
                             lex_min(best, bi, canon_d2(qx, qy, qz, At + 3 * (size_t)i), i);
                     }
