@@ -370,10 +370,17 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
     auto target_of = [&](int st, int u) {
         return (st / SPC) * SC_CHUNK + SC_TPS * (st % SPC) + soff[u];
     };
-    // register prefetch of the next stage's operands, double-buffered LDS
+    // register prefetch of the next stage's operands, double-buffered LDS.  The column threshold
+    // slack of the targets a thread stages is prefetched with them and kept until the thread
+    // reduces those same targets one stage later (sl_prev: stage st - 1, sl_cur: st, sl_next:
+    // st + 1), so the reduction never waits on memory.
+    const float *slack_t = slack + (size_t)t * Np_pad;
+    float sl_prev[SC_PER_THREAD], sl_cur[SC_PER_THREAD], sl_next[SC_PER_THREAD];
     bf16x8 q[SC_PER_THREAD][3];
 #pragma unroll
     for (int u = 0; u < SC_PER_THREAD; ++u) {
+        sl_prev[u] = sl_next[u] = 0.f;
+        sl_cur[u] = COLS ? slack_t[target_of(0, u)] : 0.f;
         const bf16x8 *src = Bt + (size_t)target_of(0, u) * 3;
         q[u][0] = src[0];
         q[u][1] = src[1];
@@ -381,6 +388,8 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
     }
     const int gk = (g == 3) ? 0 : g;
     // reduce the workgroup's row groups per target of stage sm and write its partial
+    // reduce the workgroup's row groups per target of stage sm and write its partial (padding
+    // targets too: the partial arrays span the padded target range)
     auto merge_stage = [&](int sm) {
         const int cb = sm & 1;
 #pragma unroll
@@ -397,15 +406,13 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
                 bg = v < best ? k : bg;
                 best = fminf(best, v);
             }
-            if (j < Np) {
-                // another row group within the margin of this group's best: the merge must
-                // rescan every row of the workgroup for this target
-                const float th = threshold_affine(best, slack[(size_t)t * Np_pad + j]);
-                const bool amb = !(second > th + fabsf(th) * 1e-6f);
-                const size_t o = ((size_t)t * nwg + wgx) * Np_pad + j;
-                cpart[o] = lower_bf16_bits(best);
-                ctag[o] = (uint8_t)(bg | (amb ? 0x80 : 0));
-            }
+            // another row group within the margin of this group's best: the merge must rescan
+            // every row of the workgroup for this target
+            const float th = threshold_affine(best, sl_prev[u]);
+            const bool amb = !(second > th + fabsf(th) * 1e-6f);
+            const size_t o = ((size_t)t * nwg + wgx) * Np_pad + j;
+            cpart[o] = lower_bf16_bits(best);
+            ctag[o] = (uint8_t)(bg | (amb ? 0x80 : 0));
         }
     };
     for (int st = 0; st < nstage; ++st) {
@@ -419,6 +426,7 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
         if (st + 1 < nstage) {
 #pragma unroll
             for (int u = 0; u < SC_PER_THREAD; ++u) {
+                if (COLS) sl_next[u] = slack_t[target_of(st + 1, u)];
                 const bf16x8 *src = Bt + (size_t)target_of(st + 1, u) * 3;
                 q[u][0] = src[0];
                 q[u][1] = src[1];
@@ -482,6 +490,11 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
                     m[a][r] = inf;
                 }
         }
+#pragma unroll
+        for (int u = 0; u < SC_PER_THREAD; ++u) {
+            sl_prev[u] = sl_cur[u];
+            sl_cur[u] = sl_next[u];
+        }
     }
     if (COLS) {  // the last stage's partials
         __syncthreads();
@@ -535,9 +548,10 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
 
 // Direct launch, in an XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs, so
 // the hardware ids of one XCD are mapped onto one contiguous range of (frame, row block) items and
-// each XCD's L2 holds the packed targets of about T/8 frames instead of every frame.
+// each XCD's L2 holds the packed targets of about T/8 frames instead of every frame.  Three
+// workgroups per compute unit (at most 168 registers per lane) keep three waves on every SIMD.
 template <bool COLS>
-__global__ __launch_bounds__(SC_THREADS) void k_screen(ScreenParams p) {
+__global__ __launch_bounds__(SC_THREADS, 3) void k_screen(ScreenParams p) {
     Blk b;
     b.gx = gridDim.x;
     b.gy = gridDim.y;
