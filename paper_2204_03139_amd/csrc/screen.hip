@@ -749,6 +749,26 @@ __device__ __forceinline__ void flush_stats(unsigned *cnt, unsigned long long *s
     }
 }
 
+// The workgroup's query records and query points, staged in LDS with coalesced loads issued
+// together: the teams then meet global memory only for the points they compare against.
+template <int INTS>
+__device__ __forceinline__ void stage_queries(const int32_t *rec, const float *Q, int t, int Nq,
+                                              int i0, int32_t *srec, float *sq) {
+    const int nq = min(RF_QUERIES, Nq - i0);
+    const int32_t *rb = rec + ((size_t)t * Nq + i0) * INTS;
+    const float *qb = Q + ((size_t)t * Nq + i0) * 3;
+#pragma unroll
+    for (int u = 0; u < RF_QUERIES * INTS / RF_THREADS; ++u) {
+        const int k = threadIdx.x + u * RF_THREADS;
+        if (k < nq * INTS) srec[k] = rb[k];
+    }
+#pragma unroll
+    for (int u = 0; u < RF_QUERIES * 3 / RF_THREADS; ++u) {
+        const int k = threadIdx.x + u * RF_THREADS;
+        if (k < nq * 3) sq[k] = qb[k];
+    }
+}
+
 // Row refine (a -> b): candidate slot groups of light rows; heavy rows are left to the exact
 // kernel.  A team of 16 lanes takes one query; each 64-target step gives every lane 4 consecutive
 // targets (48 contiguous bytes).
@@ -771,25 +791,29 @@ __device__ __forceinline__ void refine_body(const RefineParams &pr, const Blk &b
     float *__restrict__ dist = pr.dist;
     unsigned long long *__restrict__ stats = pr.stats;
     __shared__ unsigned cnt[2];
-    if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
-    __syncthreads();
+    __shared__ int32_t srec[RF_QUERIES * REC_INTS];
+    __shared__ float sq[RF_QUERIES * 3];
     const int t = blk.y;
+    if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+    stage_queries<REC_INTS>(rec, Q, t, Nq, blk.x * RF_QUERIES, srec, sq);
+    __syncthreads();
     const int team = threadIdx.x / RF_TEAM, tl = threadIdx.x % RF_TEAM;
     const float *Pt = P + (size_t)t * Np * 3;
     unsigned my_cand = 0, my_heavy = 0;
     for (int qq = 0; qq < RF_QUERIES / RF_TEAMS; ++qq) {
-        const int i = blk.x * RF_QUERIES + qq * RF_TEAMS + team;
-        const int32_t *rr = rec + ((size_t)t * Nq + min(i, Nq - 1)) * REC_INTS;
+        const int li = qq * RF_TEAMS + team;
+        const int i = blk.x * RF_QUERIES + li;
+        const int32_t *rr = srec + li * REC_INTS;
         const int n = (i < Nq) ? rr[0] : -2;
         float qx = 0.f, qy = 0.f, qz = 0.f;
         if (n >= 0) {
-            const float *q = Q + ((size_t)t * Nq + i) * 3;
-            qx = q[0];
-            qy = q[1];
-            qz = q[2];
+            qx = sq[3 * li];
+            qy = sq[3 * li + 1];
+            qz = sq[3 * li + 2];
         }
         float best = __builtin_inff();
         int bj = 0x7fffffff;
+#pragma unroll 2
         for (int e = 0; e < n * (SC_RUN / 64); ++e) {
             const int code = rr[2 + e / (SC_RUN / 64)];
             const int j = (code >> 4) * SC_CHUNK + SC_RUN * (code & 15) + 64 * (e % (SC_RUN / 64)) +
@@ -829,8 +853,8 @@ __device__ __forceinline__ void refine_body(const RefineParams &pr, const Blk &b
 
 __global__ __launch_bounds__(RF_THREADS) void k_refine(RefineParams p) { refine_body(p, grid_blk()); }
 
-// Column refine (b -> a): each candidate workgroup contributes its winning row group (16 rows:
-// one per lane) or, when flagged ambiguous, all of its rows.
+// Column refine (b -> a): each candidate workgroup contributes its winning row group (32 rows:
+// two per lane) or, when flagged ambiguous, all of its rows.
 __device__ __forceinline__ void colrefine_body(const RefineParams &pr, const Blk &blk) {
     const float *__restrict__ B = pr.Q;
     const float *__restrict__ A = pr.P;
@@ -840,22 +864,25 @@ __device__ __forceinline__ void colrefine_body(const RefineParams &pr, const Blk
     float *__restrict__ dist = pr.dist;
     unsigned long long *__restrict__ stats = pr.stats;
     __shared__ unsigned cnt[2];
-    if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
-    __syncthreads();
+    __shared__ int32_t srec[RF_QUERIES * CREC_INTS];
+    __shared__ float sq[RF_QUERIES * 3];
     const int t = blk.y;
+    if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+    stage_queries<CREC_INTS>(crec, B, t, Nb, blk.x * RF_QUERIES, srec, sq);
+    __syncthreads();
     const int team = threadIdx.x / RF_TEAM, tl = threadIdx.x % RF_TEAM;
     const float *At = A + (size_t)t * Na * 3;
     unsigned my_cand = 0, my_heavy = 0;
     for (int qq = 0; qq < RF_QUERIES / RF_TEAMS; ++qq) {
-        const int j = blk.x * RF_QUERIES + qq * RF_TEAMS + team;
-        const int32_t *rr = crec + ((size_t)t * Nb + min(j, Nb - 1)) * CREC_INTS;
+        const int lj = qq * RF_TEAMS + team;
+        const int j = blk.x * RF_QUERIES + lj;
+        const int32_t *rr = srec + lj * CREC_INTS;
         const int n = (j < Nb) ? rr[0] : -2;
         float qx = 0.f, qy = 0.f, qz = 0.f;
         if (n >= 0) {
-            const float *q = B + ((size_t)t * Nb + j) * 3;
-            qx = q[0];
-            qy = q[1];
-            qz = q[2];
+            qx = sq[3 * lj];
+            qy = sq[3 * lj + 1];
+            qz = sq[3 * lj + 2];
         }
         float best = __builtin_inff();
         int bi = 0x7fffffff;
