@@ -33,8 +33,8 @@ SCREEN_ISSUE_CEILING = CUS * SIMDS_PER_CU * PEAK_CLOCK_HZ / (5 * 4) * 256
 # HBM bytes of one k_screen launch on this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled
 # by a plain-copy calibration (profiles/k_screen_grid100_65536pts_100frames_counters.md); valid
 # only for the screen source they were measured on.
-SCREEN_TRAFFIC = dict(source_sha256="ed49105ad6500b7f2346a0731a76cae18bece5537e655a38b89209668df2ee28",
-                      bytes=2868097191 + 5243433288)
+SCREEN_TRAFFIC = dict(source_sha256="9495747c086798c7ecf436a261d572ef9bbdd5b2b3cd3d2e78ad647e91055ca6",
+                      bytes=2870152978 + 5243867832)
 
 
 def _screen_traffic():
