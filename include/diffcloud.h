@@ -15,8 +15,10 @@
  *    call's stream work.  Pointers marked "host" are ordinary host memory.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Direct calls are
  *    asynchronous: they validate their arguments on the host, enqueue kernels on `stream` and
- *    return.  Calls that share one context must be ordered on one stream (or otherwise not overlap
- *    in time), since they share the context's scratch memory.
+ *    return.  Calls that share one context share its scratch memory: a call on a different stream
+ *    than the previous call of the context first makes its stream wait (on the device) for the
+ *    previous call's work, so such calls never overlap in time.  The caller still orders its own
+ *    data dependences between streams.
  *  - Every entry point returns a status code.  No exception crosses the ABI.  Argument errors are
  *    reported immediately.  Errors that only the device can see (a face index outside [0, V), a
  *    frame whose total area is zero or not finite) set a sticky status word in the context, and

@@ -67,7 +67,9 @@ void dev_free(dc_ctx *ctx, void *p, size_t bytes) {
     budget_give(ctx, bytes);
 }
 
-int arena_reserve(dc_ctx *ctx, size_t bytes) {
+int arena_reserve(dc_ctx *ctx, size_t bytes, hipStream_t s) {
+    if (ctx->arena_used && s != ctx->arena_stream)
+        DC_HIP(hipStreamWaitEvent(s, ctx->arena_ev, 0));
     Arena &a = ctx->arena;
     a.reset();
     if (bytes <= a.cap) return DC_OK;
@@ -83,6 +85,18 @@ int arena_reserve(dc_ctx *ctx, size_t bytes) {
     a.base = static_cast<char *>(p);
     a.cap = want;
     return DC_OK;
+}
+
+ArenaUse::~ArenaUse() {
+    if (hipEventRecord(ctx->arena_ev, s) == hipSuccess) {
+        ctx->arena_stream = s;
+        ctx->arena_used = true;
+    } else {
+        // without a record the next call cannot order itself after this one: wait here instead
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(s);
+        ctx->arena_used = false;
+    }
 }
 
 static int check_dims(int T, std::initializer_list<long> sizes) {
@@ -201,10 +215,12 @@ int dc_create(dc_ctx **out, int device, size_t hbm_budget_bytes, int max_slots) 
     if (e == hipSuccess) e = hipMalloc(&c->d_stats, sizeof(unsigned long long) * 4);
     if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(unsigned) * 4);
     if (e == hipSuccess) e = hipMemset(c->d_stats, 0, sizeof(unsigned long long) * 4);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->arena_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         (void)hipFree(c->d_status);
         (void)hipFree(c->d_stats);
+        if (c->arena_ev) (void)hipEventDestroy(c->arena_ev);
         delete c;
         return hip_fail(e, "dc_create");
     }
@@ -224,6 +240,7 @@ int dc_destroy(dc_ctx *ctx) {
     dev_free(ctx, ctx->arena.base, ctx->arena.cap);
     (void)hipFree(ctx->d_status);
     (void)hipFree(ctx->d_stats);
+    (void)hipEventDestroy(ctx->arena_ev);
     delete ctx;
     return DC_OK;
 }
@@ -317,8 +334,9 @@ static int sample_surface_impl(dc_ctx *ctx, const float *verts, const int32_t *f
     if (rc) return rc;
     DC_HIP(hipSetDevice(ctx->device));
     std::lock_guard<std::mutex> g(ctx->mu);
-    rc = arena_reserve(ctx, sample_scratch_bytes(T, F));
+    rc = arena_reserve(ctx, sample_scratch_bytes(T, F), static_cast<hipStream_t>(stream));
     if (rc) return rc;
+    ArenaUse use{ctx, static_cast<hipStream_t>(stream)};
     return enqueue_sample(ctx, verts, faces, T, V, F, N, seed, uniforms, mask, mask_per_frame,
                           points, face_idx, bary, ctx->arena, ctx->d_status,
                           static_cast<hipStream_t>(stream));
@@ -357,8 +375,9 @@ int dc_sample_surface_bwd(dc_ctx *ctx, const float *grad_points, const int32_t *
     DC_HIP(hipSetDevice(ctx->device));
     std::lock_guard<std::mutex> g(ctx->mu);
     const size_t need = sample_bwd_scratch_bytes(T, V, F, N);
-    rc = arena_reserve(ctx, need);
+    rc = arena_reserve(ctx, need, static_cast<hipStream_t>(stream));
     if (rc) return rc;
+    ArenaUse use{ctx, static_cast<hipStream_t>(stream)};
     ProfScope ps(ctx, 3, static_cast<hipStream_t>(stream));
     launch_sample_bwd(grad_points, faces, face_idx, bary, T, V, F, N, grad_verts,
                       ctx->arena.take<char>(need), static_cast<hipStream_t>(stream));
@@ -396,8 +415,9 @@ int dc_chamfer_fwd(dc_ctx *ctx, const float *a, const float *b, int T, int Na, i
     DC_HIP(hipSetDevice(ctx->device));
     std::lock_guard<std::mutex> g(ctx->mu);
     const size_t need = chamfer_fwd_scratch_bytes(T, Na, Nb, precision);
-    rc = arena_reserve(ctx, need);
+    rc = arena_reserve(ctx, need, static_cast<hipStream_t>(stream));
     if (rc) return rc;
+    ArenaUse use{ctx, static_cast<hipStream_t>(stream)};
     return enqueue_chamfer_fwd(ctx, a, b, T, Na, Nb, precision, reduction, frame_w, dist_a, idx_a,
                                dist_b, idx_b, loss, ctx->arena.take<char>(need), ctx->d_stats,
                                static_cast<hipStream_t>(stream));
@@ -425,8 +445,9 @@ int dc_chamfer_bwd(dc_ctx *ctx, const double *grad_loss, const float *a, const f
     DC_HIP(hipSetDevice(ctx->device));
     std::lock_guard<std::mutex> g(ctx->mu);
     const size_t need = chamfer_bwd_scratch_bytes(T, Na, Nb, grad_b != nullptr);
-    rc = arena_reserve(ctx, need);
+    rc = arena_reserve(ctx, need, static_cast<hipStream_t>(stream));
     if (rc) return rc;
+    ArenaUse use{ctx, static_cast<hipStream_t>(stream)};
     ProfScope ps(ctx, 3, static_cast<hipStream_t>(stream));
     launch_chamfer_bwd(grad_loss, a, b, idx_a, idx_b, T, Na, Nb, reduction, frame_w, grad_a,
                        grad_b, ctx->arena.take<char>(need), static_cast<hipStream_t>(stream));

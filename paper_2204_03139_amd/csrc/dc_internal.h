@@ -63,6 +63,9 @@ struct dc_ctx {
     std::mutex budget_mu;         // guards budget accounting
     size_t held = 0;              // bytes of device memory held against the budget
     dc::Arena arena;              // scratch of direct calls
+    hipEvent_t arena_ev = nullptr;        // recorded after each direct call's work on its stream
+    hipStream_t arena_stream = nullptr;   // the stream of the last direct call
+    bool arena_used = false;
     unsigned *d_status = nullptr;           // sticky device status word
     unsigned long long *d_stats = nullptr;  // [3] screen counters
     dc::Scheduler *sched = nullptr;
@@ -82,8 +85,16 @@ void budget_give(dc_ctx *ctx, size_t bytes);
 // device allocation counted against the budget
 int dev_alloc(dc_ctx *ctx, void **p, size_t bytes);
 void dev_free(dc_ctx *ctx, void *p, size_t bytes);
-// make sure the direct-call arena holds at least `bytes`; resets its offset
-int arena_reserve(dc_ctx *ctx, size_t bytes);
+// Make sure the direct-call arena holds at least `bytes` and reset its offset.  When the previous
+// direct call ran on another stream, `s` first waits for that call's work, so calls on different
+// streams never share the scratch in time.
+int arena_reserve(dc_ctx *ctx, size_t bytes, hipStream_t s);
+// mark the end of a direct call's use of the arena (records the arena event on `s`)
+struct ArenaUse {
+    dc_ctx *ctx;
+    hipStream_t s;
+    ~ArenaUse();
+};
 
 // start / stop an event pair around the launches of category `cat` (no-op unless profiling)
 struct ProfScope {

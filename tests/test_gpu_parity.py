@@ -454,6 +454,33 @@ def test_determinism():
         assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
 
 
+def test_calls_on_two_streams():
+    """Direct calls of one context issued back to back on two streams share its scratch memory:
+    the second waits for the first on the device, and both return exactly the results of calls
+    made one after the other on one stream."""
+    p = gpu()
+    say("[streams] two streams, one context")
+    r = np.random.default_rng(71)
+    A1 = dev(r.uniform(-.5, .5, (24, 32768, 3)).astype(np.float32))
+    B1 = dev(r.uniform(-.5, .5, (24, 32768, 3)).astype(np.float32))
+    A2 = dev(r.uniform(-.5, .5, (3, 5000, 3)).astype(np.float32))
+    B2 = dev(r.uniform(-.5, .5, (3, 7000, 3)).astype(np.float32))
+    ctx = p.Context(0)
+    ref1 = {k: host(v).copy() for k, v in p.chamfer_fwd(A1, B1, precision=1, ctx=ctx).items()}
+    ref2 = {k: host(v).copy() for k, v in p.chamfer_fwd(A2, B2, precision=1, ctx=ctx).items()}
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s1):
+        g1 = p.chamfer_fwd(A1, B1, precision=1, ctx=ctx)
+    with torch.cuda.stream(s2):
+        g2 = p.chamfer_fwd(A2, B2, precision=1, ctx=ctx)
+    torch.cuda.synchronize()
+    for ref, g in ((ref1, g1), (ref2, g2)):
+        for k, v in ref.items():
+            assert np.array_equal(host(g[k]).view(np.uint8), v.view(np.uint8)), k
+    ctx.close()
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_full_size_sampled(precision):
     """The 100-frame, 65,536 x 65,536 workload in the benchmark's launch configuration: sampled
