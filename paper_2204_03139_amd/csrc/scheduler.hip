@@ -8,10 +8,11 @@
 // their work overlaps with the batches already running.
 //
 // A batch runs as one replay of a graph built once per slot: the fixed program below, one
-// persistent kernel node per stage, with the stages that have no work in the batch switched off.  For every request the host code of the direct calls is run in
-// recording mode, which yields the request's launches (kernel, logical grid, parameters) instead
-// of executing them; each launch is assigned, in order, to the next program stage of its kernel,
-// and the batch's stage tables are uploaded to the slot's device descriptor before the replay.
+// persistent kernel node per stage, with the stages that have no work in the batch switched off.
+// For every request the host code of the direct calls is run in recording mode, which yields the
+// request's launches (kernel, logical grid, parameters) instead of executing them; each launch is
+// assigned, in order, to the next program stage of its kernel, and the batch's stage tables are
+// uploaded to the slot's device descriptor before the replay.
 // Inputs are uploaded from pinned staging in one copy per request, results come back the same
 // way, and an event marks the batch's completion.  Every request executes exactly the launches
 // of its direct calls, so its results do not depend on what it is batched with.
