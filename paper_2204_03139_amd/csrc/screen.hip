@@ -7,8 +7,8 @@
 // Each float coordinate is split exactly into three bf16 parts (x = h + m + l); the products
 // hH, hM, mH, hL, lH, mM per coordinate (18 K-slots) plus the two norms in three parts each (6
 // K-slots) fill 24 of the 32 K-slots, so the matrix unit produces the whole screened distance.
-// Rows a stay in registers (64 per wave, four 16-row tiles); the b operands (packed once per
-// frame) stream through a double-buffered LDS stage.  Every 16x16 result tile feeds both
+// Rows a stay in registers (16-row tiles: six per wave for both directions, four for one); the
+// b operands (packed once per frame) stream through a double-buffered LDS stage.  Every 16x16 result tile feeds both
 // directions with v_min3 only:
 //   rows (a -> b): each (lane, row) folds its column of every tile into a running minimum;
 //     targets are laid out so that, inside each chunk of SC_CHUNK, result column c holds a
@@ -50,8 +50,16 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 #endif
 constexpr int SC_WAVES = 4;
 constexpr int SC_THREADS = 64 * SC_WAVES;
-constexpr int SC_ATILES = DC_SCREEN_ATILES;              // 16-row tiles per wave
-constexpr int SC_ROWS = SC_WAVES * SC_ATILES * 16;       // query rows per workgroup
+#ifndef DC_SCREEN_ATILES_COLS
+#define DC_SCREEN_ATILES_COLS 6
+#endif
+// 16-row query tiles per wave: the one-direction screen keeps three workgroups per compute unit
+// with four; the two-direction screen amortises its per-stage column reduction over six tiles
+// (at two workgroups per compute unit), which measured faster for it and slower for the other
+template <bool COLS>
+constexpr int sc_atiles() { return COLS ? DC_SCREEN_ATILES_COLS : DC_SCREEN_ATILES; }
+template <bool COLS>
+constexpr int sc_rows() { return SC_WAVES * sc_atiles<COLS>() * 16; }  // query rows per workgroup
 constexpr int SC_STAGE = DC_SCREEN_STAGE;                // targets staged in LDS per step
 constexpr int SC_CHUNK = DC_SCREEN_CHUNK;                // targets per tracking chunk
 constexpr int SC_TPS = SC_STAGE / 16;                    // tiles per stage
@@ -300,6 +308,8 @@ struct ScreenParams {
 // logical workgroup: x = row block of the frame, y = frame, gx = row blocks per frame
 template <bool COLS>
 __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &blk) {
+    constexpr int ATILES = sc_atiles<COLS>();  // 16-row query tiles per wave
+    constexpr int ROWS = sc_rows<COLS>();      // query rows per workgroup
     const float *__restrict__ Q = pr.Q;
     const bf16x8 *__restrict__ packed = pr.packed;
     const float *__restrict__ slack = pr.slack;
@@ -324,12 +334,12 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
     const int col = lane & 15; // row of the A operand; column (slot) of the result
     const float *Qt = Q + (size_t)t * Nq * 3;
     const bf16x8 *Bt = packed + (size_t)t * Np_pad * 3;
-    const int row0 = wgx * SC_ROWS + wave * (SC_ATILES * 16);
+    const int row0 = wgx * ROWS + wave * (ATILES * 16);
 
     // query operands, held for the whole sweep
-    bf16x8 A[SC_ATILES];
+    bf16x8 A[ATILES];
 #pragma unroll
-    for (int a = 0; a < SC_ATILES; ++a) {
+    for (int a = 0; a < ATILES; ++a) {
         const int r = row0 + 16 * a + col;
         __bf16 v[32];
         if (r < Nq)
@@ -342,10 +352,10 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
     // per (lane, row): running minimum of the current chunk, the three best chunk minima, and
     // the chunks of the best two packed as (best << 16) | second (0xFFFF = none)
     const float inf = __builtin_inff();
-    float m[SC_ATILES][4], b1[SC_ATILES][4], b2[SC_ATILES][4], b3[SC_ATILES][4];
-    unsigned cc[SC_ATILES][4];
+    float m[ATILES][4], b1[ATILES][4], b2[ATILES][4], b3[ATILES][4];
+    unsigned cc[ATILES][4];
 #pragma unroll
-    for (int a = 0; a < SC_ATILES; ++a)
+    for (int a = 0; a < ATILES; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             m[a][r] = inf;
@@ -449,7 +459,7 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
             }
             float cm0 = inf, cm1 = inf;
 #pragma unroll
-            for (int a = 0; a < SC_ATILES; ++a) {
+            for (int a = 0; a < ATILES; ++a) {
                 const floatx4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B0, zero, 0, 0, 0);
                 const floatx4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B1, zero, 0, 0, 0);
 #pragma unroll
@@ -474,7 +484,7 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
         if ((st + 1) % SPC == 0) {  // end of a tracking chunk
             const unsigned k = (unsigned)(st / SPC);
 #pragma unroll
-            for (int a = 0; a < SC_ATILES; ++a)
+            for (int a = 0; a < ATILES; ++a)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const float x = m[a][r];
@@ -506,7 +516,7 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
     const unsigned long long gmask = 0xFFFFull << (16 * g);
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-    for (int a = 0; a < SC_ATILES; ++a)
+    for (int a = 0; a < ATILES; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = row0 + 16 * a + 4 * g + r;
@@ -551,7 +561,7 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
 // each XCD's L2 holds the packed targets of about T/8 frames instead of every frame.  Three
 // workgroups per compute unit (at most 168 registers per lane) keep three waves on every SIMD.
 template <bool COLS>
-__global__ __launch_bounds__(SC_THREADS, 3) void k_screen(ScreenParams p) {
+__global__ __launch_bounds__(SC_THREADS, sc_atiles<COLS>() <= 4 ? 3 : 2) void k_screen(ScreenParams p) {
     Blk b;
     b.gx = gridDim.x;
     b.gy = gridDim.y;
@@ -891,19 +901,19 @@ __device__ __forceinline__ void colrefine_body(const RefineParams &pr, const Blk
             const int wg = code >> 8, grp = code & 0x7f;
             const int wv = grp >> 1, h = grp & 1;
             if (code & 0x80) {  // ambiguous: every row of the workgroup
-                for (int k = 0; k < SC_ROWS / RF_TEAM; ++k) {
-                    const int i = wg * SC_ROWS + k * RF_TEAM + tl;
+                for (int k = 0; k < sc_rows<true>() / RF_TEAM; ++k) {
+                    const int i = wg * sc_rows<true>() + k * RF_TEAM + tl;
                     if (i < Na) lex_min(best, bi, canon_d2(qx, qy, qz, At + 3 * (size_t)i), i);
                 }
             } else {  // the row group: rows 16a + 4g + r of its wave, g in {h, h + 2}
-                constexpr int PER_G = SC_ATILES * 4;
+                constexpr int PER_G = sc_atiles<true>() * 4;
 #pragma unroll
                 for (int k = 0; k < (2 * PER_G + RF_TEAM - 1) / RF_TEAM; ++k) {
                     const int ar = k * RF_TEAM + tl;
                     if (ar < 2 * PER_G) {
                         const int gg = h + 2 * (ar / PER_G), rem = ar % PER_G;
-                        const int i = wg * SC_ROWS + wv * (SC_ATILES * 16) + 16 * (rem >> 2) +
-                                      4 * gg + (rem & 3);
+                        const int i = wg * sc_rows<true>() + wv * (sc_atiles<true>() * 16) +
+                                      16 * (rem >> 2) + 4 * gg + (rem & 3);
                         if (i < Na)
                             lex_min(best, bi, canon_d2(qx, qy, qz, At + 3 * (size_t)i), i);
                     }
@@ -939,7 +949,8 @@ bool screen_available() { return true; }
 static int padded_targets(int Np) { return ((Np + SC_CHUNK - 1) / SC_CHUNK) * SC_CHUNK; }
 
 size_t screen_scratch_bytes(int T, int Na, int Nb) {
-    const size_t nwg = (size_t)(Na + SC_ROWS - 1) / SC_ROWS;
+    // column partials exist only for the two-direction screen, whose row blocks they follow
+    const size_t nwg = (size_t)(Na + sc_rows<true>() - 1) / sc_rows<true>();
     const size_t Nb_pad = padded_targets(Nb);
     return Arena::need((size_t)T, 4) * 4 +                           // norms, heavy counts
            Arena::need((size_t)T * Na, 4) + Arena::need((size_t)T * Nb, 4) +  // heavy lists
@@ -959,7 +970,8 @@ void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int
     Arena ar;
     ar.base = scratch;
     ar.cap = screen_scratch_bytes(T, Na, Nb);
-    const int nwg = (Na + SC_ROWS - 1) / SC_ROWS;
+    const int nwg = (Na + sc_rows<true>() - 1) / sc_rows<true>();        // two directions
+    const int nwg_rows = (Na + sc_rows<false>() - 1) / sc_rows<false>();  // one direction
     const int Nb_pad = padded_targets(Nb);
     float *nbmax = ar.take<float>((size_t)T);
     float *namax = ar.take<float>((size_t)T);
@@ -1014,7 +1026,7 @@ void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int
         if (cols)
             dispatch(KT_SCREEN, k_screen<true>, dim3(nwg, T), SC_THREADS, sp, s);
         else
-            dispatch(KT_SCREEN_ROWS, k_screen<false>, dim3(nwg, T), SC_THREADS, sp, s);
+            dispatch(KT_SCREEN_ROWS, k_screen<false>, dim3(nwg_rows, T), SC_THREADS, sp, s);
     }
     {
         ProfScope ps(prof, 1, s);
