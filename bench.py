@@ -33,8 +33,8 @@ SCREEN_ISSUE_CEILING = CUS * SIMDS_PER_CU * PEAK_CLOCK_HZ / (5 * 4) * 256
 # HBM bytes of one k_screen launch on this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled
 # by a plain-copy calibration (profiles/k_screen_grid100_65536pts_100frames_counters.md); valid
 # only for the screen source they were measured on.
-SCREEN_TRAFFIC = dict(source_sha256="9495747c086798c7ecf436a261d572ef9bbdd5b2b3cd3d2e78ad647e91055ca6",
-                      bytes=2870152978 + 5243867832)
+SCREEN_TRAFFIC = dict(source_sha256="d05f0634a3bc2523e8c6df6b67b314ca354b1b836d36676525fa5229cd50c886",
+                      bytes=2288081999 + 3571902024)
 
 
 def _screen_traffic():
