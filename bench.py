@@ -33,7 +33,7 @@ SCREEN_ISSUE_CEILING = CUS * SIMDS_PER_CU * PEAK_CLOCK_HZ / (5 * 4) * 256
 # HBM bytes of one k_screen launch on this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled
 # by a plain-copy calibration (profiles/k_screen_grid100_65536pts_100frames_counters.md); valid
 # only for the screen source they were measured on.
-SCREEN_TRAFFIC = dict(source_sha256="d05f0634a3bc2523e8c6df6b67b314ca354b1b836d36676525fa5229cd50c886",
+SCREEN_TRAFFIC = dict(source_sha256="e7e5f9553aede85ef6f0e3addf7752b2ea7b9bb4effaae2cc792baa6925402cf",
                       bytes=2288081999 + 3571902024)
 
 
@@ -250,8 +250,9 @@ def run_serving(p, torch, rate_hz=None, n_requests=None, budget_bytes=64 << 30, 
 def main():
     a = _args()
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(the sharding design is described in the design notes); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -45,7 +45,7 @@ extern "C" {
 #define DC_ERR_BUDGET (-3)     /* the work can never fit the context's HBM budget */
 #define DC_ERR_HIP (-4)        /* a HIP runtime call failed; see dc_last_error() */
 #define DC_ERR_DEGENERATE (-5) /* a frame's total surface area is zero or not finite */
-#define DC_ERR_UNSUPPORTED (-6)/* valid request this build does not support */
+#define DC_ERR_UNSUPPORTED (-6)/* a valid request the library cannot run (serving program) */
 
 /* precision of the all-pairs nearest-neighbour search (both give the same indices) */
 #define DC_PREC_FP32 0        /* exact single-precision search on the vector ALUs */

@@ -408,10 +408,6 @@ int dc_chamfer_fwd(dc_ctx *ctx, const float *a, const float *b, int T, int Na, i
     }
     int rc = check_dims(T, {Na, Nb});
     if (rc) return rc;
-    if (precision == DC_PREC_BF16_REFINE && !screen_available()) {
-        set_error("the bf16 screen is not available in this build");
-        return DC_ERR_UNSUPPORTED;
-    }
     DC_HIP(hipSetDevice(ctx->device));
     std::lock_guard<std::mutex> g(ctx->mu);
     const size_t need = chamfer_fwd_scratch_bytes(T, Na, Nb, precision);

@@ -126,7 +126,6 @@ void launch_nn_exact_list(const float *Q, int Nq, const float *P, int Np, int T,
 
 // bf16 matrix-core screen + certified exact refine, both directions in one pass (the same
 // indices and distances as two exact fp32 searches)
-bool screen_available();
 size_t screen_scratch_bytes(int T, int Na, int Nb);
 void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int T,
                              int32_t *idx_a, float *dist_a, int32_t *idx_b, float *dist_b,

@@ -944,7 +944,6 @@ __global__ __launch_bounds__(RF_THREADS) void k_colrefine(RefineParams p) {
 
 }  // namespace
 
-bool screen_available() { return true; }
 
 static int padded_targets(int Np) { return ((Np + SC_CHUNK - 1) / SC_CHUNK) * SC_CHUNK; }
 
