@@ -185,6 +185,15 @@ CHAMFER_CASES = {
     "ragged-1025x3": lambda: (
         np.random.default_rng(5).uniform(-.5, .5, (1, 1025, 3)).astype(np.float32),
         np.random.default_rng(6).uniform(-.5, .5, (1, 3, 3)).astype(np.float32)),
+    "tall-70000x5": lambda: (
+        np.random.default_rng(9).uniform(-.5, .5, (2, 70000, 3)).astype(np.float32),
+        np.random.default_rng(10).uniform(-.5, .5, (2, 5, 3)).astype(np.float32)),
+    "wide-3x70000": lambda: (
+        np.random.default_rng(11).uniform(-.5, .5, (2, 3, 3)).astype(np.float32),
+        np.random.default_rng(12).uniform(-.5, .5, (2, 70000, 3)).astype(np.float32)),
+    "frames-500x300x257": lambda: (
+        np.random.default_rng(13).uniform(-.5, .5, (500, 300, 3)).astype(np.float32),
+        np.random.default_rng(14).uniform(-.5, .5, (500, 257, 3)).astype(np.float32)),
     "slices-2x20000": lambda: (
         np.random.default_rng(7).uniform(-.5, .5, (1, 20000, 3)).astype(np.float32),
         np.random.default_rng(8).uniform(-.5, .5, (1, 20000, 3)).astype(np.float32)),
