@@ -13,7 +13,7 @@ namespace dc {
 namespace {
 
 constexpr int AC_THREADS = 256;
-constexpr int AC_CHUNK = 4096;  // faces staged in LDS per step (32 KiB of doubles)
+constexpr int AC_CHUNK = 4000;  // faces per chunk: two chunk buffers of doubles stay under 64 KiB
 
 __device__ __forceinline__ bool face_ok(const int32_t *fv, int V) {
     return fv[0] >= 0 && fv[0] < V && fv[1] >= 0 && fv[1] < V && fv[2] >= 0 && fv[2] < V;
@@ -45,26 +45,28 @@ struct AreaCdfParams {
     unsigned *status;
 };
 
+// Chunks of AC_CHUNK faces are double-buffered in LDS: while one lane of wave 0 runs the
+// sequential sum over chunk c (and wave 0 then copies it out), waves 1.. compute the areas of
+// chunk c + 1, so the area gathers hide behind the dependent chain of additions.
 __device__ __forceinline__ void area_cdf_body(const AreaCdfParams &p, const Blk &blk) {
     const float *__restrict__ verts = p.verts;
     const int32_t *__restrict__ faces = p.faces;
     const int V = p.V, F = p.F;
-    __shared__ double area[AC_CHUNK];  // areas, overwritten in place by the running sums
+    __shared__ double area[2][AC_CHUNK];  // areas, overwritten in place by the running sums
     __shared__ int bad;
     __shared__ int lastw[AC_THREADS / 64];
-    __shared__ double carry;
     const int t = blk.x;
     const float *vt = verts + (size_t)t * V * 3;
     double *ct = p.cdf + (size_t)t * F;
-    if (threadIdx.x == 0) {
-        bad = 0;
-        carry = 0.0;
-    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) bad = 0;
     int last = -1;  // last face with a positive area, per thread, then per workgroup
-    for (int base = 0; base < F; base += AC_CHUNK) {
+    // areas of chunk c into buffer c & 1, by the threads [first, AC_THREADS)
+    auto areas = [&](int c, int first) {
+        const int base = c * AC_CHUNK;
         const int n = min(AC_CHUNK, F - base);
-        __syncthreads();
-        for (int k = threadIdx.x; k < n; k += AC_THREADS) {
+        double *dst = area[c & 1];
+        for (int k = (int)threadIdx.x - first; k < n; k += AC_THREADS - first) {
             const int32_t *fv = faces + 3 * (size_t)(base + k);
             double a = 0.0;
             if (face_ok(fv, V)) {
@@ -75,30 +77,41 @@ __device__ __forceinline__ void area_cdf_body(const AreaCdfParams &p, const Blk 
             } else {
                 bad = 1;
             }
-            area[k] = a;
+            dst[k] = a;
             last = (a > 0.0) ? base + k : last;
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {  // the sequential sum, in face order
-            double run = carry;
+    };
+    const int nchunk = (F + AC_CHUNK - 1) / AC_CHUNK;
+    __syncthreads();  // `bad` is cleared before any thread may set it
+    areas(0, 0);
+    __syncthreads();
+    double run = 0.0;  // the running sum, held by thread 0
+    for (int c = 0; c < nchunk; ++c) {
+        const int base = c * AC_CHUNK;
+        const int n = min(AC_CHUNK, F - base);
+        double *cur = area[c & 1];
+        if (wave == 0) {
+            if (lane == 0) {  // the sequential sum, in face order
 #pragma unroll 8
-            for (int k = 0; k < n; ++k) {
-                run = run + area[k];
-                area[k] = run;
+                for (int k = 0; k < n; ++k) {
+                    run = run + cur[k];
+                    cur[k] = run;
+                }
             }
-            carry = run;
+            // lane 0's sums are visible to the rest of its wave once the wave reconverges
+            for (int k = lane; k < n; k += 64) ct[base + k] = cur[k];
+        } else if (c + 1 < nchunk) {
+            areas(c + 1, 64);
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < n; k += AC_THREADS) ct[base + k] = area[k];
     }
     // faces are visited in increasing order per thread, so the maximum is the last positive one
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) last = max(last, __shfl_xor(last, off, 64));
-    if ((threadIdx.x & 63) == 0) lastw[threadIdx.x >> 6] = last;
+    if (lane == 0) lastw[wave] = last;
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 0; w < AC_THREADS / 64; ++w) last = max(last, lastw[w]);
-        const double run = carry;
+        for (int w = 1; w < AC_THREADS / 64; ++w) last = max(last, lastw[w]);
         const bool degenerate = !(run > 0.0) || !__builtin_isfinite(run);
         p.lastpos[t] = (degenerate || bad) ? -1 : last;
         if (bad) atomicOr(p.status, (unsigned)ST_BAD_FACE);
