@@ -8,8 +8,8 @@
 // hH, hM, mH, hL, lH, mM per coordinate (18 K-slots) plus the two norms in three parts each (6
 // K-slots) fill 24 of the 32 K-slots, so the matrix unit produces the whole screened distance.
 // Rows a stay in registers (16-row tiles: six per wave for both directions, four for one); the
-// b operands (packed once per frame) stream through a double-buffered LDS stage.  Every 16x16 result tile feeds both
-// directions with v_min3 only:
+// b operands (packed once per frame) stream through a double-buffered LDS stage.  Every 16x16
+// result tile feeds both directions with v_min3 only:
 //   rows (a -> b): each (lane, row) folds its column of every tile into a running minimum;
 //     targets are laid out so that, inside each chunk of SC_CHUNK, result column c holds a
 //     contiguous run of SC_RUN targets (a "slot group"); the kernel keeps the two best slot
@@ -943,7 +943,6 @@ __global__ __launch_bounds__(RF_THREADS) void k_colrefine(RefineParams p) {
 }
 
 }  // namespace
-
 
 static int padded_targets(int Np) { return ((Np + SC_CHUNK - 1) / SC_CHUNK) * SC_CHUNK; }
 
