@@ -735,6 +735,25 @@ __device__ __forceinline__ void lex_min(float &best, int &bj, float d, int j) {
     }
 }
 
+// rows i0 .. i0 + 3 (those below Na) of the point array P, as three 16-byte loads when whole
+__device__ __forceinline__ void run4(float &best, int &bj, float qx, float qy, float qz,
+                                     const float *P, int i0, int Na) {
+    float c[12];
+    if (i0 + 3 < Na) {
+        const float4 *p4 = reinterpret_cast<const float4 *>(P + 3 * (size_t)i0);
+        const float4 u0 = p4[0], u1 = p4[1], u2 = p4[2];
+        c[0] = u0.x; c[1] = u0.y; c[2] = u0.z; c[3] = u0.w;
+        c[4] = u1.x; c[5] = u1.y; c[6] = u1.z; c[7] = u1.w;
+        c[8] = u2.x; c[9] = u2.y; c[10] = u2.z; c[11] = u2.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) c[k] = (i0 + k / 3 < Na) ? P[3 * (size_t)i0 + k] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (i0 + k < Na) lex_min(best, bj, canon_d2(qx, qy, qz, c + 3 * k), i0 + k);
+}
+
 __device__ __forceinline__ void team_reduce(float &best, int &bj) {
 #pragma unroll
     for (int off = RF_TEAM / 2; off > 0; off >>= 1) {
@@ -828,20 +847,7 @@ __device__ __forceinline__ void refine_body(const RefineParams &pr, const Blk &b
             const int code = rr[2 + e / (SC_RUN / 64)];
             const int j = (code >> 4) * SC_CHUNK + SC_RUN * (code & 15) + 64 * (e % (SC_RUN / 64)) +
                           4 * tl;
-            float c[12];
-            if (j + 3 < Np) {
-                const float4 *p4 = reinterpret_cast<const float4 *>(Pt + 3 * (size_t)j);
-                const float4 u0 = p4[0], u1 = p4[1], u2 = p4[2];
-                c[0] = u0.x; c[1] = u0.y; c[2] = u0.z; c[3] = u0.w;
-                c[4] = u1.x; c[5] = u1.y; c[6] = u1.z; c[7] = u1.w;
-                c[8] = u2.x; c[9] = u2.y; c[10] = u2.z; c[11] = u2.w;
-            } else {
-#pragma unroll
-                for (int k = 0; k < 12; ++k) c[k] = (j + k / 3 < Np) ? Pt[3 * (size_t)j + k] : 0.f;
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (j + k < Np) lex_min(best, bj, canon_d2(qx, qy, qz, c + 3 * k), j + k);
+            run4(best, bj, qx, qy, qz, Pt, j, Np);
         }
         team_reduce(best, bj);
         if (n >= 0 && tl == 0) {
@@ -900,24 +906,15 @@ __device__ __forceinline__ void colrefine_body(const RefineParams &pr, const Blk
             const int code = rr[1 + e];
             const int wg = code >> 8, grp = code & 0x7f;
             const int wv = grp >> 1, h = grp & 1;
-            if (code & 0x80) {  // ambiguous: every row of the workgroup
-                for (int k = 0; k < sc_rows<true>() / RF_TEAM; ++k) {
-                    const int i = wg * sc_rows<true>() + k * RF_TEAM + tl;
-                    if (i < Na) lex_min(best, bi, canon_d2(qx, qy, qz, At + 3 * (size_t)i), i);
-                }
-            } else {  // the row group: rows 16a + 4g + r of its wave, g in {h, h + 2}
-                constexpr int PER_G = sc_atiles<true>() * 4;
-#pragma unroll
-                for (int k = 0; k < (2 * PER_G + RF_TEAM - 1) / RF_TEAM; ++k) {
-                    const int ar = k * RF_TEAM + tl;
-                    if (ar < 2 * PER_G) {
-                        const int gg = h + 2 * (ar / PER_G), rem = ar % PER_G;
-                        const int i = wg * sc_rows<true>() + wv * (sc_atiles<true>() * 16) +
-                                      16 * (rem >> 2) + 4 * gg + (rem & 3);
-                        if (i < Na)
-                            lex_min(best, bi, canon_d2(qx, qy, qz, At + 3 * (size_t)i), i);
-                    }
-                }
+            if (code & 0x80) {  // ambiguous: every row of the workgroup, as runs of 4 rows
+                for (int u = tl; u < sc_rows<true>() / 4; u += RF_TEAM)
+                    run4(best, bi, qx, qy, qz, At, wg * sc_rows<true>() + 4 * u, Na);
+            } else {  // the row group: runs of rows 16a + 4g + (0..3) of its wave, g in {h, h+2}
+                for (int u = tl; u < 2 * sc_atiles<true>(); u += RF_TEAM)
+                    run4(best, bi, qx, qy, qz, At,
+                         wg * sc_rows<true>() + wv * (sc_atiles<true>() * 16) + 16 * (u >> 1) +
+                             4 * (h + 2 * (u & 1)),
+                         Na);
             }
         }
         team_reduce(best, bi);
