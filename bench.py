@@ -33,7 +33,7 @@ SCREEN_ISSUE_CEILING = CUS * SIMDS_PER_CU * PEAK_CLOCK_HZ / (5 * 4) * 256
 # HBM bytes of one k_screen launch on this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled
 # by a plain-copy calibration (profiles/k_screen_grid100_65536pts_100frames_counters.md); valid
 # only for the screen source they were measured on.
-SCREEN_TRAFFIC = dict(source_sha256="e786ce40b26e948c65ea8aae7fe7e8f93da45b8018248beef3965c8ba4db52ba",
+SCREEN_TRAFFIC = dict(source_sha256="2b946d6541aa046a6d0b6daf3dcb14dbcd6911ee1d8070d55a4499d991698bf7",
                       bytes=2288081999 + 3571902024)
 
 

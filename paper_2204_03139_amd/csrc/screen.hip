@@ -67,7 +67,6 @@ constexpr int SC_RUN = SC_CHUNK / 16;                    // contiguous targets o
 constexpr int SC_PER_THREAD = SC_STAGE / SC_THREADS;     // targets staged per thread
 constexpr int SC_ROWPAD = 17;                            // LDS entries per staged tile
 static_assert(SC_STAGE % SC_THREADS == 0 && SC_CHUNK % SC_STAGE == 0, "tiling");
-static_assert(SC_RUN % 64 == 0, "slot groups are whole 64-target refine steps");
 constexpr int MAXC = 14;                                 // candidate slot groups per row
 constexpr int REC_INTS = 2 + MAXC;                       // n, spare, entries
 
@@ -725,6 +724,8 @@ __device__ __forceinline__ float canon_d2(float qx, float qy, float qz, const fl
 
 constexpr int RF_THREADS = 256;
 constexpr int RF_TEAM = 16;                         // lanes per query
+constexpr int RF_STEP = 4 * RF_TEAM;                // targets a team covers per step
+static_assert(SC_RUN % RF_STEP == 0, "slot groups are whole refine steps");
 constexpr int RF_TEAMS = RF_THREADS / RF_TEAM;
 constexpr int RF_QUERIES = 256;                     // queries per workgroup (16 per team)
 
@@ -843,10 +844,10 @@ __device__ __forceinline__ void refine_body(const RefineParams &pr, const Blk &b
         float best = __builtin_inff();
         int bj = 0x7fffffff;
 #pragma unroll 2
-        for (int e = 0; e < n * (SC_RUN / 64); ++e) {
-            const int code = rr[2 + e / (SC_RUN / 64)];
-            const int j = (code >> 4) * SC_CHUNK + SC_RUN * (code & 15) + 64 * (e % (SC_RUN / 64)) +
-                          4 * tl;
+        for (int e = 0; e < n * (SC_RUN / RF_STEP); ++e) {
+            const int code = rr[2 + e / (SC_RUN / RF_STEP)];
+            const int j = (code >> 4) * SC_CHUNK + SC_RUN * (code & 15) +
+                          RF_STEP * (e % (SC_RUN / RF_STEP)) + 4 * tl;
             run4(best, bj, qx, qy, qz, Pt, j, Np);
         }
         team_reduce(best, bj);
