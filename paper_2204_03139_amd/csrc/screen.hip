@@ -469,7 +469,19 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
                     cm1 = fminf(fminf(cm1, d1[0]), d1[1]);
                     cm1 = fminf(fminf(cm1, d1[2]), d1[3]);
                 }
+                // issue order of the two-direction screen: the next tile's two MFMAs (mask 8)
+                // before this tile's eight minima (mask 2), so no minimum waits for the matrix
+                // result it reads (measured 2% faster; the one-direction screen is not helped)
+                if constexpr (COLS) {
+                    if (a == 0) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+                    } else if (a < ATILES - 1) {
+                        __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+                    }
+                }
             }
+            if constexpr (COLS) __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);
             if (COLS) {
                 // rows 2-3 of cm0 trade places with rows 0-1 of cm1, so lane group g ends up
                 // with the minimum over groups g and g + 2 (mod 4) of tile bt + (g >> 1)
