@@ -12,7 +12,7 @@
 namespace dc {
 namespace {
 
-constexpr int AC_THREADS = 256;
+constexpr int AC_THREADS = 1024;
 constexpr int AC_CHUNK = 4000;  // faces per chunk: two chunk buffers of doubles stay under 64 KiB
 
 __device__ __forceinline__ bool face_ok(const int32_t *fv, int V) {
@@ -52,7 +52,8 @@ __device__ __forceinline__ void area_cdf_body(const AreaCdfParams &p, const Blk 
     const float *__restrict__ verts = p.verts;
     const int32_t *__restrict__ faces = p.faces;
     const int V = p.V, F = p.F;
-    __shared__ double area[2][AC_CHUNK];  // areas, overwritten in place by the running sums
+    // areas, then their running sums; 16 entries of padding take the chain's read-ahead
+    __shared__ __align__(16) double area[2][AC_CHUNK + 16];
     __shared__ int bad;
     __shared__ int lastw[AC_THREADS / 64];
     const int t = blk.x;
@@ -92,8 +93,34 @@ __device__ __forceinline__ void area_cdf_body(const AreaCdfParams &p, const Blk 
         double *cur = area[c & 1];
         if (wave == 0) {
             if (lane == 0) {  // the sequential sum, in face order
-#pragma unroll 8
-                for (int k = 0; k < n; ++k) {
+                // groups of 8 areas in two register sets: the next group's loads are in flight
+                // while this group's additions run, so the chain waits on the additions only
+                // (the last read-ahead ends at most 8 entries past the chunk, in the padding)
+                double2 *c2 = reinterpret_cast<double2 *>(cur);
+                const int n16 = n & ~15;
+                double2 ga[4], gb[4];
+                auto load = [&](double2 (&x)[4], int k) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) x[i] = c2[k / 2 + i];
+                };
+                auto sum = [&](double2 (&x)[4], int k) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        run = run + x[i].x;
+                        x[i].x = run;
+                        run = run + x[i].y;
+                        x[i].y = run;
+                        c2[k / 2 + i] = x[i];
+                    }
+                };
+                load(ga, 0);
+                for (int k = 0; k < n16; k += 16) {
+                    load(gb, k + 8);
+                    sum(ga, k);
+                    load(ga, k + 16);
+                    sum(gb, k + 8);
+                }
+                for (int k = n16; k < n; ++k) {
                     run = run + cur[k];
                     cur[k] = run;
                 }
