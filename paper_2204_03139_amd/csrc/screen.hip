@@ -291,6 +291,16 @@ __device__ __forceinline__ float bf16_step_up(float x) {
 constexpr int SC_GROUPS = SC_WAVES * 2;
 constexpr int CP_PAD = SC_TPS + 1;       // column partial buffer: [group][column][tile], padded
 
+// Column partials (16-bit value, 1-byte tag) of every (row workgroup w, target j) of a frame, laid
+// out in blocks of CP_BLOCK targets: [frame][j / CP_BLOCK][w][j % CP_BLOCK].  The merge reads one
+// block's rows as one contiguous stream; a screen workgroup's stores stay runs of 16 targets.
+constexpr int CP_BLOCK = 128;
+static_assert(SC_CHUNK % CP_BLOCK == 0, "padded target counts are whole blocks");
+__device__ __forceinline__ size_t part_index(int t, int nwg, int Np_pad, int w, int j) {
+    const size_t blk = (size_t)t * (Np_pad / CP_BLOCK) + (size_t)(j / CP_BLOCK);
+    return (blk * nwg + w) * CP_BLOCK + (size_t)(j % CP_BLOCK);
+}
+
 struct ScreenParams {
     const float *Q;
     const bf16x8 *packed;
@@ -419,7 +429,7 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
             // every row of the workgroup for this target
             const float th = threshold_affine(best, sl_prev[u]);
             const bool amb = !(second > th + fabsf(th) * 1e-6f);
-            const size_t o = ((size_t)t * nwg + wgx) * Np_pad + j;
+            const size_t o = part_index(t, nwg, Np_pad, wgx, j);
             cpart[o] = lower_bf16_bits(best);
             ctag[o] = (uint8_t)(bg | (amb ? 0x80 : 0));
         }
@@ -639,7 +649,10 @@ __device__ __forceinline__ void colmerge_body(const ColmergeParams &pr, const Bl
         over[u] = false;
         slk[u] = pr.slack[(size_t)t * Np_pad + j0 + u];
     }
-    const uint16_t *frame = cpart + (size_t)t * nwg * Np_pad;
+    // this wave's block of CP_BLOCK targets (CM_TPT per lane): one row of CP_BLOCK partials per
+    // row workgroup, the rows consecutive
+    const int jb = __builtin_amdgcn_readfirstlane(j0 / CP_BLOCK);  // the same for the whole wave
+    const uint16_t *block = cpart + part_index(t, nwg, Np_pad, 0, jb * CP_BLOCK);
     // a partial passing the threshold of the running minimum goes on the list; the rest are
     // skipped with one compare.  A full list drops the entries the current threshold excludes;
     // if none can be dropped the target is made heavy (always correct: it is searched exhaustively).
@@ -670,25 +683,36 @@ __device__ __forceinline__ void colmerge_body(const ColmergeParams &pr, const Bl
         consider(0, v & 0xFFFFu, w);
         consider(1, v >> 16, w);
     };
-    // eight workgroups' partials in flight at a time: the loads are issued before the compares.
-    // Each batch reads through a buffer resource based at its first row, so a load's address is
-    // the uniform row offset (scalar) plus the lane's offset: no per-lane 64-bit address math.
+    // eight workgroups' partials per batch, the next batch's loads in flight while this batch is
+    // compared.  Each batch reads through a buffer resource based at its first row, so a load's
+    // address is the uniform row offset (scalar) plus the lane's offset: no per-lane 64-bit
+    // address math.  The loads are unconditional (the last whole batch re-reads itself, unused),
+    // so the waits fall on the batch being compared only.
     constexpr int CM_BATCH = 8;
-    const unsigned row_bytes = (unsigned)Np_pad * 2u;
-    const unsigned lane_bytes = (unsigned)j0 * 2u;
-    int w = 0;
-    for (; w + CM_BATCH <= nwg; w += CM_BATCH) {
+    static_assert(CP_BLOCK == 64 * CM_TPT, "one wave reads one block");
+    const unsigned row_bytes = (unsigned)CP_BLOCK * 2u;
+    const unsigned lane_bytes = (unsigned)(j0 % CP_BLOCK) * 2u;
+    const int nfull = nwg / CM_BATCH * CM_BATCH;
+    auto load_batch = [&](int w0, unsigned (&v)[CM_BATCH]) {
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(frame + (size_t)w * Np_pad), 0, (int)(row_bytes * CM_BATCH), 0x00020000);
-        unsigned v[CM_BATCH];
+            (void *)(block + (size_t)w0 * CP_BLOCK), 0, (int)(row_bytes * CM_BATCH), 0x00020000);
 #pragma unroll
         for (int k = 0; k < CM_BATCH; ++k)
             v[k] = __builtin_amdgcn_raw_buffer_load_b32(rs, lane_bytes, k * row_bytes, 0);
+    };
+    unsigned nxt[CM_BATCH];
+    if (nfull > 0) load_batch(0, nxt);
+    int w = 0;
+    for (; w < nfull; w += CM_BATCH) {
+        unsigned cur[CM_BATCH];
 #pragma unroll
-        for (int k = 0; k < CM_BATCH; ++k) merge2(v[k], w + k);
+        for (int k = 0; k < CM_BATCH; ++k) cur[k] = nxt[k];
+        load_batch(w + CM_BATCH < nfull ? w + CM_BATCH : w, nxt);
+#pragma unroll
+        for (int k = 0; k < CM_BATCH; ++k) merge2(cur[k], w + k);
     }
     for (; w < nwg; ++w)
-        merge2(*reinterpret_cast<const unsigned *>(frame + (size_t)w * Np_pad + j0), w);
+        merge2(*reinterpret_cast<const unsigned *>(block + (size_t)w * CP_BLOCK + j0 % CP_BLOCK), w);
     const float nqm = nqmax[t];
 #pragma unroll
     for (int u = 0; u < CM_TPT; ++u) {
@@ -710,7 +734,7 @@ __device__ __forceinline__ void colmerge_body(const ColmergeParams &pr, const Bl
                 if (__uint_as_float(e << 16) <= theta) {
                     const int wk = (int)(e >> 16);
                     if (n < CMAXC)
-                        rr[1 + n] = (wk << 8) | ctag[((size_t)t * nwg + wk) * Np_pad + j];
+                        rr[1 + n] = (wk << 8) | ctag[part_index(t, nwg, Np_pad, wk, j)];
                     ++n;
                 }
             }
