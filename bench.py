@@ -33,8 +33,8 @@ SCREEN_ISSUE_CEILING = CUS * SIMDS_PER_CU * PEAK_CLOCK_HZ / (5 * 4) * 256
 # HBM bytes of one k_screen launch on this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled
 # by a plain-copy calibration (profiles/k_screen_grid100_65536pts_100frames_counters.md); valid
 # only for the screen source they were measured on.
-SCREEN_TRAFFIC = dict(source_sha256="e8e9c9a48f768981987f41b31c6328f52c82b80e8af3992b3ce580baf60ded1d",
-                      bytes=2290014712 + 3571890576)
+SCREEN_TRAFFIC = dict(source_sha256="fa5a5aac127f2ca6223efca522f9c33f91c89e745ed764e1fb0abf6ada9f86b4",
+                      bytes=2290113415 + 3571933520)
 
 
 def _screen_traffic():

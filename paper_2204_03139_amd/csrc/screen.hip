@@ -406,6 +406,13 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
         q[u][2] = src[2];
     }
     const int gk = (g == 3) ? 0 : g;
+    // the column partial offsets of this thread's staged targets in stage 0: a stage's targets
+    // lie in its chunk's slot groups, one CP_BLOCK block per slot group
+    static_assert(SC_RUN == CP_BLOCK, "a slot group is one partial block");
+    size_t pbase[SC_PER_THREAD];
+#pragma unroll
+    for (int u = 0; u < SC_PER_THREAD; ++u)
+        pbase[u] = COLS ? part_index(t, nwg, Np_pad, wgx, soff[u]) : 0;
     // reduce the workgroup's row groups per target of stage sm and write its partial
     // reduce the workgroup's row groups per target of stage sm and write its partial (padding
     // targets too: the partial arrays span the padded target range)
@@ -415,7 +422,6 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
         for (int u = 0; u < SC_PER_THREAD; ++u) {
             const int e = threadIdx.x + u * SC_THREADS;
             const int c = e / SC_TPS, btl = e % SC_TPS;
-            const int j = target_of(sm, u);
             float best = inf, second = inf;
             int bg = 0;
 #pragma unroll
@@ -429,7 +435,10 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
             // every row of the workgroup for this target
             const float th = threshold_affine(best, sl_prev[u]);
             const bool amb = !(second > th + fabsf(th) * 1e-6f);
-            const size_t o = part_index(t, nwg, Np_pad, wgx, j);
+            // part_index(t, nwg, Np_pad, wgx, target_of(sm, u)): the thread's chunk-0 offset
+            // plus a uniform step
+            const size_t o = pbase[u] + (size_t)(sm / SPC) * (SC_CHUNK / CP_BLOCK) * nwg * CP_BLOCK +
+                             SC_TPS * (sm % SPC);
             cpart[o] = lower_bf16_bits(best);
             ctag[o] = (uint8_t)(bg | (amb ? 0x80 : 0));
         }
