@@ -12,7 +12,10 @@
 namespace dc {
 namespace {
 
-constexpr int AC_THREADS = 1024;
+#ifndef DC_AREA_CDF_THREADS
+#define DC_AREA_CDF_THREADS 1024
+#endif
+constexpr int AC_THREADS = DC_AREA_CDF_THREADS;  // one lane sums, the other waves compute areas
 constexpr int AC_CHUNK = 4000;  // faces per chunk: two chunk buffers of doubles stay under 64 KiB
 
 __device__ __forceinline__ bool face_ok(const int32_t *fv, int V) {
