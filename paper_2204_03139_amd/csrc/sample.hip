@@ -260,9 +260,17 @@ __device__ __forceinline__ void sample_body(const SampleParams &pr, const Blk &b
     const float *p1 = vt + 3 * (size_t)fv[0];
     const float *p2 = vt + 3 * (size_t)fv[1];
     const float *p3 = vt + 3 * (size_t)fv[2];
+    // the three corners are read whole (one 12-byte load each) before any store
+    float c1[3], c2[3], c3[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        c1[k] = p1[k];
+        c2[k] = p2[k];
+        c3[k] = p3[k];
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-        points[3 * o + k] = __builtin_fmaf(bw, p3[k], __builtin_fmaf(bv, p2[k], bu * p1[k]));
+        points[3 * o + k] = __builtin_fmaf(bw, c3[k], __builtin_fmaf(bv, c2[k], bu * c1[k]));
     bary[3 * o] = bu;
     bary[3 * o + 1] = bv;
     bary[3 * o + 2] = bw;
