@@ -19,7 +19,8 @@ constexpr int AC_THREADS = DC_AREA_CDF_THREADS;  // one lane sums, the other wav
 constexpr int AC_CHUNK = 4000;  // faces per chunk: two chunk buffers of doubles stay under 64 KiB
 
 __device__ __forceinline__ bool face_ok(const int32_t *fv, int V) {
-    return fv[0] >= 0 && fv[0] < V && fv[1] >= 0 && fv[1] < V && fv[2] >= 0 && fv[2] < V;
+    const int32_t i0 = fv[0], i1 = fv[1], i2 = fv[2];  // one 12-byte load
+    return (unsigned)i0 < (unsigned)V && (unsigned)i1 < (unsigned)V && (unsigned)i2 < (unsigned)V;
 }
 
 // |(p2-p1) x (p3-p1)| / 2 with every product and difference rounded in double.
