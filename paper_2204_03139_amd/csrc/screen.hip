@@ -1118,8 +1118,12 @@ void register_screen_kernels(BatchedKernel *table) {
     table[KT_PACK] = batched_kernel<PackParams, pack_body, 256, 1024>();
     // two screen workgroups per compute unit fit the batched kernel's registers (forcing three
     // spills registers and measured slower)
-    table[KT_SCREEN] = batched_kernel<ScreenParams, screen_body<true>, SC_THREADS, 512>();
-    table[KT_SCREEN_ROWS] = batched_kernel<ScreenParams, screen_body<false>, SC_THREADS, 768>();
+    // persistent blocks = the workgroups that fit at once (two or three per compute unit), with
+    // the same register bounds as the direct kernels so that they all stay resident
+    table[KT_SCREEN] = batched_kernel<ScreenParams, screen_body<true>, SC_THREADS, 512,
+                                      sc_atiles<true>() <= 4 ? 3 : 2>();
+    table[KT_SCREEN_ROWS] = batched_kernel<ScreenParams, screen_body<false>, SC_THREADS, 768,
+                                           sc_atiles<false>() <= 4 ? 3 : 2>();
     table[KT_REFINE] = batched_kernel<RefineParams, refine_body, RF_THREADS, 2048>();
     table[KT_COLMERGE] = batched_kernel<ColmergeParams, colmerge_body, CM_THREADS, 1024>();
     table[KT_COLREFINE] = batched_kernel<RefineParams, colrefine_body, RF_THREADS, 2048>();
