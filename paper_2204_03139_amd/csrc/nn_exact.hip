@@ -432,7 +432,8 @@ void launch_loss(const float *dist_a, const float *dist_b, int T, int Na, int Nb
 void register_nn_kernels(BatchedKernel *table) {
     table[KT_NN1] = batched_kernel<NNParams, nn_exact_body<1>, NN_THREADS, 2048>();
     table[KT_NN4] = batched_kernel<NNParams, nn_exact_body<4>, NN_THREADS, 2048>();
-    table[KT_NN8] = batched_kernel<NNParams, nn_exact_body<8>, NN_THREADS, 2048>();
+    // the eight-queries-per-lane body keeps four waves per SIMD: 1,024 blocks are all resident
+    table[KT_NN8] = batched_kernel<NNParams, nn_exact_body<8>, NN_THREADS, 1024>();
     table[KT_NN_MERGE] = batched_kernel<NNMergeParams, nn_merge_body, MERGE_THREADS, 512>();
     table[KT_LOSS] = batched_kernel<LossParams, loss_body, LOSS_THREADS, 256>();
 }

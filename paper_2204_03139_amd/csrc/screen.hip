@@ -1124,9 +1124,10 @@ void register_screen_kernels(BatchedKernel *table) {
                                       sc_atiles<true>() <= 4 ? 3 : 2>();
     table[KT_SCREEN_ROWS] = batched_kernel<ScreenParams, screen_body<false>, SC_THREADS, 768,
                                            sc_atiles<false>() <= 4 ? 3 : 2>();
-    table[KT_REFINE] = batched_kernel<RefineParams, refine_body, RF_THREADS, 2048>();
+    // eight waves per SIMD (at most 64 registers), like the direct refine kernels: 2,048 blocks
+    table[KT_REFINE] = batched_kernel<RefineParams, refine_body, RF_THREADS, 2048, 8>();
     table[KT_COLMERGE] = batched_kernel<ColmergeParams, colmerge_body, CM_THREADS, 1024>();
-    table[KT_COLREFINE] = batched_kernel<RefineParams, colrefine_body, RF_THREADS, 2048>();
+    table[KT_COLREFINE] = batched_kernel<RefineParams, colrefine_body, RF_THREADS, 2048, 8>();
 }
 
 }  // namespace dc
