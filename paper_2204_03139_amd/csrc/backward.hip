@@ -89,7 +89,7 @@ __device__ __forceinline__ void chamfer_bwd_body(const ChamferBwdParams &pr, con
 }
 
 __global__ __launch_bounds__(BW_THREADS) void k_chamfer_bwd(ChamferBwdParams p) {
-    chamfer_bwd_body(p, grid_blk());
+    chamfer_bwd_body(p, grid_blk_xcd());
 }
 
 // face_start[t][f] = first sorted position whose face is >= f, for f in [0, F]
@@ -153,7 +153,7 @@ __device__ __forceinline__ void face_grad_body(const FaceGradParams &pr, const B
 }
 
 __global__ __launch_bounds__(BW_THREADS) void k_face_grad(FaceGradParams p) {
-    face_grad_body(p, grid_blk());
+    face_grad_body(p, grid_blk_xcd());
 }
 
 // grad_verts[t,v] = sum over the incident (face f, corner c), in increasing (f, c), of fg[t,f,c]

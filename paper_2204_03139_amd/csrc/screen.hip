@@ -913,7 +913,9 @@ __device__ __forceinline__ void refine_body(const RefineParams &pr, const Blk &b
                 my_heavy, tl);
 }
 
-__global__ __launch_bounds__(RF_THREADS) void k_refine(RefineParams p) { refine_body(p, grid_blk()); }
+__global__ __launch_bounds__(RF_THREADS) void k_refine(RefineParams p) {
+    refine_body(p, grid_blk_xcd());
+}
 
 // Column refine (b -> a): each candidate workgroup contributes its winning row group (32 rows:
 // two per lane) or, when flagged ambiguous, all of its rows.
@@ -982,7 +984,7 @@ __device__ __forceinline__ void colrefine_body(const RefineParams &pr, const Blk
 }
 
 __global__ __launch_bounds__(RF_THREADS) void k_colrefine(RefineParams p) {
-    colrefine_body(p, grid_blk());
+    colrefine_body(p, grid_blk_xcd());
 }
 
 }  // namespace
