@@ -189,7 +189,7 @@ __device__ __forceinline__ void vertex_grad_body(const VertexGradParams &pr, con
 }
 
 __global__ __launch_bounds__(BW_THREADS) void k_vertex_grad(VertexGradParams p) {
-    vertex_grad_body(p, grid_blk());
+    vertex_grad_body(p, grid_blk_xcd());
 }
 
 }  // namespace

@@ -174,7 +174,7 @@ __device__ __forceinline__ void ss_scatter_body(const SortPassParams &pr, const 
 }
 
 __global__ __launch_bounds__(SB_THREADS) void k_ss_scatter(SortPassParams p) {
-    ss_scatter_body(p, grid_blk());
+    ss_scatter_body(p, grid_blk_xcd());
 }
 
 static_assert(SB_THREADS == BINS, "one thread per digit bin");
