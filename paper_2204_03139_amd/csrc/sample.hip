@@ -278,7 +278,7 @@ __device__ __forceinline__ void sample_body(const SampleParams &pr, const Blk &b
     face_idx[o] = f;
 }
 
-__global__ __launch_bounds__(SP_THREADS) void k_sample(SampleParams p) { sample_body(p, grid_blk()); }
+__global__ __launch_bounds__(SP_THREADS) void k_sample(SampleParams p) { sample_body(p, grid_blk_xcd()); }
 
 }  // namespace
 

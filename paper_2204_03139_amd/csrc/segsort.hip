@@ -90,7 +90,7 @@ __device__ __forceinline__ void ss_hist_body(const SortPassParams &pr, const Blk
 }
 
 __global__ __launch_bounds__(SB_THREADS) void k_ss_hist(SortPassParams p) {
-    ss_hist_body(p, grid_blk());
+    ss_hist_body(p, grid_blk_xcd());
 }
 
 // exclusive prefix over (digit, block) of one frame, in place: each thread sums a contiguous run,
