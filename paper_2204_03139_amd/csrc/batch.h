@@ -39,21 +39,21 @@ __device__ __forceinline__ Blk grid_blk() {
 // workgroups out to the 8 XCDs in turn (flat id modulo 8), so XCD k is given the k-th contiguous
 // eighth of the frame-major order.  Each XCD's L2 then holds the data of the one or two frames its
 // workgroups are on, instead of every XCD touching every frame in flight.  A bijection on the
-// workgroups of a 2-D grid (z must be 1); only the mapping, never the work, changes.
+// workgroups of the grid (x fastest, then y, then z); only the mapping, never the work, changes.
 constexpr unsigned NUM_XCD = 8;
 __device__ __forceinline__ Blk grid_blk_xcd() {
-    const unsigned gx = gridDim.x, total = gridDim.x * gridDim.y;
-    const unsigned b = blockIdx.x + gx * blockIdx.y;
+    const unsigned gx = gridDim.x, gxy = gridDim.x * gridDim.y, total = gxy * gridDim.z;
+    const unsigned b = blockIdx.x + gx * blockIdx.y + gxy * blockIdx.z;
     const unsigned per = total / NUM_XCD, rem = total % NUM_XCD;
     const unsigned xcd = b % NUM_XCD, k = b / NUM_XCD;
     const unsigned l = xcd * per + (xcd < rem ? xcd : rem) + k;
     Blk r;
     r.x = (int)(l % gx);
-    r.y = (int)(l / gx);
-    r.z = 0;
+    r.y = (int)((l % gxy) / gx);
+    r.z = (int)(l / gxy);
     r.gx = (int)gx;
     r.gy = (int)gridDim.y;
-    r.gz = 1;
+    r.gz = (int)gridDim.z;
     return r;
 }
 

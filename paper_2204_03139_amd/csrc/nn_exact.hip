@@ -213,7 +213,7 @@ __device__ __forceinline__ void nn_exact_body(const NNParams &pr, const Blk &blk
 
 template <int QPT>
 __global__ __launch_bounds__(NN_THREADS) void k_nn_exact(NNParams p) {
-    nn_exact_body<QPT>(p, grid_blk());
+    nn_exact_body<QPT>(p, grid_blk_xcd());
 }
 
 // combine per-slice winners; slices hold increasing index ranges, so strict-less keeps the
