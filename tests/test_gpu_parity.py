@@ -531,6 +531,32 @@ def test_full_size_sampled(precision):
     assert np.all(np.abs(sv - sa) <= 1e-4 * scale)
 
 
+def test_full_size_unidirectional_sampled():
+    """Eq. 2 on the 100-frame, 65,536 x 65,536 workload in the benchmark's launch configuration
+    (the bf16 row-only screen, no b outputs): indices and distances of sampled rows equal the
+    oracle's exhaustive search bit for bit on three frames, and every frame's loss equals the sum
+    of its row distances."""
+    p = gpu()
+    say("[full-size] unidirectional bf16")
+    w = gen.workload(4)
+    verts, faces, obs = w["verts"], w["faces"], w["observed"]
+    T, Na = w["T"], w["Na"]
+    pts, _, _ = p.sample_surface(dev(verts), dev(faces), Na, seed=w["seed"])
+    f = p.chamfer_fwd(pts, dev(obs), precision=1, reduction=1, b_side=False)
+    torch.cuda.synchronize()
+    assert f["idx_b"] is None
+    hp, ia, da = host(pts), host(f["idx_a"]), host(f["dist_a"])
+    r = np.random.default_rng(45)
+    for t in sorted(r.choice(T, 3, replace=False)):
+        qa = r.choice(Na, 48, replace=False)
+        oi, od, _ = oracle.nearest(hp[t][qa], obs[t])
+        assert np.array_equal(ia[t][qa], oi)
+        assert np.array_equal(da[t][qa].view(np.uint32), od.view(np.uint32))
+    # Eq. 2: the frame loss is the plain sum of the frame's squared distances
+    loss = host(f["loss"])
+    assert_rel(loss, da.astype(np.float64).sum(1), 1e-5, "loss")
+
+
 def _words_frame(seed, t, N):
     """Philox words of one frame t (the generator is keyed by frame, so a frame can be drawn
     alone)."""
