@@ -60,10 +60,31 @@ __device__ __noinline__ void short_list_search(const NNParams &pr, int t, int z,
                     qz = Qt[3 * (size_t)qi + 2];
         float best = inf;
         int bj = 0x7fffffff;
-        for (int j = j_begin + lane; j < j_end; j += 64) {
+        // four targets per lane per step, each read whole (one 12-byte load), the four loads in
+        // flight together; a lane still visits its targets in increasing order
+        int j = j_begin + lane;
+        for (; j + 3 * 64 < j_end; j += 4 * 64) {
+            float c[4][3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float *p = Pt + 3 * (size_t)(j + 64 * u);
+                c[u][0] = p[0];
+                c[u][1] = p[1];
+                c[u][2] = p[2];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float d = canon_d2(qx, qy, qz, c[u][0], c[u][1], c[u][2]);
+                if (d < best) {  // a lane's indices increase: strict-less keeps its first minimum
+                    best = d;
+                    bj = j + 64 * u;
+                }
+            }
+        }
+        for (; j < j_end; j += 64) {
             const float *p = Pt + 3 * (size_t)j;
             const float d = canon_d2(qx, qy, qz, p[0], p[1], p[2]);
-            if (d < best) {  // a lane's indices increase: strict-less keeps its first minimum
+            if (d < best) {
                 best = d;
                 bj = j;
             }
