@@ -60,20 +60,20 @@ __device__ __noinline__ void short_list_search(const NNParams &pr, int t, int z,
                     qz = Qt[3 * (size_t)qi + 2];
         float best = inf;
         int bj = 0x7fffffff;
-        // four targets per lane per step, each read whole (one 12-byte load), the four loads in
+        // eight targets per lane per step, each read whole (one 12-byte load), the eight loads in
         // flight together; a lane still visits its targets in increasing order
         int j = j_begin + lane;
-        for (; j + 3 * 64 < j_end; j += 4 * 64) {
-            float c[4][3];
+        for (; j + 7 * 64 < j_end; j += 8 * 64) {
+            float c[8][3];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 8; ++u) {
                 const float *p = Pt + 3 * (size_t)(j + 64 * u);
                 c[u][0] = p[0];
                 c[u][1] = p[1];
                 c[u][2] = p[2];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 8; ++u) {
                 const float d = canon_d2(qx, qy, qz, c[u][0], c[u][1], c[u][2]);
                 if (d < best) {  // a lane's indices increase: strict-less keeps its first minimum
                     best = d;
