@@ -259,7 +259,8 @@ __device__ __forceinline__ void pack_body(const PackParams &pr, const Blk &blk) 
     if (j >= Np_pad) return;
     const bool valid = j < Np;
     const float *p = P + ((size_t)t * Np + (valid ? j : 0)) * 3;
-    const float x = valid ? p[0] : 0.f, y = valid ? p[1] : 0.f, z = valid ? p[2] : 0.f;
+    const float px = p[0], py = p[1], pz = p[2];  // one 12-byte load (row 0 for padding)
+    const float x = valid ? px : 0.f, y = valid ? py : 0.f, z = valid ? pz : 0.f;
     __bf16 v[32];
     target_vector(x, y, z, valid, v);
     bf16x8 *o = pr.packed + ((size_t)t * Np_pad + j) * 3;
