@@ -33,7 +33,7 @@ SCREEN_ISSUE_CEILING = CUS * SIMDS_PER_CU * PEAK_CLOCK_HZ / (5 * 4) * 256
 # HBM bytes of one k_screen launch on this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled
 # by a plain-copy calibration (profiles/k_screen_grid100_65536pts_100frames_counters.md); valid
 # only for the screen source they were measured on.
-SCREEN_TRAFFIC = dict(source_sha256="a0f8ef927556c3cff2f8fe6bf9c3b868de1e9d0486e96aaf1653a878c442f1ce",
+SCREEN_TRAFFIC = dict(source_sha256="e4a750a077ab8e88af008c2926d0a9b0c57734e31dbecfde6d19a8bfc011e2e1",
                       bytes=2290113415 + 3571933520)
 
 

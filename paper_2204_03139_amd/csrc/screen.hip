@@ -183,8 +183,23 @@ __device__ __forceinline__ void norm_max_body(const NormMaxParams &pr, const Blk
     const int t = blk.x;
     if (threadIdx.x == 0) heavy_cnt[t] = 0;
     const float *pt = P + (size_t)t * Np * 3;
+    // four points per step, each read whole (one 12-byte load), their loads in flight together;
+    // the maximum does not depend on the order (fmaxf drops NaN whatever the order)
     float m = 0.f;
-    for (int j = threadIdx.x; j < Np; j += NM_THREADS)
+    int j = threadIdx.x;
+    for (; j + 3 * NM_THREADS < Np; j += 4 * NM_THREADS) {
+        float c[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float *q = pt + 3 * (size_t)(j + u * NM_THREADS);
+            c[u][0] = q[0];
+            c[u][1] = q[1];
+            c[u][2] = q[2];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) m = fmaxf(m, norm2(c[u][0], c[u][1], c[u][2]));
+    }
+    for (; j < Np; j += NM_THREADS)
         m = fmaxf(m, norm2(pt[3 * (size_t)j], pt[3 * (size_t)j + 1], pt[3 * (size_t)j + 2]));
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
