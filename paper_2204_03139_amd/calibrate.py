@@ -60,7 +60,7 @@ class StandInCloth(torch.nn.Module):
         self.kx, self.ky = r.uniform(-2, 2, 3), r.uniform(-2, 2, 3)
         self.phase, self.omega = r.uniform(0, 2 * math.pi, 3), r.uniform(0.2, 0.6, 3)
 
-    def forward(self, w: torch.Tensor) -> torch.Tensor:
+    def forward(self, w: torch.Tensor, dtype=torch.float32) -> torch.Tensor:
         ws, wm = w[0].double(), w[1].double()
         bump = (1 - 4 * self.x ** 2) * (1 - 4 * self.y ** 2)
         sag = 0.25 * wm / (wm + 2.0)
@@ -73,7 +73,7 @@ class StandInCloth(torch.nn.Module):
                 z = z + amp * torch.sin(2 * math.pi * (self.kx[k] * self.x + self.ky[k] * self.y)
                                         + self.phase[k] + self.omega[k] * freq * t)
             frames.append(torch.stack([self.x, self.y, z], -1))
-        return torch.stack(frames).to(torch.float32).contiguous()
+        return torch.stack(frames).to(dtype).contiguous()
 
 
 def calibrate(model: StandInCloth, observed: torch.Tensor, n_sim: int, iters: int = 150,

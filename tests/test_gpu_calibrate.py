@@ -6,6 +6,8 @@ import json
 import numpy as np
 import pytest
 
+import oracle
+
 from gpu_helpers import gpu, say, torch
 
 pytestmark = pytest.mark.gpu
@@ -30,10 +32,31 @@ def test_calibration_recovers_multipliers(precision):
     assert out["loss"] <= 1.05 * l_true and out["loss"] < 0.5 * first
     assert abs(out["w"][0] - w_true[0]) <= 0.1 * w_true[0]
     assert abs(out["w"][1] - w_true[1]) <= 0.1 * w_true[1]
-    # the stand-in's gradient path: autograd through the model matches a central difference
+    # the gradient path: autograd through the library and the stand-in against a central
+    # difference in s of the same loss in double, with the face choice, the barycentric weights
+    # and the nearest neighbours of s held fixed (Eq. 4 gives no gradient through them)
     s = torch.tensor([0.3, -0.2], dtype=torch.float64, device="cuda", requires_grad=True)
-    loss = p.diffcloud_loss(model(cal.multipliers(s)), model.faces, obs, 2048, seed=5,
+    seed, n_sim = 5, 2048
+    loss = p.diffcloud_loss(model(cal.multipliers(s)), model.faces, obs, n_sim, seed=seed,
                             precision=precision, reduction=1)
     loss.backward()
     g = s.grad.cpu().numpy()
-    assert np.all(np.isfinite(g)) and np.any(g != 0)
+    faces = model.faces.cpu().numpy()
+    obs_h = obs.cpu().numpy()
+    with torch.no_grad():
+        v32 = model(cal.multipliers(s.detach())).cpu().numpy()
+    pts, fi, ba = oracle.sample_surface(v32, faces, n_sim, seed=seed)
+    idx_a = oracle.chamfer(pts, obs_h, 1)["idx_a"]
+
+    def frozen_loss(sv):
+        with torch.no_grad():
+            v64 = model(cal.multipliers(torch.tensor(sv, dtype=torch.float64, device="cuda")),
+                        dtype=torch.float64).cpu().numpy()
+        return oracle.loss_f64(oracle.points_f64(v64, faces, fi, ba), obs_h, 1, idx_a=idx_a)
+
+    h = 1e-4
+    s0 = s.detach().cpu().numpy()
+    fd = np.array([(frozen_loss(s0 + h * e) - frozen_loss(s0 - h * e)) / (2 * h)
+                   for e in np.eye(2)])
+    say(f"[calibrate] dL/ds autograd {g} central difference {fd}")
+    assert np.linalg.norm(g - fd) <= 1e-3 * np.linalg.norm(fd)

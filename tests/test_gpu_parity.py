@@ -167,6 +167,8 @@ def _check_chamfer(g, o):
     assert np.array_equal(g["dist_b"].view(np.uint32), o["d32b"].view(np.uint32))
     nz = o["d64a"] > 0
     assert_rel(g["dist_a"][nz], o["d64a"][nz], 1e-5, "dist_a vs double")
+    nz = o["d64b"] > 0
+    assert_rel(g["dist_b"][nz], o["d64b"][nz], 1e-5, "dist_b vs double")
     assert_rel(g["loss"], o["loss"], 1e-5, "loss")
 
 
@@ -490,25 +492,104 @@ def test_calls_on_two_streams():
     ctx.close()
 
 
+def _frame_oracle(verts, faces, obs, seed, t, Na, V, reduction):
+    """The oracle's whole pipeline on frame t alone: Philox words of (seed, t), sampling, the
+    exhaustive nearest neighbours both ways, the loss, and the double gradients to the points,
+    to the observed cloud and (through Eq. 4) to the vertices."""
+    op, ofi, oba = oracle.sample_surface(verts[t:t + 1], faces, Na,
+                                         words=_words_frame(seed, t, Na))
+    och = oracle.chamfer(op, obs[t:t + 1], reduction)
+    og = oracle.chamfer_grad(op, obs[t:t + 1], och["idx_a"], och["idx_b"], reduction,
+                             want_b=True)
+    ogv, ogva = oracle.sample_grad(og["ga"], faces, ofi, oba, V, og["ga_abs"])
+    return dict(points=op[0], face_idx=ofi[0], bary=oba[0], ch=och, g=og, gv=ogv[0],
+                gva=ogva[0])
+
+
+def _check_whole_frame(o, t, g, both=True):
+    """Element-wise comparison of frame t of the GPU outputs `g` (host arrays of the whole
+    trajectory) with the oracle's frame `o`."""
+    och = o["ch"]
+    assert np.array_equal(g["face_idx"][t], o["face_idx"])
+    assert np.array_equal(g["points"][t].view(np.uint32), o["points"].view(np.uint32))
+    assert np.array_equal(g["bary"][t].view(np.uint32), o["bary"].view(np.uint32))
+    assert np.array_equal(g["idx_a"][t], och["idx_a"][0])
+    assert np.array_equal(g["dist_a"][t].view(np.uint32), och["d32a"][0].view(np.uint32))
+    nz = och["d64a"][0] > 0
+    assert_rel(g["dist_a"][t][nz], och["d64a"][0][nz], 1e-5, "dist_a vs double")
+    if both:
+        assert np.array_equal(g["idx_b"][t], och["idx_b"][0])
+        assert np.array_equal(g["dist_b"][t].view(np.uint32), och["d32b"][0].view(np.uint32))
+        nz = och["d64b"][0] > 0
+        assert_rel(g["dist_b"][t][nz], och["d64b"][0][nz], 1e-5, "dist_b vs double")
+        assert_grad(g["grad_b"][t], o["g"]["gb"][0], o["g"]["gb_abs"][0], what="grad_b")
+    assert_rel(g["loss"][t:t + 1], och["loss"], 1e-5, "loss")
+    assert_grad(g["grad_a"][t], o["g"]["ga"][0], o["g"]["ga_abs"][0], what="grad_a")
+    assert_grad(g["grad_verts"][t], o["gv"], o["gva"], what="grad_verts")
+
+
+def _gpu_pipeline(p, w, precision, reduction, both=True):
+    """The whole path on the GPU for every frame of workload `w` (sampler keyed by its seed, as
+    the benchmark runs it); host copies of every output."""
+    verts, faces, obs = dev(w["verts"]), dev(w["faces"]), dev(w["observed"])
+    T = w["T"]
+    pts, fi, ba = p.sample_surface(verts, faces, w["Na"], seed=w["seed"])
+    f = p.chamfer_fwd(pts, obs, precision=precision, reduction=reduction, b_side=both)
+    ga, gb = p.chamfer_bwd(torch.ones(T, dtype=torch.float64, device="cuda"), pts, obs,
+                           f["idx_a"], f["idx_b"], reduction=reduction, want_b=both)
+    gv = p.sample_surface_bwd(ga, faces, fi, ba, w["V"])
+    torch.cuda.synchronize()
+    out = dict(points=pts, face_idx=fi, bary=ba, grad_a=ga, grad_b=gb, grad_verts=gv, **f)
+    return {k: (None if v is None else host(v)) for k, v in out.items()}
+
+
+@pytest.mark.parametrize("reduction", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_trajectory_workload_full(precision, reduction):
+    """The 40-frame, 50x50-grid, 8,192 x 8,192 trajectory workload at its stated size, every
+    frame element by element: faces, points and weights bit for bit, neighbour indices exact in
+    both directions, float distances bit for bit (and within 1e-5 of the double twin), losses
+    within 1e-5, gradients to the points, the observed cloud and the vertices within 1e-5 of the
+    sum of absolute contributions (Sec. III-A Eq. 1-2, Sec. III-B Eq. 3-4)."""
+    p = gpu()
+    say(f"[trajectory] 40 frames 8192x8192 precision={precision} reduction={reduction}")
+    w = gen.workload(2)
+    assert w["T"] == 40 and w["Na"] == 8192 and w["Nb"] == 8192
+    g = _gpu_pipeline(p, w, precision, reduction)
+    verts, faces, obs, T, Na = w["verts"], w["faces"], w["observed"], w["T"], w["Na"]
+    op, ofi, oba = oracle.sample_surface(verts, faces, Na, seed=w["seed"])
+    assert np.array_equal(g["face_idx"], ofi)
+    assert np.array_equal(g["points"].view(np.uint32), op.view(np.uint32))
+    assert np.array_equal(g["bary"].view(np.uint32), oba.view(np.uint32))
+    och = oracle.chamfer(op, obs, reduction)
+    _check_chamfer(g, och)
+    og = oracle.chamfer_grad(op, obs, och["idx_a"], och["idx_b"], reduction, want_b=True)
+    assert_grad(g["grad_a"], og["ga"], og["ga_abs"], what="grad_a")
+    assert_grad(g["grad_b"], og["gb"], og["gb_abs"], what="grad_b")
+    ogv, ogva = oracle.sample_grad(og["ga"], faces, ofi, oba, w["V"], og["ga_abs"])
+    assert_grad(g["grad_verts"], ogv, ogva, what="grad_verts")
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_full_size_sampled(precision):
-    """The 100-frame, 65,536 x 65,536 workload in the benchmark's launch configuration: sampled
-    points checked bit-exactly on a few whole frames, nearest neighbours checked exactly on
-    sampled queries (the oracle searches the full frame for each), and properties of the whole
-    gradient that hold at any size."""
+    """The 100-frame, 65,536 x 65,536 workload in the benchmark's launch configuration: one whole
+    frame (drawn at random) element by element against the oracle (faces, points, indices and
+    distances in both directions, loss, gradients to points, observed cloud and vertices); on
+    three more frames sampled points bit for bit and the neighbours of sampled queries (the oracle
+    searches the full frame for each); and properties of the whole gradient that hold at any
+    size."""
     p = gpu()
     say(f"[full-size] precision={precision}")
     w = gen.workload(4)
     verts, faces, obs = w["verts"], w["faces"], w["observed"]
     T, Na, Nb = w["T"], w["Na"], w["Nb"]
-    pts, fi, ba = p.sample_surface(dev(verts), dev(faces), Na, seed=w["seed"])
-    f = p.chamfer_fwd(pts, dev(obs), precision=precision)
-    ga, gb = p.chamfer_bwd(torch.ones(T, dtype=torch.float64, device="cuda"), pts, dev(obs),
-                           f["idx_a"], f["idx_b"], want_b=True)
-    gv = p.sample_surface_bwd(ga, dev(faces), fi, ba, w["V"])
-    torch.cuda.synchronize()
-    hp, hfi, ia, ib = host(pts), host(fi), host(f["idx_a"]), host(f["idx_b"])
-    r = np.random.default_rng(44)
+    g = _gpu_pipeline(p, w, precision, 0)
+    r = np.random.default_rng(44 + precision)
+    t_whole = int(r.integers(T))
+    say(f"[full-size] whole frame {t_whole}")
+    _check_whole_frame(_frame_oracle(verts, faces, obs, w["seed"], t_whole, Na, w["V"], 0),
+                       t_whole, g)
+    hp, hfi, ia, ib = g["points"], g["face_idx"], g["idx_a"], g["idx_b"]
     frames = sorted(r.choice(T, 3, replace=False))
     for t in frames:
         op, ofi, _ = oracle.sample_surface(verts[t:t + 1], faces, Na,
@@ -523,38 +604,76 @@ def test_full_size_sampled(precision):
         assert np.array_equal(ib[t][qb], oi)
     # whole-gradient properties: translation invariance makes every frame's a- and b-gradients
     # sum to zero; Eq. 4 weights sum to one, so vertex gradients sum to the point gradients
-    sa = host(ga).astype(np.float64).sum(1)
-    sb = host(gb).astype(np.float64).sum(1)
-    scale = np.abs(host(ga)).astype(np.float64).sum(1) + 1e-30
+    ga, gb, gv = g["grad_a"], g["grad_b"], g["grad_verts"]
+    sa = ga.astype(np.float64).sum(1)
+    sb = gb.astype(np.float64).sum(1)
+    scale = np.abs(ga).astype(np.float64).sum(1) + 1e-30
     assert np.all(np.abs(sa + sb) <= 1e-4 * scale)
-    sv = host(gv).astype(np.float64).sum(1)
+    sv = gv.astype(np.float64).sum(1)
     assert np.all(np.abs(sv - sa) <= 1e-4 * scale)
 
 
 def test_full_size_unidirectional_sampled():
     """Eq. 2 on the 100-frame, 65,536 x 65,536 workload in the benchmark's launch configuration
-    (the bf16 row-only screen, no b outputs): indices and distances of sampled rows equal the
-    oracle's exhaustive search bit for bit on three frames, and every frame's loss equals the sum
-    of its row distances."""
+    (the bf16 row-only screen, no b outputs): one whole frame element by element against the
+    oracle (indices and distances bit for bit, loss, gradients to the points and vertices);
+    sampled rows of three more frames bit for bit; every frame's loss equals the sum of its row
+    distances."""
     p = gpu()
     say("[full-size] unidirectional bf16")
     w = gen.workload(4)
     verts, faces, obs = w["verts"], w["faces"], w["observed"]
     T, Na = w["T"], w["Na"]
-    pts, _, _ = p.sample_surface(dev(verts), dev(faces), Na, seed=w["seed"])
-    f = p.chamfer_fwd(pts, dev(obs), precision=1, reduction=1, b_side=False)
-    torch.cuda.synchronize()
-    assert f["idx_b"] is None
-    hp, ia, da = host(pts), host(f["idx_a"]), host(f["dist_a"])
+    g = _gpu_pipeline(p, w, 1, 1, both=False)
+    assert g["idx_b"] is None
     r = np.random.default_rng(45)
+    t_whole = int(r.integers(T))
+    say(f"[full-size] whole frame {t_whole}")
+    _check_whole_frame(_frame_oracle(verts, faces, obs, w["seed"], t_whole, Na, w["V"], 1),
+                       t_whole, g, both=False)
+    hp, ia, da = g["points"], g["idx_a"], g["dist_a"]
     for t in sorted(r.choice(T, 3, replace=False)):
         qa = r.choice(Na, 48, replace=False)
         oi, od, _ = oracle.nearest(hp[t][qa], obs[t])
         assert np.array_equal(ia[t][qa], oi)
         assert np.array_equal(da[t][qa].view(np.uint32), od.view(np.uint32))
     # Eq. 2: the frame loss is the plain sum of the frame's squared distances
-    loss = host(f["loss"])
-    assert_rel(loss, da.astype(np.float64).sum(1), 1e-5, "loss")
+    assert_rel(g["loss"], da.astype(np.float64).sum(1), 1e-5, "loss")
+
+
+def test_face_choice_at_the_top_of_the_range():
+    """Face choice with the largest face word (all 53 bits set, r = 1 - 2^-53) on a mesh whose
+    last faces are outside the subset: r S stays below S, so the first face whose running sum
+    exceeds it is the last face of nonzero area, never one of the trailing excluded faces; the
+    same with the smallest word (r = 0: the first face of nonzero area).  Points, weights and
+    faces bit for bit against the oracle."""
+    p = gpu()
+    say("[sample] top and bottom of the face-word range, trailing excluded faces")
+    verts, faces = gen.trajectory(12, 3, 4)
+    F = len(faces)
+    N = 64
+    words = np.zeros((3, N, 4), np.uint32)
+    words[:, : N // 2, 0] = 0xFFFFFFFF
+    words[:, : N // 2, 1] = 0xFFFFFFFF
+    words[:, :, 2] = np.arange(N, dtype=np.uint32) << 20
+    words[:, :, 3] = np.arange(N, dtype=np.uint32)[::-1] << 21
+    mask = np.ones((3, F), np.uint8)
+    mask[0, F - 5:] = 0     # five trailing excluded faces
+    mask[1, F - 1:] = 0     # one
+    mask[2, :7] = 0         # leading excluded faces: r = 0 must skip them
+    m = torch.from_numpy(mask).to("cuda")
+    g = p.sample_surface(dev(verts), dev(faces), N, uniforms=dev(words.view(np.int32)),
+                         face_mask=m)
+    gp, gf, gb = (host(x) for x in g)
+    o = oracle.sample_surface(verts, faces, N, words=words, face_mask=mask)
+    assert np.array_equal(gf, o[1])
+    assert np.array_equal(gp.view(np.uint32), o[0].view(np.uint32))
+    assert np.array_equal(gb.view(np.uint32), o[2].view(np.uint32))
+    last = [int(np.nonzero(mask[t])[0].max()) for t in range(3)]
+    first = [int(np.nonzero(mask[t])[0].min()) for t in range(3)]
+    for t in range(3):
+        assert np.all(gf[t, : N // 2] == last[t])
+        assert np.all(gf[t, N // 2:] == first[t])
 
 
 def _words_frame(seed, t, N):

@@ -1,12 +1,14 @@
-"""The serving loop (dc_submit / dc_poll): results equal the direct calls bit for bit, a request's
-result is the same alone and in a mix, admission respects the HBM budget, and failures stay with
-the request that caused them."""
+"""The serving loop (dc_submit / dc_poll): served results match the oracle (Eq. 1-2 losses and
+Eq. 4 vertex gradients) on requests of the serving mix's extreme sizes, equal the direct calls bit
+for bit, are the same alone and in a mix; admission respects the HBM budget, and failures stay
+with the request that caused them."""
 import numpy as np
 import pytest
 
+import oracle
 from workloads import gen
 
-from gpu_helpers import dev, gpu, host, say, torch
+from gpu_helpers import assert_grad, assert_rel, dev, gpu, host, say, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -155,4 +157,61 @@ def test_failures_stay_with_their_request():
     assert srv.wait(t_bad)[0] == -5
     st, loss, grad, _ = srv.wait(t_ok)
     assert st == 0 and np.all(np.isfinite(loss))
+    srv.close()
+
+
+def _mix_extremes():
+    """Requests of the 256-request serving mix at its extremes: the most point pairs, an 80x80
+    grid, the most observed points, the most sampled points and 60 frames; plus one request at
+    every upper limit of the mix together (80x80 grid, 32,768 x 32,768 points, 60 frames)."""
+    reqs, _ = gen.serving_requests()
+    pairs = [r["T"] * r["Na"] * r["Nb"] for r in reqs]
+    picks = [int(np.argmax(pairs)),
+             next(k for k, r in enumerate(reqs) if r["n"] == 80),
+             int(np.argmax([r["Nb"] for r in reqs])),
+             int(np.argmax([r["Na"] for r in reqs])),
+             next(k for k, r in enumerate(reqs) if r["T"] == 60)]
+    out = [reqs[k] for k in dict.fromkeys(picks)]
+    out.append(dict(n=80, Na=32768, Nb=32768, T=60, seed=77_777, extra=999))
+    return out
+
+
+def _oracle_frame(verts, faces, obs, seed, t, Na, reduction):
+    """Frame t of a served request through the oracle: its sampler words come from (seed, t)."""
+    words = oracle.words_from_seed(seed, t + 1, Na)[t:t + 1]
+    op, ofi, oba = oracle.sample_surface(verts[t:t + 1], faces, Na, words=words)
+    och = oracle.chamfer(op, obs[t:t + 1], reduction)
+    og = oracle.chamfer_grad(op, obs[t:t + 1], och["idx_a"], och["idx_b"], reduction)
+    gv, gva = oracle.sample_grad(og["ga"], faces, ofi, oba, verts.shape[1], og["ga_abs"])
+    return och["loss"][0], gv[0], gva[0]
+
+
+def test_served_results_match_the_oracle():
+    """Requests of the serving mix's extreme sizes, each in both precisions and both reductions
+    (Eq. 1 and Eq. 2), all submitted together so that they are batched and overlap on the device:
+    on two whole frames of every request (the first and one drawn at random) the served loss is
+    within 1e-5 of the oracle's and the served vertex gradient within 1e-5 of the sum of absolute
+    contributions, component by component (Sec. III-A Eq. 1-2, Sec. III-B Eq. 3-4); every
+    frame's loss is finite and positive."""
+    gpu()
+    from paper_2204_03139_amd.serving import Server
+    srv = Server(hbm_budget_bytes=16 << 30)
+    cases = []
+    for k, req in enumerate(_mix_extremes()):
+        verts, faces, obs = gen.request_inputs(req)
+        for prec, red in ((0, 0), (1, 0), (0, 1), (1, 1)):
+            say(f"[serving] submit {req} precision={prec} reduction={red}")
+            tk = srv.submit(verts, faces, obs, req["Na"], req["seed"], prec, red)
+            cases.append((req, verts, faces, obs, prec, red, tk))
+    rng = np.random.default_rng(12)
+    for req, verts, faces, obs, prec, red, tk in cases:
+        st, loss, grad, _ = srv.wait(tk, timeout=300)
+        assert st == 0, (req, prec, red)
+        assert np.all(np.isfinite(loss)) and np.all(loss > 0)
+        frames = sorted({0, int(rng.integers(req["T"]))})
+        say(f"[serving] check {req} precision={prec} reduction={red} frames={frames}")
+        for t in frames:
+            ol, ogv, ogva = _oracle_frame(verts, faces, obs, req["seed"], t, req["Na"], red)
+            assert_rel(loss[t:t + 1], [ol], 1e-5, "served loss")
+            assert_grad(grad[t], ogv, ogva, what="served grad_verts")
     srv.close()
