@@ -183,23 +183,25 @@ def _frame_words(oracle, seed, t, N):
 
 
 def run_serving(p, torch, rate_hz=None, n_requests=None, budget_bytes=64 << 30, max_slots=64,
-                precision=1, arrival_seeds=3):
+                precision=1, arrival_seeds=5):
     """Serving leg: seeded requests of uneven mesh size, point counts and frame counts arrive as a
     Poisson process; each is submitted to the library's serving loop at its arrival time and its
     latency is completion minus scheduled arrival.  The same requests are replayed under several
-    arrival seeds (p50/p99 per seed and their medians); a last pass submits everything at once to
-    measure capacity."""
+    arrival seeds: p50/p99 over all requests of all seeds pooled, and per seed p50, p99 and max;
+    a last pass submits everything at once to measure capacity."""
     from paper_2204_03139_amd.serving import Server
     from workloads import gen
     reqs, _ = gen.serving_requests(n_requests=n_requests, rate_hz=rate_hz)
     inputs = [gen.request_inputs(r) for r in reqs]
     pairs = [float(r["T"]) * r["Na"] * r["Nb"] for r in reqs]
     srv = Server(hbm_budget_bytes=budget_bytes, max_slots=max_slots)
-    # warm the loop (batch slots, pinned staging, the memory pool, code objects) with 16 requests
+    # warm-up (untimed): every request submitted at once, so the loop's device segments and pinned
+    # staging reach the size the mix needs and every code object is loaded before timing starts
     warm = [srv.submit(*inputs[k], reqs[k]["Na"], reqs[k]["seed"], precision)
-            for k in range(min(16, len(reqs)))]
+            for k in range(len(reqs))]
     for tk in warm:
-        srv.wait(tk)
+        if srv.wait(tk)[0] != 0:
+            raise RuntimeError("a warm-up request failed")
 
     def drive(times):
         pending = {}
@@ -225,19 +227,28 @@ def run_serving(p, torch, rate_hz=None, n_requests=None, budget_bytes=64 << 30, 
         return np.array([done[kk] for kk in sorted(done)]), span
 
     per_seed = []
+    pooled = []
     for seed in range(arrival_seeds):
         _, arrivals = gen.serving_requests(n_requests=n_requests, rate_hz=rate_hz,
                                            arrival_seed=seed)
         lat, span = drive(arrivals)
+        pooled.append(lat)
         per_seed.append(dict(arrival_seed=seed, p50_ms=float(np.percentile(lat, 50) * 1e3),
                              p99_ms=float(np.percentile(lat, 99) * 1e3),
                              max_ms=float(lat.max() * 1e3), span_s=float(span)))
     _, span_sat = drive(np.zeros(len(reqs)))
+    held = srv.ctx.memory_held()[0]
     srv.close()
     total = sum(pairs)
-    med = lambda key: float(np.median([d[key] for d in per_seed]))
+    pooled = np.concatenate(pooled)
     return dict(requests=len(reqs), rate_hz=gen.CONFIGS[5]["rate_hz"] if rate_hz is None else rate_hz,
-                p50_ms=med("p50_ms"), p99_ms=med("p99_ms"), per_arrival_seed=per_seed,
+                p50_ms=float(np.percentile(pooled, 50) * 1e3),
+                p99_ms=float(np.percentile(pooled, 99) * 1e3),
+                max_ms=float(pooled.max() * 1e3),
+                latency_note=f"p50/p99/max over all {len(pooled)} requests of "
+                             f"{arrival_seeds} arrival seeds pooled",
+                worst_seed_p99_ms=max(d["p99_ms"] for d in per_seed),
+                per_arrival_seed=per_seed, device_bytes_held_at_end=held,
                 pairs_total=total,
                 pairs_per_s_at_offered_load=total / float(np.median([d["span_s"] for d in per_seed])),
                 saturation_pairs_per_s=total / span_sat,

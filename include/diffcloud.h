@@ -59,9 +59,13 @@ typedef struct dc_ctx dc_ctx;
 
 /* ------------------------------------------------------------------ context */
 /* Create a context on HIP device `device`.  hbm_budget_bytes caps the device memory the context
- * may hold at once (scratch of direct calls plus resident requests of the serving loop);
- * 0 means 64 GiB.  max_slots caps the requests the serving loop keeps in flight (0 means 64).
- * On success *out receives the context.  Errors: DC_ERR_INVALID, DC_ERR_HIP, DC_ERR_NOMEM. */
+ * holds at any time (0 means 64 GiB): its status words, the scratch of direct calls (grow-only,
+ * kept until dc_destroy), and once the serving loop has started, its batch descriptors and the
+ * segments its requests' regions are carved from (kept while requests are in flight, given back
+ * only when none is).  max_slots caps the requests the serving loop keeps in flight (0 means 64).
+ * On success *out receives the context.
+ * Errors: DC_ERR_INVALID, DC_ERR_HIP, DC_ERR_NOMEM, DC_ERR_BUDGET (budget below a few hundred
+ * bytes). */
 int dc_create(dc_ctx **out, int device, size_t hbm_budget_bytes, int max_slots);
 
 /* Wait for the serving loop to drain, free everything the context owns, destroy it. */
@@ -243,10 +247,17 @@ typedef struct dc_result {
     int status;         /* DC_OK or an error code once done */
 } dc_result;
 
-/* Queue a request.  It is admitted once its device memory fits under the budget and a slot is
- * free; admitted requests are batched with whatever else is waiting and run on the device
- * alongside requests already in flight.  A request whose memory alone exceeds the budget fails
- * with DC_ERR_BUDGET at once.  *ticket identifies it for dc_poll().  Thread-safe. */
+/* Queue a request.  Its host inputs are copied into pinned staging before the call returns.
+ * Requests are admitted in arrival order, each once a device region of dc_request_bytes() can be
+ * carved from the serving loop's memory (growing it if the budget allows) and fewer than
+ * max_slots requests are in flight; admitted requests are batched with whatever else is waiting
+ * and run on the device alongside requests already in flight.  A request that cannot fit waits
+ * while others are in flight; if it still cannot fit when none is (the direct calls' scratch
+ * holds too much of the budget), it fails with DC_ERR_BUDGET, and a refused device allocation
+ * fails it with DC_ERR_NOMEM: either way alone, the others of its batch are unaffected.  A
+ * request larger than the budget can ever hold (its region beside the context's status words and
+ * the serving loop's batch descriptors, about 1.1 MB) fails with DC_ERR_BUDGET at once.  *ticket
+ * identifies it for dc_poll().  Thread-safe. */
 int dc_submit(dc_ctx *ctx, const dc_request *req, dc_result *out, uint64_t *ticket);
 
 /* Device bytes the request would hold while admitted (inputs, intermediates, outputs, scratch),
@@ -254,12 +265,20 @@ int dc_submit(dc_ctx *ctx, const dc_request *req, dc_result *out, uint64_t *tick
  * (dc_submit runs it when the result's grad_verts is not NULL).  Errors: DC_ERR_INVALID. */
 int dc_request_bytes(const dc_request *req, int want_grad, size_t *bytes);
 
-/* DC_PENDING while queued or running; then the request's final status (DC_OK or an error),
- * after which the ticket is forgotten (a second poll gives DC_ERR_INVALID).  Thread-safe. */
+/* DC_PENDING while queued or running.  Once the request has finished, the poll copies its
+ * results into the caller's dc_result buffers, sets status and t_done, and returns the final
+ * status (DC_OK or an error); the ticket is then forgotten (a second poll gives DC_ERR_INVALID).
+ * Thread-safe. */
 int dc_poll(dc_ctx *ctx, uint64_t ticket);
 
+/* Device bytes the context holds against its budget now (*held), and the budget (*budget, may be
+ * NULL).  Errors: DC_ERR_INVALID. */
+int dc_memory_held(dc_ctx *ctx, size_t *held, size_t *budget);
+
 /* Test hook: make the context's next n device allocations fail with DC_ERR_NOMEM, so that
- * failure handling can be exercised without exhausting the device. */
+ * failure handling can be exercised without exhausting the device.  An allocation is a growth of
+ * the direct calls' scratch, or the device region of one serving request at its admission (that
+ * request then fails alone). */
 int dc_debug_fail_allocs(dc_ctx *ctx, int n);
 
 /* Library version as major*10000 + minor*100 + patch. */

@@ -37,7 +37,7 @@ EXPORTS = ["dc_create", "dc_destroy", "dc_last_error", "dc_sync", "dc_sample_sur
            "dc_sample_surface_masked", "dc_rigid_pose", "dc_rigid_pose_bwd",
            "dc_sample_surface_bwd", "dc_chamfer_fwd", "dc_chamfer_bwd", "dc_get_stats",
            "dc_submit", "dc_poll", "dc_version", "dc_debug_fail_allocs", "dc_profile",
-           "dc_get_kernel_times", "dc_request_bytes"]
+           "dc_get_kernel_times", "dc_request_bytes", "dc_memory_held"]
 
 
 class DCError(RuntimeError):
@@ -102,6 +102,8 @@ def load():
     L.dc_poll.argtypes = [vp, u64]
     L.dc_request_bytes.argtypes = [ctypes.POINTER(Request), i, ctypes.POINTER(ctypes.c_size_t)]
     L.dc_debug_fail_allocs.argtypes = [vp, i]
+    L.dc_memory_held.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t),
+                                 ctypes.POINTER(ctypes.c_size_t)]
     L.dc_profile.argtypes = [vp, i]
     L.dc_get_kernel_times.argtypes = [vp, ctypes.POINTER(KernelTimes), i]
     _lib = L
@@ -181,6 +183,13 @@ class Context:
         _check(load().dc_get_kernel_times(self._h, ctypes.byref(kt), int(reset)),
                "dc_get_kernel_times")
         return {name: (kt.ms[k], kt.launches[k]) for k, name in enumerate(KERNEL_CATEGORIES)}
+
+    def memory_held(self) -> tuple[int, int]:
+        """(device bytes held against the budget, the budget)."""
+        held, budget = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(load().dc_memory_held(self._h, ctypes.byref(held), ctypes.byref(budget)),
+               "dc_memory_held")
+        return held.value, budget.value
 
     def debug_fail_allocs(self, n: int):
         _check(load().dc_debug_fail_allocs(self._h, n), "dc_debug_fail_allocs")

@@ -37,20 +37,19 @@ void budget_give(dc_ctx *ctx, size_t bytes) {
     ctx->held -= bytes;
 }
 
-int dev_alloc(dc_ctx *ctx, void **p, size_t bytes) {
+bool forced_alloc_failure(dc_ctx *ctx) {
+    std::lock_guard<std::mutex> g(ctx->budget_mu);
+    if (ctx->fail_next_alloc <= 0) return false;
+    --ctx->fail_next_alloc;
+    return true;
+}
+
+int dev_alloc_raw(dc_ctx *ctx, void **p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) return DC_OK;
     int rc = budget_take(ctx, bytes);
     if (rc != DC_OK) return rc;
-    bool forced = false;
-    {
-        std::lock_guard<std::mutex> g(ctx->budget_mu);
-        if (ctx->fail_next_alloc > 0) {
-            --ctx->fail_next_alloc;
-            forced = true;
-        }
-    }
-    hipError_t e = forced ? hipErrorOutOfMemory : hipMalloc(p, bytes);
+    const hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         budget_give(ctx, bytes);
@@ -59,6 +58,16 @@ int dev_alloc(dc_ctx *ctx, void **p, size_t bytes) {
         return DC_ERR_NOMEM;
     }
     return DC_OK;
+}
+
+int dev_alloc(dc_ctx *ctx, void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) return DC_OK;
+    if (forced_alloc_failure(ctx)) {
+        set_error("device allocation of " + std::to_string(bytes) + " bytes failed (forced)");
+        return DC_ERR_NOMEM;
+    }
+    return dev_alloc_raw(ctx, p, bytes);
 }
 
 void dev_free(dc_ctx *ctx, void *p, size_t bytes) {
@@ -211,6 +220,13 @@ int dc_create(dc_ctx **out, int device, size_t hbm_budget_bytes, int max_slots) 
     c->device = device;
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t(64) << 30);
     c->max_slots = max_slots ? max_slots : 64;
+    // the status and counter words are the first device memory held against the budget
+    c->held = CTX_WORDS_BYTES;
+    if (c->held > c->budget) {
+        delete c;
+        set_error("dc_create: the budget cannot hold the context's status words");
+        return DC_ERR_BUDGET;
+    }
     hipError_t e = hipMalloc(&c->d_status, sizeof(unsigned) * 4);
     if (e == hipSuccess) e = hipMalloc(&c->d_stats, sizeof(unsigned long long) * 4);
     if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(unsigned) * 4);
@@ -311,6 +327,15 @@ int dc_get_kernel_times(dc_ctx *ctx, dc_kernel_times *out, int reset) {
             ctx->prof_n[k] = 0;
         }
     }
+    return DC_OK;
+}
+
+int dc_memory_held(dc_ctx *ctx, size_t *held, size_t *budget) {
+    clear_error();
+    if (!ctx || !held) return DC_ERR_INVALID;
+    std::lock_guard<std::mutex> g(ctx->budget_mu);
+    *held = ctx->held;
+    if (budget) *budget = ctx->budget;
     return DC_OK;
 }
 

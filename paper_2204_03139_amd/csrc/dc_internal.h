@@ -82,8 +82,14 @@ namespace dc {
 // reserve `bytes` of the budget; DC_ERR_BUDGET if it cannot fit
 int budget_take(dc_ctx *ctx, size_t bytes);
 void budget_give(dc_ctx *ctx, size_t bytes);
-// device allocation counted against the budget
+// device bytes of the context's status and counter words (held from dc_create on)
+constexpr size_t CTX_WORDS_BYTES = sizeof(unsigned) * 4 + sizeof(unsigned long long) * 4;
+// test hook: true (and one fewer pending) when the next allocation is to fail
+bool forced_alloc_failure(dc_ctx *ctx);
+// device allocation counted against the budget; dev_alloc honours the test hook, dev_alloc_raw
+// does not (its caller has consulted the hook for the allocation it serves)
 int dev_alloc(dc_ctx *ctx, void **p, size_t bytes);
+int dev_alloc_raw(dc_ctx *ctx, void **p, size_t bytes);
 void dev_free(dc_ctx *ctx, void *p, size_t bytes);
 // Make sure the direct-call arena holds at least `bytes` and reset its offset.  When the previous
 // direct call ran on another stream, `s` first waits for that call's work, so calls on different

@@ -13,13 +13,23 @@
 // request's launches (kernel, logical grid, parameters) instead of executing them; each launch is
 // assigned, in order, to the next program stage of its kernel, and the batch's stage tables are
 // uploaded to the slot's device descriptor before the replay.
-// Inputs are uploaded from pinned staging in one copy per request, results come back the same
-// way, and an event marks the batch's completion.  Every request executes exactly the launches
-// of its direct calls, so its results do not depend on what it is batched with.
+// Memory.  Device memory of requests comes from a pool of large segments held against the
+// context's HBM budget: a request is admitted when a region of its size can be carved from the
+// segments, or a new segment fits under the budget; its region returns to the pool (not to the
+// device) when its batch completes.  Segments are only released when no request is in flight, so
+// the scheduler thread never frees device memory while batches run.  Host inputs are copied at
+// submit into pinned staging (a second pool, host memory) laid out like the front of the
+// request's device region, so each request is uploaded with one copy and the scheduler thread
+// never copies request data itself; results come back the same way into pinned staging, and
+// dc_poll moves them into the caller's buffers.  An event marks the batch's completion.  Every
+// request executes exactly the launches of its direct calls, so its results do not depend on
+// what it is batched with.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
+#include <memory>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -109,32 +119,102 @@ static_assert(NPROG <= MAX_STAGES, "program longer than the descriptor");
 
 enum { Q_QUEUED = 0, Q_RUNNING = 1, Q_DONE = 2 };
 
-struct Req {
-    uint64_t ticket = 0;
-    dc_result *out = nullptr;
-    int T = 0, V = 0, F = 0, Na = 0, Nb = 0, precision = 0, reduction = 0;
-    uint64_t seed = 0;
-    bool want_grad = false, has_w = false;
-    std::vector<float> verts, obs, fw;
-    std::vector<int32_t> faces;
-    size_t bytes = 0;
-    double pairs = 0;
-    int state = Q_QUEUED;
-    int status = DC_OK;
-    // within the batch
-    size_t dev_off = 0, in_off = 0, out_off = 0;
-    std::vector<OpRec> ops;
-    std::vector<int> stage_of;
+// ---------------------------------------------------------------- segment pools
+// Free ranges of one segment: first fit, neighbouring free ranges merged on release.
+class RangeList {
+  public:
+    void init(size_t cap) {
+        free_.clear();
+        free_[0] = cap;
+    }
+    bool take(size_t n, size_t *off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            *off = it->first;
+            const size_t rest = it->second - n, o = it->first;
+            free_.erase(it);
+            if (rest) free_[o + n] = rest;
+            return true;
+        }
+        return false;
+    }
+    void give(size_t off, size_t n) {
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+  private:
+    std::map<size_t, size_t> free_;  // offset -> length
 };
 
-// device pieces of one request, carved from its region: inputs, then outputs, then the rest
-struct Layout {
-    float *verts, *obs, *fw, *pts, *bary, *da, *db, *gpts, *gverts;
-    int32_t *faces, *fidx, *ia, *ib;
-    double *loss, *gl;
-    unsigned *status;
-    char *scratch;
-    size_t in_bytes, out_bytes;
+struct Segment {
+    char *base = nullptr;
+    size_t cap = 0;
+    RangeList ranges;
+};
+
+struct Block {
+    char *p = nullptr;
+    size_t bytes = 0;
+    Segment *seg = nullptr;
+};
+
+// A pool of segments (device or pinned host memory); the owner allocates and frees segments.
+struct SegPool {
+    std::vector<std::unique_ptr<Segment>> segs;
+    bool carve(size_t n, Block *b) {
+        n = Arena::need(n, 1);
+        for (auto &sg : segs) {
+            size_t off = 0;
+            if (sg->ranges.take(n, &off)) {
+                b->p = sg->base + off;
+                b->bytes = n;
+                b->seg = sg.get();
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(Block *b) {
+        if (!b->seg) return;
+        b->seg->ranges.give((size_t)(b->p - b->seg->base), b->bytes);
+        *b = Block();
+    }
+    Segment *add(char *base, size_t cap) {
+        segs.emplace_back(new Segment());
+        Segment *sg = segs.back().get();
+        sg->base = base;
+        sg->cap = cap;
+        sg->ranges.init(cap);
+        return sg;
+    }
+};
+
+constexpr size_t MIB = size_t(1) << 20;
+constexpr size_t HOST_SEG_MIN = 64 * MIB;     // first pinned staging segment
+constexpr size_t HOST_SEG_MAX = 1024 * MIB;   // segments double up to this size
+constexpr size_t DEV_SEG_MIN = 256 * MIB;     // device segments: budget / 8 within these bounds
+constexpr size_t DEV_SEG_MAX = 4096 * MIB;
+
+// ---------------------------------------------------------------- request layout
+// Byte offsets of a request's pieces within its device region: inputs, then outputs, then the
+// intermediates and scratch.  The inputs form one contiguous prefix (one upload) and the outputs
+// the next contiguous range (one download).
+struct RegionMap {
+    size_t verts, faces, obs, fw, loss, status, gverts, pts, bary, fidx, da, ia, db, ib, gl, gpts,
+        scratch;
+    size_t in_bytes, out_bytes, total;
 };
 
 size_t scratch_bytes(int T, int V, int F, int Na, int Nb, int precision, bool want_grad) {
@@ -147,34 +227,84 @@ size_t scratch_bytes(int T, int V, int F, int Na, int Nb, int precision, bool wa
     return s;
 }
 
-Layout carve(const Req *r, char *base) {
-    Arena ar;
-    ar.base = base;
-    ar.cap = r->bytes;
-    const int T = r->T, V = r->V, F = r->F, Na = r->Na, Nb = r->Nb;
+RegionMap region_map(int T, int V, int F, int Na, int Nb, int precision, bool want_grad) {
     const size_t TV = (size_t)T * V, TA = (size_t)T * Na, TB = (size_t)T * Nb;
+    RegionMap m;
+    size_t off = 0;
+    auto take = [&](size_t count, size_t elem) {
+        const size_t o = off;
+        off += Arena::need(count, elem);
+        return o;
+    };
+    m.verts = take(TV * 3, 4);
+    m.faces = take((size_t)F * 3, 4);
+    m.obs = take(TB * 3, 4);
+    m.fw = take(T, 4);
+    m.in_bytes = off;
+    m.loss = take(T, 8);
+    m.status = take(4, 4);
+    m.gverts = want_grad ? take(TV * 3, 4) : off;
+    m.out_bytes = off - m.in_bytes;
+    m.pts = take(TA * 3, 4);
+    m.bary = take(TA * 3, 4);
+    m.fidx = take(TA, 4);
+    m.da = take(TA, 4);
+    m.ia = take(TA, 4);
+    m.db = take(TB, 4);
+    m.ib = take(TB, 4);
+    m.gl = want_grad ? take(T, 8) : off;
+    m.gpts = want_grad ? take(TA * 3, 4) : off;
+    m.scratch = take(scratch_bytes(T, V, F, Na, Nb, precision, want_grad), 1);
+    m.total = off;
+    return m;
+}
+
+// device pieces of one request at `base`
+struct Layout {
+    float *verts, *obs, *fw, *pts, *bary, *da, *db, *gpts, *gverts;
+    int32_t *faces, *fidx, *ia, *ib;
+    double *loss, *gl;
+    unsigned *status;
+    char *scratch;
+};
+
+Layout layout_at(const RegionMap &m, char *base, bool want_grad) {
     Layout L;
-    L.verts = ar.take<float>(TV * 3);
-    L.faces = ar.take<int32_t>((size_t)F * 3);
-    L.obs = ar.take<float>(TB * 3);
-    L.fw = ar.take<float>(T);
-    L.in_bytes = ar.off;
-    L.loss = ar.take<double>(T);
-    L.status = ar.take<unsigned>(4);
-    L.gverts = r->want_grad ? ar.take<float>(TV * 3) : nullptr;
-    L.out_bytes = ar.off - L.in_bytes;
-    L.pts = ar.take<float>(TA * 3);
-    L.bary = ar.take<float>(TA * 3);
-    L.fidx = ar.take<int32_t>(TA);
-    L.da = ar.take<float>(TA);
-    L.ia = ar.take<int32_t>(TA);
-    L.db = ar.take<float>(TB);
-    L.ib = ar.take<int32_t>(TB);
-    L.gl = r->want_grad ? ar.take<double>(T) : nullptr;
-    L.gpts = r->want_grad ? ar.take<float>(TA * 3) : nullptr;
-    L.scratch = ar.take<char>(scratch_bytes(T, V, F, Na, Nb, r->precision, r->want_grad));
+    L.verts = reinterpret_cast<float *>(base + m.verts);
+    L.faces = reinterpret_cast<int32_t *>(base + m.faces);
+    L.obs = reinterpret_cast<float *>(base + m.obs);
+    L.fw = reinterpret_cast<float *>(base + m.fw);
+    L.loss = reinterpret_cast<double *>(base + m.loss);
+    L.status = reinterpret_cast<unsigned *>(base + m.status);
+    L.gverts = want_grad ? reinterpret_cast<float *>(base + m.gverts) : nullptr;
+    L.pts = reinterpret_cast<float *>(base + m.pts);
+    L.bary = reinterpret_cast<float *>(base + m.bary);
+    L.fidx = reinterpret_cast<int32_t *>(base + m.fidx);
+    L.da = reinterpret_cast<float *>(base + m.da);
+    L.ia = reinterpret_cast<int32_t *>(base + m.ia);
+    L.db = reinterpret_cast<float *>(base + m.db);
+    L.ib = reinterpret_cast<int32_t *>(base + m.ib);
+    L.gl = want_grad ? reinterpret_cast<double *>(base + m.gl) : nullptr;
+    L.gpts = want_grad ? reinterpret_cast<float *>(base + m.gpts) : nullptr;
+    L.scratch = base + m.scratch;
     return L;
 }
+
+struct Req {
+    uint64_t ticket = 0;
+    dc_result *out = nullptr;
+    int T = 0, V = 0, F = 0, Na = 0, Nb = 0, precision = 0, reduction = 0;
+    uint64_t seed = 0;
+    bool want_grad = false, has_w = false;
+    RegionMap map{};
+    double pairs = 0;
+    int state = Q_QUEUED;
+    int status = DC_OK;
+    Block dev;          // device region, from admission to the batch's completion
+    Block h_in, h_out;  // pinned staging, from submit to the final poll
+    std::vector<OpRec> ops;
+    std::vector<int> stage_of;
+};
 
 // the launches of a request's whole pipeline, issued through dispatch()
 int issue_request(const Req *r, const Layout &L, unsigned long long *stats) {
@@ -183,7 +313,7 @@ int issue_request(const Req *r, const Layout &L, unsigned long long *stats) {
     fill_u32(L.status, 4, 0u, s);
     Arena sar;
     sar.base = L.scratch;
-    sar.cap = r->bytes;
+    sar.cap = r->map.total - r->map.scratch;
     int rc = enqueue_sample(nullptr, L.verts, L.faces, T, V, F, Na, r->seed, nullptr, nullptr, 0,
                             L.pts, L.fidx, L.bary, sar, L.status, s);
     if (rc) return rc;
@@ -202,12 +332,11 @@ int issue_request(const Req *r, const Layout &L, unsigned long long *stats) {
     return DC_OK;
 }
 
-// record a request's launches against a region at `base` and assign them to program stages
-int plan_request(Req *r, char *base, unsigned long long *stats) {
+// record a request's launches against its device region and assign them to program stages
+int plan_request(Req *r, unsigned long long *stats) {
     Recording rec;
     g_record = &rec;
-    const Layout L = carve(r, base);
-    const int rc = issue_request(r, L, stats);
+    const int rc = issue_request(r, layout_at(r->map, r->dev.p, r->want_grad), stats);
     g_record = nullptr;
     if (rc) return rc;
     r->ops.swap(rec.ops);
@@ -225,7 +354,7 @@ int plan_request(Req *r, char *base, unsigned long long *stats) {
     return DC_OK;
 }
 
-// one batch slot: a stream, the captured program over the slot's descriptor, pinned staging
+// one batch slot: a stream and the captured program over the slot's descriptor
 struct BatchSlot {
     hipStream_t stream = nullptr;
     BatchDesc *d_desc = nullptr;
@@ -234,31 +363,10 @@ struct BatchSlot {
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t nodes[MAX_STAGES] = {};
     bool enabled[MAX_STAGES] = {};
-    char *h_in = nullptr, *h_out = nullptr;
-    size_t in_cap = 0, out_cap = 0;
-    // the batch's device region: owned by the slot and grown when a batch needs more (a
-    // per-batch stream-ordered allocation and free cost 0.35 ms of host time per batch)
-    char *dmem = nullptr;
-    size_t dcap = 0;
     hipEvent_t ev = nullptr;
     std::vector<Req *> reqs;
     bool busy = false;
 };
-
-int grow_pinned(char **p, size_t *cap, size_t need) {
-    if (*cap >= need) return DC_OK;
-    if (*p) (void)hipHostFree(*p);
-    *p = nullptr;
-    *cap = 0;
-    const size_t n = std::max(need, (size_t)1 << 20) * 5 / 4;
-    if (hipHostMalloc(reinterpret_cast<void **>(p), n, 0) != hipSuccess) {
-        *p = nullptr;
-        set_error("pinned staging allocation failed");
-        return DC_ERR_NOMEM;
-    }
-    *cap = n;
-    return DC_OK;
-}
 
 }  // namespace
 
@@ -269,47 +377,121 @@ struct Scheduler {
     std::deque<Req *> queue;
     std::unordered_map<uint64_t, Req *> table;
     uint64_t next_ticket = 1;
-    int running = 0;  // requests admitted and not finished
+    int running = 0;  // requests admitted and not finished on the device
     bool stop = false;
     BatchedKernel kern[KT_COUNT] = {};
     BatchSlot slots[NSLOTS];
     std::thread th;
+    // device memory of admitted requests (scheduler thread only)
+    SegPool dpool;
+    size_t dev_seg = DEV_SEG_MIN;
+    // pinned staging of requests between submit and poll
+    std::mutex hmu;
+    SegPool hpool;
+    size_t host_seg = HOST_SEG_MIN;
 };
 
 size_t request_bytes(int T, int V, int F, int Na, int Nb, int precision, bool want_grad) {
-    const size_t TV = (size_t)T * V, TA = (size_t)T * Na, TB = (size_t)T * Nb;
-    size_t b = 0;
-    b += Arena::need(TV * 3, 4) + Arena::need((size_t)F * 3, 4) + Arena::need(TB * 3, 4);
-    b += Arena::need(T, 4) + Arena::need(4, 4);                         // frame weights, status
-    b += Arena::need(TA * 3, 4) * 2 + Arena::need(TA, 4);              // points, bary, face_idx
-    b += Arena::need(TA, 4) * 2 + Arena::need(TB, 4) * 2 + Arena::need(T, 8);  // nn + loss
-    if (want_grad)
-        b += Arena::need(T, 8) + Arena::need(TA * 3, 4) + Arena::need(TV * 3, 4);
-    b += scratch_bytes(T, V, F, Na, Nb, precision, want_grad);
-    return b;
+    return region_map(T, V, F, Na, Nb, precision, want_grad).total;
 }
 
-static void finish_req(Scheduler *S, Req *r, const char *h) {
-    if (r->status == DC_OK && h) {
-        std::memcpy(r->out->loss, h, (size_t)r->T * 8);
-        unsigned st = 0;
-        std::memcpy(&st, h + Arena::need(r->T, 8), 4);
-        if (st & ST_BAD_FACE)
-            r->status = DC_ERR_INVALID;
-        else if (st & ST_DEGENERATE)
-            r->status = DC_ERR_DEGENERATE;
-        if (r->want_grad)
-            std::memcpy(r->out->grad_verts, h + Arena::need(r->T, 8) + Arena::need(4, 4),
-                        (size_t)r->T * r->V * 3 * 4);
+size_t serving_fixed_bytes() { return sizeof(BatchDesc) * NSLOTS; }
+
+// pinned staging for `n` bytes; a new segment is added when none has room (client threads only)
+static int host_alloc(Scheduler *S, size_t n, Block *b) {
+    std::lock_guard<std::mutex> g(S->hmu);
+    if (S->hpool.carve(n, b)) return DC_OK;
+    const size_t want = std::max(Arena::need(n, 1), S->host_seg);
+    void *p = nullptr;
+    if (hipHostMalloc(&p, want, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("pinned staging allocation failed");
+        return DC_ERR_NOMEM;
     }
-    budget_give(S->ctx, r->bytes);
-    --S->running;
-    r->out->t_done = now_s();
-    r->out->status = r->status;
+    S->hpool.add(static_cast<char *>(p), want);
+    S->host_seg = std::min(S->host_seg * 2, HOST_SEG_MAX);
+    return S->hpool.carve(n, b) ? DC_OK : DC_ERR_NOMEM;
+}
+
+static void host_release(Scheduler *S, Block *b) {
+    std::lock_guard<std::mutex> g(S->hmu);
+    S->hpool.release(b);
+}
+
+// Add a device segment that holds `need` bytes, counted against the budget: the default segment
+// size when it fits, else whatever the budget still allows.  DC_ERR_BUDGET when the budget has
+// no room for `need`; DC_ERR_NOMEM when the device refuses the allocation.
+static int dev_grow(Scheduler *S, size_t need, bool exact) {
+    dc_ctx *ctx = S->ctx;
+    size_t room;
+    {
+        std::lock_guard<std::mutex> g(ctx->budget_mu);
+        room = ctx->budget - ctx->held;
+    }
+    need = Arena::need(need, 1);
+    if (need > room) {
+        set_error("request of " + std::to_string(need) + " bytes does not fit the budget (" +
+                  std::to_string(room) + " bytes free)");
+        return DC_ERR_BUDGET;
+    }
+    const size_t want = exact ? need : std::min(std::max(need, S->dev_seg), room);
+    void *p = nullptr;
+    const int rc = dev_alloc_raw(ctx, &p, want);
+    if (rc != DC_OK) return rc;
+    S->dpool.add(static_cast<char *>(p), want);
+    return DC_OK;
+}
+
+// give the device segments back (only while no request is in flight: every segment is free)
+static void dev_release_all(Scheduler *S) {
+    for (auto &sg : S->dpool.segs) dev_free(S->ctx, sg->base, sg->cap);
+    S->dpool.segs.clear();
+}
+
+// A queued request's device region and plan.  DC_OK: admitted; DC_PENDING: not now (memory
+// returns when requests in flight finish); an error: the request fails alone.
+static int admit(Scheduler *S, Req *r) {
+    if (forced_alloc_failure(S->ctx)) {
+        set_error("device region of a request: allocation failed (forced)");
+        return DC_ERR_NOMEM;
+    }
+    const size_t n = r->map.total;
+    if (!S->dpool.carve(n, &r->dev)) {
+        int rc = dev_grow(S, n, false);
+        if (rc != DC_OK) {
+            if (S->running > 0) return DC_PENDING;
+            // nothing in flight, so every segment is free and none is large enough: trade them
+            // for one that holds this request exactly
+            dev_release_all(S);
+            rc = dev_grow(S, n, true);
+            if (rc != DC_OK) return rc;
+        }
+        if (!S->dpool.carve(n, &r->dev)) {
+            set_error("device pool: a new segment could not hold its request");
+            return DC_ERR_NOMEM;
+        }
+    }
+    const int rc = plan_request(r, S->ctx->d_stats);
+    if (rc != DC_OK) S->dpool.release(&r->dev);
+    return rc;
+}
+
+// a request leaves the device: its status word is read from its staging, its region returns to
+// the pool; dc_poll hands the results over
+static void finish_req(Scheduler *S, Req *r, bool on_device) {
+    if (on_device) {
+        if (r->status == DC_OK) {
+            unsigned st = 0;
+            std::memcpy(&st, r->h_out.p + (r->map.status - r->map.in_bytes), 4);
+            if (st & ST_BAD_FACE)
+                r->status = DC_ERR_INVALID;
+            else if (st & ST_DEGENERATE)
+                r->status = DC_ERR_DEGENERATE;
+        }
+        S->dpool.release(&r->dev);
+        --S->running;
+    }
     r->state = Q_DONE;
-    std::vector<float>().swap(r->verts);
-    std::vector<float>().swap(r->obs);
-    std::vector<int32_t>().swap(r->faces);
     std::vector<OpRec>().swap(r->ops);
 }
 
@@ -317,38 +499,6 @@ static void finish_req(Scheduler *S, Req *r, const char *h) {
 // fails with the returned status
 static int run_batch(Scheduler *S, BatchSlot &sl) {
     hipStream_t s = sl.stream;
-    size_t dbytes = 0, in_bytes = 0, out_bytes = 0;
-    for (Req *r : sl.reqs) {
-        r->dev_off = dbytes;
-        dbytes += Arena::need(r->bytes, 1);
-    }
-    if (dbytes > sl.dcap) {  // the slot is idle: its previous batch no longer uses the region
-        if (sl.dmem) (void)hipFree(sl.dmem);
-        sl.dmem = nullptr;
-        sl.dcap = 0;
-        const size_t want = dbytes + dbytes / 4;
-        if (hipMalloc(reinterpret_cast<void **>(&sl.dmem), want) != hipSuccess) {
-            (void)hipGetLastError();
-            sl.dmem = nullptr;
-            set_error("device allocation of a batch failed");
-            return DC_ERR_NOMEM;
-        }
-        sl.dcap = want;
-    }
-    // record every request against its region, then lay the stages out
-    std::vector<Layout> lay;
-    for (Req *r : sl.reqs) {
-        const int rc = plan_request(r, sl.dmem + r->dev_off, S->ctx->d_stats);
-        if (rc) return rc;
-        lay.push_back(carve(r, sl.dmem + r->dev_off));
-        r->in_off = in_bytes;
-        r->out_off = out_bytes;
-        in_bytes += lay.back().in_bytes;
-        out_bytes += lay.back().out_bytes;
-    }
-    int rc = grow_pinned(&sl.h_in, &sl.in_cap, in_bytes);
-    if (rc == DC_OK) rc = grow_pinned(&sl.h_out, &sl.out_cap, out_bytes);
-    if (rc) return rc;
     BatchDesc *D = sl.h_desc;
     int nops = 0;
     for (int st = 0; st < NPROG; ++st) {
@@ -366,22 +516,10 @@ static int run_batch(Scheduler *S, BatchSlot &sl) {
             }
         D->stage[st].total = (int)total;
     }
-    // inputs: one copy per request from pinned staging laid out like its device region
-    for (size_t q = 0; q < sl.reqs.size(); ++q) {
-        const Req *r = sl.reqs[q];
-        const Layout &L = lay[q];
-        char *h = sl.h_in + r->in_off;
-        const char *d0 = reinterpret_cast<const char *>(L.verts);
-        std::memcpy(h, r->verts.data(), r->verts.size() * 4);
-        std::memcpy(h + (reinterpret_cast<const char *>(L.faces) - d0), r->faces.data(),
-                    r->faces.size() * 4);
-        std::memcpy(h + (reinterpret_cast<const char *>(L.obs) - d0), r->obs.data(),
-                    r->obs.size() * 4);
-        if (r->has_w)
-            std::memcpy(h + (reinterpret_cast<const char *>(L.fw) - d0), r->fw.data(),
-                        r->fw.size() * 4);
-        DC_HIP(hipMemcpyAsync(L.verts, h, L.in_bytes, hipMemcpyHostToDevice, s));
-    }
+    // inputs: one copy per request from its pinned staging (laid out like its region's front)
+    for (Req *r : sl.reqs)
+        DC_HIP(hipMemcpyAsync(r->dev.p + r->map.verts, r->h_in.p, r->map.in_bytes,
+                              hipMemcpyHostToDevice, s));
     const size_t dsz = sizeof(D->stage) + (size_t)nops * sizeof(OpRec);
     DC_HIP(hipMemcpyAsync(sl.d_desc, D, dsz, hipMemcpyHostToDevice, s));
     // stages without work in this batch are switched off (the slot is idle, so its executable
@@ -394,11 +532,9 @@ static int run_batch(Scheduler *S, BatchSlot &sl) {
         }
     }
     DC_HIP(hipGraphLaunch(sl.exec, s));
-    for (size_t q = 0; q < sl.reqs.size(); ++q) {
-        const Layout &L = lay[q];
-        DC_HIP(hipMemcpyAsync(sl.h_out + sl.reqs[q]->out_off, L.loss, L.out_bytes,
+    for (Req *r : sl.reqs)
+        DC_HIP(hipMemcpyAsync(r->h_out.p, r->dev.p + r->map.in_bytes, r->map.out_bytes,
                               hipMemcpyDeviceToHost, s));
-    }
     DC_HIP(hipEventRecord(sl.ev, s));
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "serving batch launch");
@@ -409,7 +545,7 @@ static void fail_batch(Scheduler *S, BatchSlot &sl, int rc) {
     (void)hipStreamSynchronize(sl.stream);  // anything already enqueued has finished
     for (Req *r : sl.reqs) {
         r->status = rc;
-        finish_req(S, r, nullptr);
+        finish_req(S, r, true);
     }
     sl.reqs.clear();
     sl.busy = false;
@@ -422,24 +558,17 @@ static bool form_batch(Scheduler *S, BatchSlot &sl) {
            S->running < S->ctx->max_slots) {
         Req *r = S->queue.front();
         if (!sl.reqs.empty() && pairs + r->pairs > BATCH_PAIRS) break;
-        if (budget_take(S->ctx, r->bytes) != DC_OK) break;
+        const int rc = admit(S, r);
+        if (rc == DC_PENDING) break;
         S->queue.pop_front();
-        ++S->running;
-        r->state = Q_RUNNING;
         r->out->t_admit = now_s();
-        bool fail = false;
-        {
-            std::lock_guard<std::mutex> g(S->ctx->budget_mu);
-            if (S->ctx->fail_next_alloc > 0) {  // test hook: a forced allocation failure
-                --S->ctx->fail_next_alloc;
-                fail = true;
-            }
-        }
-        if (fail) {
-            r->status = DC_ERR_NOMEM;
-            finish_req(S, r, nullptr);
+        if (rc != DC_OK) {  // this request alone fails
+            r->status = rc;
+            finish_req(S, r, false);
             continue;
         }
+        ++S->running;
+        r->state = Q_RUNNING;
         sl.reqs.push_back(r);
         pairs += r->pairs;
     }
@@ -454,6 +583,14 @@ static void loop(Scheduler *S) {
         for (auto &sl : S->slots) any_busy |= sl.busy;
         if (S->stop && S->queue.empty() && !any_busy) break;
         bool progressed = false;
+        // completions first: their memory may admit the next requests
+        for (auto &sl : S->slots) {
+            if (!sl.busy || hipEventQuery(sl.ev) != hipSuccess) continue;
+            for (Req *r : sl.reqs) finish_req(S, r, true);
+            sl.reqs.clear();
+            sl.busy = false;
+            progressed = true;
+        }
         for (auto &sl : S->slots) {
             if (sl.busy) continue;
             if (!form_batch(S, sl)) {
@@ -462,19 +599,12 @@ static void loop(Scheduler *S) {
             }
             sl.busy = true;
             progressed = true;
-            // staging and launching run unlocked: the slot and its requests belong to this
-            // thread until they finish, and submit / poll only touch the queue and the table
+            // launching runs unlocked: the slot and its requests belong to this thread until
+            // they finish, and submit / poll only touch the queue and the table
             lk.unlock();
             const int rc = run_batch(S, sl);
             lk.lock();
             if (rc != DC_OK) fail_batch(S, sl, rc);
-        }
-        for (auto &sl : S->slots) {
-            if (!sl.busy || hipEventQuery(sl.ev) != hipSuccess) continue;
-            for (Req *r : sl.reqs) finish_req(S, r, sl.h_out + r->out_off);
-            sl.reqs.clear();
-            sl.busy = false;
-            progressed = true;
         }
         if (!progressed) S->cv.wait_for(lk, std::chrono::microseconds(50));
     }
@@ -483,7 +613,10 @@ static void loop(Scheduler *S) {
 static int init_slot(Scheduler *S, BatchSlot &sl) {
     DC_HIP(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
     DC_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
-    DC_HIP(hipMalloc(reinterpret_cast<void **>(&sl.d_desc), sizeof(BatchDesc)));
+    void *p = nullptr;
+    const int rc = dev_alloc_raw(S->ctx, &p, sizeof(BatchDesc));
+    if (rc != DC_OK) return rc;
+    sl.d_desc = static_cast<BatchDesc *>(p);
     DC_HIP(hipHostMalloc(reinterpret_cast<void **>(&sl.h_desc), sizeof(BatchDesc), 0));
     // an empty descriptor: a replay before the first upload does nothing
     std::memset(sl.h_desc, 0, sizeof(BatchDesc));
@@ -511,22 +644,27 @@ static int init_slot(Scheduler *S, BatchSlot &sl) {
     return DC_OK;
 }
 
-static void release_slot(BatchSlot &sl) {
-    if (sl.dmem) (void)hipFree(sl.dmem);
+static void release_slot(dc_ctx *ctx, BatchSlot &sl) {
     if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
     if (sl.graph) (void)hipGraphDestroy(sl.graph);
-    if (sl.d_desc) (void)hipFree(sl.d_desc);
+    if (sl.d_desc) dev_free(ctx, sl.d_desc, sizeof(BatchDesc));
     if (sl.h_desc) (void)hipHostFree(sl.h_desc);
-    if (sl.h_in) (void)hipHostFree(sl.h_in);
-    if (sl.h_out) (void)hipHostFree(sl.h_out);
     if (sl.ev) (void)hipEventDestroy(sl.ev);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    sl = BatchSlot();
+}
+
+static void release_pools(Scheduler *S) {
+    dev_release_all(S);
+    for (auto &sg : S->hpool.segs) (void)hipHostFree(sg->base);
+    S->hpool.segs.clear();
 }
 
 static int ensure_scheduler(dc_ctx *ctx) {
     if (ctx->sched) return DC_OK;
     Scheduler *S = new Scheduler();
     S->ctx = ctx;
+    S->dev_seg = std::min(std::max(ctx->budget / 8, DEV_SEG_MIN), DEV_SEG_MAX);
     register_sample_kernels(S->kern);
     register_nn_kernels(S->kern);
     register_screen_kernels(S->kern);
@@ -544,7 +682,7 @@ static int ensure_scheduler(dc_ctx *ctx) {
     for (auto &sl : S->slots)
         if (rc == DC_OK) rc = init_slot(S, sl);
     if (rc != DC_OK) {
-        for (auto &sl : S->slots) release_slot(sl);
+        for (auto &sl : S->slots) release_slot(ctx, sl);
         delete S;
         return rc;
     }
@@ -574,12 +712,19 @@ int sched_submit(dc_ctx *ctx, const dc_request *q, dc_result *out, uint64_t *tic
         return DC_ERR_INVALID;
     }
     const bool want_grad = out->grad_verts != nullptr;
-    const size_t bytes =
-        request_bytes(q->T, q->V, q->F, q->n_sim, q->n_obs, q->precision, want_grad);
-    if (bytes > ctx->budget) {
-        set_error("dc_submit: request needs " + std::to_string(bytes) +
-                  " bytes, more than the whole budget");
+    const RegionMap map =
+        region_map(q->T, q->V, q->F, q->n_sim, q->n_obs, q->precision, want_grad);
+    if (map.total + serving_fixed_bytes() + CTX_WORDS_BYTES > ctx->budget) {
+        set_error("dc_submit: request needs " + std::to_string(map.total) +
+                  " bytes, more than the budget holds beside the serving loop's descriptors");
         return DC_ERR_BUDGET;
+    }
+    Scheduler *S = nullptr;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);  // creation of the loop is serialised with direct calls
+        const int rc = ensure_scheduler(ctx);
+        if (rc) return rc;
+        S = ctx->sched;
     }
     Req *r = new Req();
     r->out = out;
@@ -592,26 +737,26 @@ int sched_submit(dc_ctx *ctx, const dc_request *q, dc_result *out, uint64_t *tic
     r->reduction = q->reduction;
     r->seed = q->seed;
     r->want_grad = want_grad;
-    r->bytes = bytes;
+    r->has_w = q->frame_w != nullptr;
+    r->map = map;
     r->pairs = (double)q->T * q->n_sim * q->n_obs;
-    r->verts.assign(q->verts, q->verts + (size_t)q->T * q->V * 3);
-    r->faces.assign(q->faces, q->faces + (size_t)q->F * 3);
-    r->obs.assign(q->observed, q->observed + (size_t)q->T * q->n_obs * 3);
-    if (q->frame_w) {
-        r->has_w = true;
-        r->fw.assign(q->frame_w, q->frame_w + q->T);
+    // the inputs go straight into pinned staging laid out like the region's input prefix
+    int rc = host_alloc(S, map.in_bytes, &r->h_in);
+    if (rc == DC_OK) rc = host_alloc(S, map.out_bytes, &r->h_out);
+    if (rc != DC_OK) {
+        host_release(S, &r->h_in);
+        delete r;
+        return rc;
     }
+    char *h = r->h_in.p;
+    std::memcpy(h + map.verts, q->verts, (size_t)q->T * q->V * 3 * 4);
+    std::memcpy(h + map.faces, q->faces, (size_t)q->F * 3 * 4);
+    std::memcpy(h + map.obs, q->observed, (size_t)q->T * q->n_obs * 3 * 4);
+    if (r->has_w) std::memcpy(h + map.fw, q->frame_w, (size_t)q->T * 4);
     out->t_submit = now_s();
     out->t_admit = 0;
     out->t_done = 0;
     out->status = DC_PENDING;
-    std::lock_guard<std::mutex> g(ctx->mu);  // creation of the loop is serialised with direct calls
-    int rc = ensure_scheduler(ctx);
-    if (rc) {
-        delete r;
-        return rc;
-    }
-    Scheduler *S = ctx->sched;
     {
         std::lock_guard<std::mutex> lk(S->mu);
         r->ticket = S->next_ticket++;
@@ -629,17 +774,33 @@ int sched_poll(dc_ctx *ctx, uint64_t ticket) {
         set_error("dc_poll: unknown ticket");
         return DC_ERR_INVALID;
     }
-    std::lock_guard<std::mutex> lk(S->mu);
-    auto it = S->table.find(ticket);
-    if (it == S->table.end()) {
-        set_error("dc_poll: unknown ticket");
-        return DC_ERR_INVALID;
+    Req *r = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->table.find(ticket);
+        if (it == S->table.end()) {
+            set_error("dc_poll: unknown ticket");
+            return DC_ERR_INVALID;
+        }
+        if (it->second->state != Q_DONE) return DC_PENDING;
+        r = it->second;
+        S->table.erase(it);
     }
-    Req *r = it->second;
-    if (r->state != Q_DONE) return DC_PENDING;
+    // the request now belongs to this thread: hand its results over outside the scheduler's lock
+    const char *h = r->h_out.p;
+    if (r->status == DC_OK) {
+        std::memcpy(r->out->loss, h + (r->map.loss - r->map.in_bytes), (size_t)r->T * 8);
+        if (r->want_grad)
+            std::memcpy(r->out->grad_verts, h + (r->map.gverts - r->map.in_bytes),
+                        (size_t)r->T * r->V * 3 * 4);
+    }
     const int st = r->status;
-    S->table.erase(it);
+    r->out->status = st;
+    r->out->t_done = now_s();
+    host_release(S, &r->h_in);
+    host_release(S, &r->h_out);
     delete r;
+    if (st != DC_OK) set_error("dc_poll: the request failed");
     return st;
 }
 
@@ -653,7 +814,8 @@ void sched_destroy(dc_ctx *ctx) {
     S->cv.notify_one();
     S->th.join();
     for (auto &kv : S->table) delete kv.second;
-    for (auto &sl : S->slots) release_slot(sl);
+    for (auto &sl : S->slots) release_slot(ctx, sl);
+    release_pools(S);
     delete S;
 }
 

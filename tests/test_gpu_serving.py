@@ -141,22 +141,96 @@ def test_budget_rejects_and_queues():
 
 
 def test_failures_stay_with_their_request():
+    """A forced failure of a request's device region, a degenerate request and a request that
+    cannot fit beside the direct calls' scratch each fail alone; requests submitted with them
+    (batched together) complete normally."""
     p = gpu()
     from paper_2204_03139_amd.serving import Server
     say("[serving] failure isolation")
     srv = Server(hbm_budget_bytes=1 << 30)
     good = _request(4)
+    ref = srv.submit(good["verts"], good["faces"], good["obs"], good["Na"], good["seed"])
+    st, loss_ref, grad_ref, _ = srv.wait(ref)
+    assert st == 0
+    # the first of four requests submitted back to back has its region allocation fail
     srv.ctx.debug_fail_allocs(1)
-    t_fail = srv.submit(good["verts"], good["faces"], good["obs"], good["Na"], good["seed"])
-    st, _, _, _ = srv.wait(t_fail)
-    assert st == -2
+    ts = [srv.submit(good["verts"], good["faces"], good["obs"], good["Na"], good["seed"])
+          for _ in range(4)]
+    res = [srv.wait(t) for t in ts]
+    assert res[0][0] == -2
+    for st, loss, grad, _ in res[1:]:
+        assert st == 0
+        assert np.array_equal(loss.view(np.uint64), loss_ref.view(np.uint64))
+        assert np.array_equal(grad.view(np.uint32), grad_ref.view(np.uint32))
     bad = dict(good)
     bad["verts"] = np.zeros_like(good["verts"])  # zero total area in every frame
     t_bad = srv.submit(bad["verts"], bad["faces"], bad["obs"], bad["Na"], bad["seed"])
     t_ok = srv.submit(good["verts"], good["faces"], good["obs"], good["Na"], good["seed"])
     assert srv.wait(t_bad)[0] == -5
     st, loss, grad, _ = srv.wait(t_ok)
-    assert st == 0 and np.all(np.isfinite(loss))
+    assert st == 0 and np.array_equal(loss.view(np.uint64), loss_ref.view(np.uint64))
+    srv.close()
+
+
+def test_request_that_cannot_fit_beside_direct_scratch_fails():
+    """The direct calls' scratch shares the budget: a request that fits the budget alone but not
+    beside that scratch fails with DC_ERR_BUDGET once nothing else is in flight (it neither
+    waits forever nor blocks the context's destruction); a smaller one still runs."""
+    p = gpu()
+    from paper_2204_03139_amd.serving import Server
+    say("[serving] request beside the direct scratch")
+    q = _request(5, n=20, T=3, Na=3000, Nb=3000)
+    small = _request(6, n=8, T=1, Na=300, Nb=300)
+    need = Server.footprint(q["verts"], q["faces"], q["obs"], q["Na"])
+    need_small = Server.footprint(small["verts"], small["faces"], small["obs"], small["Na"])
+    mib = 1 << 20
+    assert need_small + 2 * mib < need
+    # the budget: the request, the serving loop's batch descriptors and status words (under
+    # 1.25 MiB together) and 1 MiB more
+    ctx = p.Context(0, hbm_budget_bytes=need + 2 * mib + mib // 4)
+    # a direct sampling call of 200 frames of 1,152 faces grows the scratch to 2 MiB
+    verts, faces = gen.trajectory(25, 200, 1)
+    p.sample_surface(dev(verts), dev(faces), 16, seed=1, ctx=ctx)
+    ctx.sync()
+    held, budget = ctx.memory_held()
+    assert held >= 2 * mib
+    srv = Server(ctx)
+    t = srv.submit(q["verts"], q["faces"], q["obs"], q["Na"], q["seed"])
+    assert srv.wait(t, timeout=60)[0] == -3
+    t = srv.submit(small["verts"], small["faces"], small["obs"], small["Na"], small["seed"])
+    assert srv.wait(t, timeout=60)[0] == 0
+    assert ctx.memory_held()[0] <= budget
+    srv.close()
+
+
+def test_held_memory_stays_within_the_budget():
+    """Under a budget that holds about three requests, 24 requests submitted at once all
+    complete; the device memory the context holds by its own count never exceeds the budget while
+    they run, and the device's free memory drops by no more than the budget plus a small fixed
+    allowance for the runtime (graphs, streams, events)."""
+    p = gpu()
+    from paper_2204_03139_amd.serving import Server
+    say("[serving] held memory within the budget")
+    reqs = [_request(40 + k, n=20, T=3, Na=3000, Nb=3000) for k in range(24)]
+    need = max(Server.footprint(q["verts"], q["faces"], q["obs"], q["Na"]) for q in reqs)
+    budget = 3 * need + (2 << 20)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    srv = Server(hbm_budget_bytes=budget)
+    tickets = [srv.submit(q["verts"], q["faces"], q["obs"], q["Na"], q["seed"]) for q in reqs]
+    peak = 0
+    pending = set(tickets)
+    while pending:
+        peak = max(peak, srv.ctx.memory_held()[0])
+        for t in list(pending):
+            st = srv.poll(t)
+            if st != 1:
+                assert srv.take(t, st)[0] == 0
+                pending.discard(t)
+    free1 = torch.cuda.mem_get_info()[0]
+    say(f"[serving] budget {budget} peak held {peak} device free drop {free0 - free1}")
+    assert 0 < peak <= budget
+    assert free0 - free1 <= budget + (64 << 20)
     srv.close()
 
 
