@@ -119,6 +119,21 @@ int dc_sample_surface_masked(dc_ctx *ctx, const float *verts, const int32_t *fac
                              const uint8_t *face_mask, int mask_per_frame, float *points,
                              int32_t *face_idx, float *bary, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): dc_sample_surface with the same arguments, arithmetic,
+ * results and errors, except that its scratch - the per-frame area CDF in double and the last
+ * drawable face of each frame, T*F*8 + T*4 bytes, each part rounded up to 256 - lives in a static
+ * device array of 16 MiB per GPU instead of the context's scratch, so the call allocates nothing
+ * (the context's own memory is untouched).  The array exists on every GPU the library runs on and
+ * is held until the process ends.  T and F whose scratch exceeds 16 MiB (T*F above about 2.09
+ * million; 100 frames of 19,602 faces fit) give DC_ERR_UNSUPPORTED.  Every call on one GPU shares
+ * its array, which keeps the last call's contents: calls whose device work overlaps (on different
+ * streams, or from different contexts of the same GPU) race, so order them on one stream or with
+ * events. */
+int dc_sample_surface_noalloc(dc_ctx *ctx, const float *verts, const int32_t *faces, int T, int V,
+                              int F, int N, uint64_t seed, const uint32_t *uniforms,
+                              float *points, int32_t *face_idx, float *bary, void *stream);
+
 /* Backward of dc_sample_surface through Eq. 4 (dx_i/dp_{i,c} = bary_c(i) I):
  *   grad_verts[t,v] = sum over points i of frame t and corners c with faces[face_idx[t,i]][c]==v
  *                     of bary[t,i,c] * grad_points[t,i].

@@ -37,7 +37,8 @@ EXPORTS = ["dc_create", "dc_destroy", "dc_last_error", "dc_sync", "dc_sample_sur
            "dc_sample_surface_masked", "dc_rigid_pose", "dc_rigid_pose_bwd",
            "dc_sample_surface_bwd", "dc_chamfer_fwd", "dc_chamfer_bwd", "dc_get_stats",
            "dc_submit", "dc_poll", "dc_version", "dc_debug_fail_allocs", "dc_profile",
-           "dc_get_kernel_times", "dc_request_bytes", "dc_memory_held"]
+           "dc_get_kernel_times", "dc_request_bytes", "dc_memory_held",
+           "dc_sample_surface_noalloc"]
 
 
 class DCError(RuntimeError):
@@ -91,6 +92,7 @@ def load():
     L.dc_sync.argtypes = [vp, vp]
     L.dc_sample_surface.argtypes = [vp, vp, vp, i, i, i, i, u64, vp, vp, vp, vp, vp]
     L.dc_sample_surface_masked.argtypes = [vp, vp, vp, i, i, i, i, u64, vp, vp, i, vp, vp, vp, vp]
+    L.dc_sample_surface_noalloc.argtypes = [vp, vp, vp, i, i, i, i, u64, vp, vp, vp, vp, vp]
     L.dc_rigid_pose.argtypes = [vp, vp, vp, vp, i, i, i, vp, vp]
     L.dc_rigid_pose_bwd.argtypes = [vp, vp, vp, vp, vp, i, i, i, vp, vp]
     L.dc_sample_surface_bwd.argtypes = [vp, vp, vp, vp, vp, i, i, i, i, vp, vp]
@@ -233,6 +235,25 @@ def sample_surface(verts, faces, N: int, seed: int = 0, uniforms=None, out=None,
         rc = load().dc_sample_surface_masked(*ins, m, int(per_frame), *outs)
         _check(rc, "dc_sample_surface_masked")
     return points, face_idx, bary
+
+
+def sample_surface_noalloc(verts, faces, N: int, out, seed: int = 0, uniforms=None, ctx=None,
+                           stream=None):
+    """dc_sample_surface_noalloc: sampling into the caller's `out` = (points [T,N,3],
+    face_idx [T,N], bary [T,N,3]) with the library allocating nothing (its scratch is a static
+    device array); returns `out`."""
+    ctx = ctx or default_context(verts.device.index)
+    T, V, _ = verts.shape
+    F = faces.shape[0]
+    points, face_idx, bary = out
+    rc = load().dc_sample_surface_noalloc(
+        ctx.handle, _ptr(verts, torch.float32, (T, V, 3), "verts"),
+        _ptr(faces, torch.int32, (F, 3), "faces"), T, V, F, N, seed & (2**64 - 1),
+        _words_ptr(uniforms, (T, N, 4)), _ptr(points, torch.float32, (T, N, 3), "points"),
+        _ptr(face_idx, torch.int32, (T, N), "face_idx"),
+        _ptr(bary, torch.float32, (T, N, 3), "bary"), _stream(stream))
+    _check(rc, "dc_sample_surface_noalloc")
+    return out
 
 
 def sample_surface_bwd(grad_points, faces, face_idx, bary, V: int, out=None, ctx=None,

@@ -16,7 +16,7 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libdiffcloud.so")
 
 SOURCES = ["abi.hip", "sample.hip", "nn_exact.hip", "screen.hip", "segsort.hip", "backward.hip",
-           "rigid.hip", "scheduler.hip"]
+           "rigid.hip", "scheduler.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",

@@ -233,12 +233,13 @@ int dc_create(dc_ctx **out, int device, size_t hbm_budget_bytes, int max_slots) 
     if (e == hipSuccess) e = hipMemset(c->d_stats, 0, sizeof(unsigned long long) * 4);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->arena_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e != hipSuccess) {
+    const int rc = e == hipSuccess ? noalloc_init(device) : hip_fail(e, "dc_create");
+    if (rc != DC_OK) {
         (void)hipFree(c->d_status);
         (void)hipFree(c->d_stats);
         if (c->arena_ev) (void)hipEventDestroy(c->arena_ev);
         delete c;
-        return hip_fail(e, "dc_create");
+        return rc;
     }
     *out = c;
     return DC_OK;

@@ -168,6 +168,10 @@ void launch_rigid_bwd(const double *q, const float *p0, const int32_t *body_star
                       const float *grad_verts, int T, int B, int V, double *grad_q,
                       unsigned *status, hipStream_t s);
 
+// the allocation-free sampling entry point: look up its scratch address on `device` (once per
+// device, with that device current)
+int noalloc_init(int device);
+
 // composite enqueues shared by the direct calls and the serving loop
 // `prof` is the context whose profiling records the launches, or NULL
 int enqueue_sample(dc_ctx *prof, const float *verts, const int32_t *faces, int T, int V, int F,
