@@ -13,11 +13,17 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 
 CFLAGS = ["-O2", "-march=x86-64-v3", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
           "-fPIC", "-shared", "-std=c11"]
+# DC_ORACLE_SANITIZE=1 builds and loads a separate copy under AddressSanitizer and
+# UndefinedBehaviorSanitizer (host code only; the Python process must preload libasan)
+SANITIZE = os.environ.get("DC_ORACLE_SANITIZE") == "1"
+if SANITIZE:
+    CFLAGS = CFLAGS + ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                       "-fno-omit-frame-pointer", "-g"]
+_SO = os.path.join(_HERE, "liboracle_san.so" if SANITIZE else "liboracle.so")
 
 
 def build(force: bool = True) -> str:

@@ -9,10 +9,12 @@ Recipe (the simulator of the paper is not rebuilt; these trajectories stand in f
   + omega_k t) - sag * (t / (T-1)) * (1 - 4x^2)(1 - 4y^2), with amp_k = 0.05,
   kx, ky ~ U(-3, 3) cycles/m, phi ~ U(0, 2 pi), omega ~ U(0.05, 0.2) rad/frame.  |z| <= 0.27.
 * Observed cloud: the "perturbed" surface uses phi_k + U(-0.3, 0.3), amp_k * U(0.9, 1.1) and
-  sag * 1.2 (the single-frame workload uses the unperturbed mesh).  Points are drawn uniformly in
-  the (x, y) square, lifted onto the piecewise-linear mesh surface (a height-field lookup), then
-  moved by i.i.d. N(0, 0.005^2) noise per axis.  This is input data, generated here in float64
-  and handed to every consumer in float32.
+  sag * 1.2 (the single-frame workload uses the unperturbed mesh).  Points are spread uniformly
+  over the area of the piecewise-linear mesh surface by rejection in the (x, y) square: a uniform
+  (x, y) is kept with probability J / J_max, where J = sqrt(1 + z_x^2 + z_y^2) is the area element
+  of the grid triangle under it (its area over its projected area) and J_max the frame's largest,
+  then lifted onto the surface (a height-field lookup) and moved by i.i.d. N(0, 0.005^2) noise per
+  axis.  This is input data, generated here in float64 and handed to every consumer in float32.
 * Sampler words: four uint32 per (frame, point), drawn from numpy's generator.
 
 Every stream is seeded from (workload id, stream id), so inputs are reproducible.
@@ -111,8 +113,9 @@ def trajectory(n: int, T: int, cfg_id: int, sag: float = 0.1, extra: int = 0,
     return verts.astype(np.float32), faces
 
 
-def _lift_onto_grid(zgrid: np.ndarray, n: int, x: np.ndarray, y: np.ndarray):
-    """Height of the piecewise-linear grid surface at (x, y) (height-field lookup)."""
+def _grid_cell(zgrid: np.ndarray, n: int, x: np.ndarray, y: np.ndarray):
+    """Height of the piecewise-linear grid surface at (x, y) (height-field lookup) and the area
+    element sqrt(1 + z_x^2 + z_y^2) of the grid triangle under (x, y)."""
     gx = (x + 0.5) * (n - 1)
     gy = (y + 0.5) * (n - 1)
     i = np.clip(np.floor(gx).astype(np.int64), 0, n - 2)
@@ -127,7 +130,40 @@ def _lift_onto_grid(zgrid: np.ndarray, n: int, x: np.ndarray, y: np.ndarray):
     lower = s >= r
     z_lo = z00 + s * (z10 - z00) + r * (z11 - z10)
     z_up = z00 + r * (z01 - z00) + s * (z11 - z01)
-    return np.where(lower, z_lo, z_up)
+    # slopes in metres per metre: one grid step is 1 / (n - 1)
+    zx = np.where(lower, z10 - z00, z11 - z01) * (n - 1)
+    zy = np.where(lower, z11 - z10, z01 - z00) * (n - 1)
+    return np.where(lower, z_lo, z_up), np.sqrt(1.0 + zx * zx + zy * zy)
+
+
+def _area_element_max(zgrid: np.ndarray, n: int) -> float:
+    """Largest area element over all triangles of the grid surface."""
+    z00, z10 = zgrid[:-1, :-1], zgrid[:-1, 1:]
+    z01, z11 = zgrid[1:, :-1], zgrid[1:, 1:]
+    lo = (z10 - z00) ** 2 + (z11 - z10) ** 2
+    up = (z11 - z01) ** 2 + (z01 - z00) ** 2
+    return float(np.sqrt(1.0 + max(lo.max(), up.max()) * (n - 1) ** 2))
+
+
+def _surface_uniform_xy(rxy: np.random.Generator, zgrid: np.ndarray, n: int, count: int):
+    """`count` points spread uniformly over the area of the grid surface: uniform (x, y) kept
+    with probability J / J_max (rejection), in the order they are drawn; returns x, y, z."""
+    jmax = _area_element_max(zgrid, n)
+    xs, ys, zs = [], [], []
+    have = 0
+    while have < count:
+        m = max(1024, int((count - have) * 1.25 * jmax))
+        x = rxy.uniform(-0.5, 0.5, m)
+        y = rxy.uniform(-0.5, 0.5, m)
+        keep_u = rxy.uniform(0.0, 1.0, m)
+        z, jac = _grid_cell(zgrid, n, x, y)
+        keep = keep_u * jmax < jac
+        xs.append(x[keep])
+        ys.append(y[keep])
+        zs.append(z[keep])
+        have += int(keep.sum())
+    return (np.concatenate(xs)[:count], np.concatenate(ys)[:count],
+            np.concatenate(zs)[:count])
 
 
 def observed_cloud(n: int, T: int, Nb: int, cfg_id: int, sag: float = 0.1,
@@ -139,9 +175,7 @@ def observed_cloud(n: int, T: int, Nb: int, cfg_id: int, sag: float = 0.1,
     out = np.empty((T, Nb, 3), dtype=np.float64)
     for t in range(T):
         zgrid = verts[t, :, 2].astype(np.float64).reshape(n, n)
-        x = rxy.uniform(-0.5, 0.5, Nb)
-        y = rxy.uniform(-0.5, 0.5, Nb)
-        z = _lift_onto_grid(zgrid, n, x, y)
+        x, y, z = _surface_uniform_xy(rxy, zgrid, n, Nb)
         out[t, :, 0] = x
         out[t, :, 1] = y
         out[t, :, 2] = z
