@@ -162,7 +162,8 @@ int enqueue_sample(dc_ctx *prof, const float *verts, const int32_t *faces, int T
 
 size_t chamfer_fwd_scratch_bytes(int T, int Na, int Nb, int precision) {
     if (precision == DC_PREC_BF16_REFINE) return screen_scratch_bytes(T, Na, Nb);
-    return std::max(nn_exact_scratch_bytes(T, Na, Nb), nn_exact_scratch_bytes(T, Nb, Na));
+    return std::max({nn_exact_scratch_bytes(T, Na, Nb), nn_exact_scratch_bytes(T, Nb, Na),
+                     nn_bidir_scratch_bytes(T, Na, Nb)});
 }
 
 int enqueue_chamfer_fwd(dc_ctx *prof, const float *a, const float *b, int T, int Na, int Nb,
@@ -174,13 +175,21 @@ int enqueue_chamfer_fwd(dc_ctx *prof, const float *a, const float *b, int T, int
         launch_chamfer_screened(a, Na, b, Nb, T, idx_a, dist_a, idx_b, dist_b, scratch, stats,
                                 prof, s);
     } else {
-        {
-            ProfScope ps(prof, 0, s);
-            launch_nn_exact_ws(a, Na, b, Nb, T, idx_a, dist_a, scratch, s);
-        }
+        // both directions: one pass over the pairs when the frames are large enough
+        bool done = false;
         if (idx_b) {
             ProfScope ps(prof, 0, s);
-            launch_nn_exact_ws(b, Nb, a, Na, T, idx_b, dist_b, scratch, s);
+            done = launch_nn_bidir(a, Na, b, Nb, T, idx_a, dist_a, idx_b, dist_b, scratch, s);
+        }
+        if (!done) {
+            {
+                ProfScope ps(prof, 0, s);
+                launch_nn_exact_ws(a, Na, b, Nb, T, idx_a, dist_a, scratch, s);
+            }
+            if (idx_b) {
+                ProfScope ps(prof, 0, s);
+                launch_nn_exact_ws(b, Nb, a, Na, T, idx_b, dist_b, scratch, s);
+            }
         }
     }
     launch_loss(dist_a, dist_b, T, Na, Nb, reduction, frame_w, loss, s);

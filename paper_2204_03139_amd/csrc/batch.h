@@ -82,6 +82,9 @@ enum KernelType : int {
     KT_BOUNDS,
     KT_FACE_GRAD,
     KT_VERTEX_GRAD,
+    KT_BIDIR8,
+    KT_BIDIR4,
+    KT_BIDIR_MERGE,
     KT_COUNT
 };
 

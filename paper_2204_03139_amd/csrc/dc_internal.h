@@ -124,6 +124,11 @@ void launch_sample(const float *verts, const int32_t *faces, int T, int V, int F
 size_t nn_exact_scratch_bytes(int T, int Nq, int Np);
 void launch_nn_exact_ws(const float *Q, int Nq, const float *P, int Np, int T, int32_t *idx,
                         float *dist, char *scratch, hipStream_t st);
+// both directions in one pass (each pair evaluated once), when the frames have enough rows to
+// fill the chip; false (nothing launched) otherwise
+size_t nn_bidir_scratch_bytes(int T, int Na, int Nb);
+bool launch_nn_bidir(const float *A, int Na, const float *B, int Nb, int T, int32_t *idx_a,
+                     float *dist_a, int32_t *idx_b, float *dist_b, char *scratch, hipStream_t st);
 // the same search restricted, per frame t, to the rows qlist[t*Nq + k], k < qcount[t]
 size_t nn_exact_list_scratch_bytes(int T, int Nq, int Np);
 void launch_nn_exact_list(const float *Q, int Nq, const float *P, int Np, int T,

@@ -10,6 +10,15 @@
 // index among the exact ties, so the result is the exact argmin with the smallest-index rule.
 // Large frames split the target range over grid.z slices; a merge kernel combines the slices in
 // slice order with the same strict-less rule.
+//
+// k_nn_bidir: both directions in one pass, each pair's canonical distance evaluated once.  A lane
+// owns BD_QPT consecutive rows of a; targets b stream through LDS.  Rows keep k_nn_exact's
+// sub-tile minima (and its rescan); for the columns each lane folds its rows into one value per
+// target, the lanes' values of a 64-target block meet in LDS, and four lanes per target reduce
+// them to the workgroup's (minimum, first lane reaching it), written as one 64-bit key (distance
+// bits, lane).  k_bidir_merge takes the smallest key over the workgroups of a frame (the smallest
+// distance, then the first lane in row order) and evaluates that lane's rows again for the first
+// one whose distance equals the minimum: the exact argmin with the smallest-index rule.
 #include "batch.h"
 
 namespace dc {
@@ -337,7 +346,251 @@ __device__ __forceinline__ void loss_body(const LossParams &p, const Blk &blk) {
 
 __global__ __launch_bounds__(LOSS_THREADS) void k_loss(LossParams p) { loss_body(p, grid_blk()); }
 
+// ---------------------------------------------------------------- one pass, both directions
+constexpr int BD_THREADS = 256;
+constexpr int BD_TILE = 256;    // targets staged in LDS per step
+constexpr int BD_SUB = 64;      // targets per column block = the rows' sub-tile
+constexpr int BD_PITCH = BD_SUB + 4;             // a lane's block of column values, padded
+constexpr int BD_WAVE_SKEW = 16;                 // per-wave offset: the four waves' values of one
+constexpr int BD_WAVE_STRIDE = 64 * BD_PITCH + BD_WAVE_SKEW;  // target fall in distinct banks
+
+struct BidirParams {
+    const float *A;  // rows [T,Na,3]
+    const float *B;  // targets [T,Nb,3]
+    int32_t *idx_a;
+    float *dist_a;
+    unsigned long long *colkey;  // [T][row blocks][Nb]: (distance bits << 32) | global lane
+    int Na, Nb;
+};
+
+template <int QPT>
+__device__ __forceinline__ void bidir_body(const BidirParams &pr, const Blk &blk) {
+    constexpr int ROWS = BD_THREADS * QPT;
+    const float *__restrict__ A = pr.A;
+    const float *__restrict__ B = pr.B;
+    const int Na = pr.Na, Nb = pr.Nb;
+    __shared__ float4 tile[BD_TILE];
+    __shared__ __align__(16) float colbuf[4 * BD_WAVE_STRIDE];
+    const int t = blk.y, wg = blk.x, nwg = blk.gx;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const float *At = A + (size_t)t * Na * 3;
+    const float *Bt = B + (size_t)t * Nb * 3;
+    const int glane = wg * BD_THREADS + (int)threadIdx.x;  // lanes in row order over the frame
+    const int r0 = glane * QPT;
+    const float nan = __builtin_nanf("");
+    // rows past Na are NaN: their distances never win a minimum in either direction
+    float qx[QPT], qy[QPT], qz[QPT], best[QPT];
+    int bsub[QPT];
+#pragma unroll
+    for (int k = 0; k < QPT; ++k) {
+        const bool ok = r0 + k < Na;
+        const float *q = At + 3 * (size_t)(ok ? r0 + k : 0);
+        qx[k] = ok ? q[0] : nan;
+        qy[k] = ok ? q[1] : nan;
+        qz[k] = ok ? q[2] : nan;
+        best[k] = __builtin_inff();
+        bsub[k] = 0;
+    }
+    float *mycol = colbuf + wave * BD_WAVE_STRIDE + lane * BD_PITCH;
+    // column reduction: four lanes per target, lane `part` scanning the 64 lanes of wave `part`
+    const int jr = threadIdx.x >> 2, part = threadIdx.x & 3;
+    const float *rdcol = colbuf + part * BD_WAVE_STRIDE + (jr & (BD_SUB - 1));
+    unsigned long long *keyrow = pr.colkey + ((size_t)t * nwg + wg) * Nb;
+    for (int base = 0; base < Nb; base += BD_TILE) {
+        const int n = min(BD_TILE, Nb - base);
+        __syncthreads();  // the previous tile is no longer read
+        for (int j = threadIdx.x; j < BD_TILE; j += BD_THREADS) {
+            float4 v = make_float4(nan, nan, nan, 0.f);  // padding targets: NaN distances
+            if (j < n) {
+                const float *p = Bt + 3 * (size_t)(base + j);
+                v = make_float4(p[0], p[1], p[2], 0.f);
+            }
+            tile[j] = v;
+        }
+        for (int s0 = 0; s0 < n; s0 += BD_SUB) {
+            __syncthreads();  // the tile is staged / the previous block's values were reduced
+            float m[QPT];
+#pragma unroll
+            for (int k = 0; k < QPT; ++k) m[k] = __builtin_inff();
+#pragma unroll 2
+            for (int jj = 0; jj < BD_SUB; jj += 4) {
+                const float4 p0 = tile[s0 + jj], p1 = tile[s0 + jj + 1];
+                const float4 p2 = tile[s0 + jj + 2], p3 = tile[s0 + jj + 3];
+                float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
+#pragma unroll
+                for (int k = 0; k < QPT; ++k) {
+                    const float d0 = canon_d2(qx[k], qy[k], qz[k], p0.x, p0.y, p0.z);
+                    const float d1 = canon_d2(qx[k], qy[k], qz[k], p1.x, p1.y, p1.z);
+                    const float d2 = canon_d2(qx[k], qy[k], qz[k], p2.x, p2.y, p2.z);
+                    const float d3 = canon_d2(qx[k], qy[k], qz[k], p3.x, p3.y, p3.z);
+                    m[k] = __builtin_fminf(__builtin_fminf(m[k], d0), d1);
+                    m[k] = __builtin_fminf(__builtin_fminf(m[k], d2), d3);
+                    c0 = k ? __builtin_fminf(c0, d0) : d0;
+                    c1 = k ? __builtin_fminf(c1, d1) : d1;
+                    c2 = k ? __builtin_fminf(c2, d2) : d2;
+                    c3 = k ? __builtin_fminf(c3, d3) : d3;
+                }
+                *reinterpret_cast<float4 *>(mycol + jj) = make_float4(c0, c1, c2, c3);
+            }
+            // rows: the first sub-tile with a strictly smaller minimum is remembered
+#pragma unroll
+            for (int k = 0; k < QPT; ++k)
+                if (m[k] < best[k]) {
+                    best[k] = m[k];
+                    bsub[k] = base + s0;
+                }
+            __syncthreads();  // the block's column values are complete
+            // columns: the smallest value over the 64 lanes of wave `part`, the first lane on ties
+            float v = __builtin_inff();
+            int vl = 0;
+#pragma unroll 8
+            for (int l = 0; l < 64; ++l) {
+                const float x = rdcol[l * BD_PITCH];
+                if (x < v) {
+                    v = x;
+                    vl = l;
+                }
+            }
+            unsigned long long key = ((unsigned long long)__float_as_uint(v) << 32) |
+                                     (unsigned)(wg * BD_THREADS + part * 64 + vl);
+#pragma unroll
+            for (int off = 1; off < 4; off <<= 1) {
+                const unsigned long long o = __shfl_xor(key, off, 64);
+                key = o < key ? o : key;
+            }
+            const int j = base + s0 + jr;
+            if (part == 0 && jr < BD_SUB && s0 + jr < n) keyrow[j] = key;
+        }
+    }
+    // rows: rescan the winning sub-tile for the first exact match
+#pragma unroll
+    for (int k = 0; k < QPT; ++k) {
+        const int r = r0 + k;
+        if (r >= Na) continue;
+        const int js = bsub[k];
+        const int je = min(js + BD_SUB, Nb);
+        int found = js;
+        for (int j = js; j < je; ++j) {
+            const float *p = Bt + 3 * (size_t)j;
+            if (canon_d2(qx[k], qy[k], qz[k], p[0], p[1], p[2]) == best[k]) {
+                found = j;
+                break;
+            }
+        }
+        pr.idx_a[(size_t)t * Na + r] = found;
+        pr.dist_a[(size_t)t * Na + r] = best[k];
+    }
+}
+
+template <int QPT>
+__global__ __launch_bounds__(BD_THREADS) void k_nn_bidir(BidirParams p) {
+    bidir_body<QPT>(p, grid_blk_xcd());
+}
+
+// Columns: the smallest key over a frame's row blocks gives the minimum and the first lane (in
+// row order) reaching it; that lane's rows are evaluated again for the first one whose distance
+// equals it.  When no distance is below infinity the result follows k_nn_exact: the first row of
+// the first 64-row sub-tile at an infinite distance, or row 0.
+struct BidirMergeParams {
+    const float *A;
+    const float *B;
+    const unsigned long long *colkey;
+    int32_t *idx_b;
+    float *dist_b;
+    int Na, Nb, nwg, qpt;
+};
+
+constexpr int BM_THREADS = 256;
+
+__device__ __forceinline__ void bidir_merge_body(const BidirMergeParams &pr, const Blk &blk) {
+    const int t = blk.y;
+    const int j = blk.x * BM_THREADS + (int)threadIdx.x;
+    const int Na = pr.Na, Nb = pr.Nb, nwg = pr.nwg;
+    if (j >= Nb) return;
+    const unsigned long long *kp = pr.colkey + (size_t)t * nwg * Nb + j;
+    unsigned long long key = kp[0];
+    for (int w = 1; w < nwg; ++w) {
+        const unsigned long long o = kp[(size_t)w * Nb];
+        key = o < key ? o : key;
+    }
+    const float v = __uint_as_float((unsigned)(key >> 32));
+    const float *At = pr.A + (size_t)t * Na * 3;
+    const float *pb = pr.B + ((size_t)t * Nb + j) * 3;
+    const float bx = pb[0], by = pb[1], bz = pb[2];
+    int first, last;
+    if (v < __builtin_inff()) {
+        first = (int)(unsigned)key * pr.qpt;
+        last = min(first + pr.qpt, Na);
+    } else {
+        first = 0;
+        last = min(BD_SUB, Na);
+    }
+    int found = first < Na && v < __builtin_inff() ? first : 0;
+    for (int i = first; i < last; ++i) {
+        const float *a = At + 3 * (size_t)i;
+        if (canon_d2(a[0], a[1], a[2], bx, by, bz) == v) {
+            found = i;
+            break;
+        }
+    }
+    pr.idx_b[(size_t)t * Nb + j] = found;
+    pr.dist_b[(size_t)t * Nb + j] = v;
+}
+
+__global__ __launch_bounds__(BM_THREADS) void k_bidir_merge(BidirMergeParams p) {
+    bidir_merge_body(p, grid_blk_xcd());
+}
+
 }  // namespace
+
+// One pass for both directions pays when there are enough row blocks to fill the chip; smaller
+// problems use the two searches of k_nn_exact, which split targets over slices.
+static int bidir_qpt(int Na, int T) {
+    const long wg8 = (long)T * ((Na + BD_THREADS * 8 - 1) / (BD_THREADS * 8));
+    const long wg4 = (long)T * ((Na + BD_THREADS * 4 - 1) / (BD_THREADS * 4));
+    if (wg8 >= 1024) return 8;
+    if (wg4 >= 256) return 4;
+    return 0;
+}
+
+size_t nn_bidir_scratch_bytes(int T, int Na, int Nb) {
+    const int qpt = bidir_qpt(Na, T);
+    if (!qpt) return 0;
+    const size_t nwg = (size_t)(Na + BD_THREADS * qpt - 1) / (BD_THREADS * qpt);
+    return Arena::need((size_t)T * nwg * Nb, sizeof(unsigned long long));
+}
+
+bool launch_nn_bidir(const float *A, int Na, const float *B, int Nb, int T, int32_t *idx_a,
+                     float *dist_a, int32_t *idx_b, float *dist_b, char *scratch, hipStream_t st) {
+    const int qpt = bidir_qpt(Na, T);
+    if (!qpt) return false;
+    const int nwg = (Na + BD_THREADS * qpt - 1) / (BD_THREADS * qpt);
+    BidirParams bp;
+    bp.A = A;
+    bp.B = B;
+    bp.idx_a = idx_a;
+    bp.dist_a = dist_a;
+    bp.colkey = reinterpret_cast<unsigned long long *>(scratch);
+    bp.Na = Na;
+    bp.Nb = Nb;
+    if (qpt == 8)
+        dispatch(KT_BIDIR8, k_nn_bidir<8>, dim3(nwg, T), BD_THREADS, bp, st);
+    else
+        dispatch(KT_BIDIR4, k_nn_bidir<4>, dim3(nwg, T), BD_THREADS, bp, st);
+    BidirMergeParams mp;
+    mp.A = A;
+    mp.B = B;
+    mp.colkey = bp.colkey;
+    mp.idx_b = idx_b;
+    mp.dist_b = dist_b;
+    mp.Na = Na;
+    mp.Nb = Nb;
+    mp.nwg = nwg;
+    mp.qpt = qpt;
+    dispatch(KT_BIDIR_MERGE, k_bidir_merge, dim3((Nb + BM_THREADS - 1) / BM_THREADS, T),
+             BM_THREADS, mp, st);
+    return true;
+}
 
 // scratch for the slice partials (0 when no slicing is needed)
 static int nn_slices(int Nq, int Np, int T, int qpt) {
@@ -457,6 +710,9 @@ void register_nn_kernels(BatchedKernel *table) {
     table[KT_NN8] = batched_kernel<NNParams, nn_exact_body<8>, NN_THREADS, 1024>();
     table[KT_NN_MERGE] = batched_kernel<NNMergeParams, nn_merge_body, MERGE_THREADS, 512>();
     table[KT_LOSS] = batched_kernel<LossParams, loss_body, LOSS_THREADS, 256>();
+    table[KT_BIDIR8] = batched_kernel<BidirParams, bidir_body<8>, BD_THREADS, 512>();
+    table[KT_BIDIR4] = batched_kernel<BidirParams, bidir_body<4>, BD_THREADS, 512>();
+    table[KT_BIDIR_MERGE] = batched_kernel<BidirMergeParams, bidir_merge_body, BM_THREADS, 1024>();
 }
 
 }  // namespace dc

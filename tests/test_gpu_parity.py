@@ -344,6 +344,46 @@ def test_non_finite_points_follow_the_exhaustive_path():
             assert g1[k].min() >= 0 and g1[k].max() < n
 
 
+def _many_frames(seed, T, Na, Nb, bad=False):
+    """T frames with exact ties (duplicated targets and rows) and, with `bad`, rows and targets at
+    NaN or at distances whose square overflows in a few frames."""
+    r = np.random.default_rng(seed)
+    A = r.uniform(-.5, .5, (T, Na, 3)).astype(np.float32)
+    B = r.uniform(-.5, .5, (T, Nb, 3)).astype(np.float32)
+    B[:, Nb // 2: Nb // 2 + 40] = B[:, :40]          # duplicated targets: row ties
+    A[:, Na // 3: Na // 3 + 40] = A[:, 5:45]         # duplicated rows: column ties
+    if bad:
+        for t in r.choice(T, 8, replace=False):
+            A[t, r.choice(Na, 3, replace=False)] = np.nan
+            A[t, r.choice(Na, 2, replace=False), 1] = 4e30
+            B[t, r.choice(Nb, 3, replace=False), 2] = np.nan
+            B[t, r.choice(Nb, 2, replace=False)] = -3e30
+        A[T - 1] = np.nan                            # a frame of NaN rows only
+        B[T - 2, :, 0] = 5e30                        # a frame whose targets are all overflowing
+    return A, B
+
+
+@pytest.mark.parametrize("shape", [(300, 1000, 777), (260, 2300, 5000), (1100, 2048, 300)])
+def test_one_pass_both_directions(shape):
+    """Many frames (the fp32 path then searches both directions in one pass over the pairs): equal
+    to the oracle element by element, and, with NaN and overflowing points added, bit for bit equal
+    to the two single-direction searches that smaller calls of the same frames use."""
+    p = gpu()
+    T, Na, Nb = shape
+    say(f"[chamfer] one pass both directions T={T} Na={Na} Nb={Nb}")
+    A, B = _many_frames(7 + T, T, Na, Nb)
+    g, o = _chamfer_both(p, A, B, precision=0)
+    _check_chamfer(g, o)
+    A, B = _many_frames(8 + T, T, Na, Nb, bad=True)
+    whole = {k: host(v) for k, v in p.chamfer_fwd(dev(A), dev(B), precision=0).items()}
+    torch.cuda.synchronize()
+    for t in sorted({0, T - 2, T - 1} | set(range(1, T, max(1, T // 12)))):
+        part = {k: host(v) for k, v in
+                p.chamfer_fwd(dev(A[t:t + 1]), dev(B[t:t + 1]), precision=0).items()}
+        for k in ("idx_a", "idx_b", "dist_a", "dist_b"):
+            assert np.array_equal(whole[k][t].view(np.uint32), part[k][0].view(np.uint32)), (t, k)
+
+
 @pytest.mark.parametrize("reduction", [0, 1])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_loss_reductions_and_weights(reduction, precision):
