@@ -16,6 +16,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import struct
 import sys
 import time
 
@@ -30,22 +31,66 @@ CUS, SIMDS_PER_CU, PEAK_CLOCK_HZ = 256, 4, 2.4e9
 # VALU-issue ceiling of the screen's design: per 16x16 result tile (256 pairs) one MFMA issue plus
 # four v_min3 (two values folded per instruction and direction), 4 cycles each per wave64 on a SIMD
 SCREEN_ISSUE_CEILING = CUS * SIMDS_PER_CU * PEAK_CLOCK_HZ / (5 * 4) * 256
-# HBM bytes of one k_screen launch on this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled
-# by a plain-copy calibration (profiles/k_screen_grid100_65536pts_100frames_counters.md); valid
-# only for the screen source they were measured on.
-SCREEN_TRAFFIC = dict(source_sha256="e4a750a077ab8e88af008c2926d0a9b0c57734e31dbecfde6d19a8bfc011e2e1",
-                      bytes=2290113415 + 3571933520)
+# HBM bytes of one k_screen<true> launch on this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# scaled by a plain-copy calibration (profiles/k_screen_grid100_65536pts_100frames_counters.md);
+# valid only for the machine code they were measured on (sha256 of the kernel's bytes in the
+# built library's gfx950 code object).
+SCREEN_SYMBOL = "_ZN2dc12_GLOBAL__N_18k_screenILb1EEEvNS0_12ScreenParamsE"
+SCREEN_TRAFFIC = dict(code_sha256="0ae043d4b324d96073aa4268471a3da68b5f4c49f41313217d634f6aeb47f66f",
+                      bytes=1117925 * 1024 * 2 + 3488129 * 1024)
+LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2204_03139_amd",
+                   "libdiffcloud.so")
+
+
+def kernel_code_sha256(lib_path: str, symbol: str):
+    """(sha256, size) of a kernel's machine code in the gfx950 code objects the library embeds
+    (clang offload bundles in .hip_fatbin: an ELF per bundle, the kernel a symbol of its .text)."""
+    import hashlib
+    data = open(lib_path, "rb").read()
+    magic = b"__CLANG_OFFLOAD_BUNDLE__"
+    pos = 0
+    while True:
+        i = data.find(magic, pos)
+        if i < 0:
+            return None
+        pos = i + len(magic)
+        (n,) = struct.unpack_from("<Q", data, i + 24)
+        o = i + 32
+        for _ in range(n):
+            eoff, esize, tlen = struct.unpack_from("<QQQ", data, o)
+            o += 24
+            triple = data[o:o + tlen].decode()
+            o += tlen
+            if not triple.endswith("gfx950") or esize == 0:
+                continue
+            elf = data[i + eoff:i + eoff + esize]
+            (shoff,) = struct.unpack_from("<Q", elf, 0x28)
+            shentsize, shnum = struct.unpack_from("<HH", elf, 0x3A)
+            secs = [struct.unpack_from("<IIQQQQIIQQ", elf, shoff + k * shentsize)
+                    for k in range(shnum)]
+            for sec in secs:
+                if sec[1] != 2:  # SHT_SYMTAB
+                    continue
+                strtab = secs[sec[6]]
+                for k in range(sec[5] // 24):
+                    name, _, _, shndx, value, size = struct.unpack_from("<IBBHQQ", elf,
+                                                                        sec[4] + 24 * k)
+                    start = strtab[4] + name
+                    if elf[start:elf.index(b"\0", start)].decode() != symbol or not size:
+                        continue
+                    text = secs[shndx]
+                    off = text[4] + (value - text[3])
+                    return hashlib.sha256(elf[off:off + size]).hexdigest(), size
 
 
 def _screen_traffic():
-    import hashlib
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2204_03139_amd", "csrc",
-                       "screen.hip")
     try:
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    except OSError:
+        h = kernel_code_sha256(LIB, SCREEN_SYMBOL)
+    except (OSError, ValueError, struct.error):
         return None
-    return SCREEN_TRAFFIC["bytes"] if h == SCREEN_TRAFFIC["source_sha256"] else None
+    if h is None or SCREEN_TRAFFIC["code_sha256"] is None:
+        return None
+    return SCREEN_TRAFFIC["bytes"] if h[0] == SCREEN_TRAFFIC["code_sha256"] else None
 
 
 def _args():
@@ -56,7 +101,10 @@ def _args():
     ap.add_argument("--workload", type=int, default=4, choices=[1, 2, 4])
     ap.add_argument("--precision", choices=["fp32", "bf16", "both"], default="both")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="target CPU time of the oracle baseline sample (0 disables it)")
+                    help="target all-core time of the oracle baseline sample of the headline "
+                         "workload (0 disables the CPU baseline)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the GPU legs of the single-frame and 40-frame workloads")
     ap.add_argument("--frames", type=int, default=None, help="override the frame count")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving leg (256 Poisson requests, p50/p99 latency)")
@@ -123,42 +171,93 @@ def run_path(p, torch, w, precision, steps, warmup, reduction=0):
     return ms, kt, stats, loss, outs
 
 
-def cpu_baseline(w, seconds, gpu=None):
-    """Time the oracle (as it stands) on a bounded sample of the workload: whole frames in order
-    (sampling, both nearest-neighbour directions searched exhaustively, the gradient formulas)
-    until about `seconds` of wall time; report point pairs per second.  Afterwards (untimed) the
-    GPU results of the reported path on the same frames are compared with the oracle's: points
-    and neighbour indices exactly, distances and losses against the double-precision twins,
-    vertex gradients relative to the sum of absolute contributions."""
+def _oracle_frame(oracle, w, t, nthreads=0):
+    """The oracle's whole path on frame t: sampling (Philox words of (seed, t)), exhaustive
+    nearest neighbours both ways, the Eq. 1 gradient to the points and to the vertices."""
+    faces, Na = w["faces"], w["Na"]
+    pts, fi, ba = oracle.sample_surface(w["verts"][t:t + 1], faces, Na,
+                                        words=_frame_words(oracle, w["seed"], t, Na))
+    ch = oracle.chamfer(pts, w["observed"][t:t + 1], nthreads=nthreads)
+    g = oracle.chamfer_grad(pts, w["observed"][t:t + 1], ch["idx_a"], ch["idx_b"])
+    oracle.sample_grad(g["ga"], faces, fi, ba, w["V"])
+    return pts, fi, ba, ch, g
+
+
+def _time_oracle(oracle, w, frames, nthreads):
+    t0 = time.perf_counter()
+    for t in frames:
+        _oracle_frame(oracle, w, t, nthreads)
+    dt = time.perf_counter() - t0
+    return float(len(frames)) * w["Na"] * w["Nb"] / dt, dt
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, seconds, gpu=None, gpu_eq2=None):
+    """Time the oracle (as it stands) on host cores.  Headline value: all cores on whole frames of
+    the headline workload in order (sampling, both nearest-neighbour directions searched
+    exhaustively, the gradient formulas) until about `seconds`; beside it one frame on one
+    thread, and the single-frame, 40-frame and 4-frame workloads in full on one thread and on all
+    cores.  Afterwards (untimed) the GPU results on the headline frames are compared with the
+    oracle's: points and neighbour indices exactly, distances and losses against the
+    double-precision twins, vertex gradients relative to the sum of absolute contributions; the
+    same for the unidirectional (Eq. 2) leg's outputs."""
     import oracle
+    from workloads import gen
     threads = oracle.max_threads()
-    faces = w["faces"]
-    Na, Nb = w["Na"], w["Nb"]
     pairs = 0.0
-    frames = 0
     kept = []
     t0 = time.perf_counter()
     for t in range(w["T"]):
-        pts, fi, ba = oracle.sample_surface(w["verts"][t:t + 1], faces, Na,
-                                            words=_frame_words(oracle, w["seed"], t, Na))
-        ch = oracle.chamfer(pts, w["observed"][t:t + 1])
-        g = oracle.chamfer_grad(pts, w["observed"][t:t + 1], ch["idx_a"], ch["idx_b"])
-        oracle.sample_grad(g["ga"], faces, fi, ba, w["V"])
-        pairs += float(Na) * Nb
-        frames += 1
-        kept.append((pts, fi, ba, ch, g))
+        kept.append(_oracle_frame(oracle, w, t))
+        pairs += float(w["Na"]) * w["Nb"]
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
+    frames = len(kept)
+    single, single_dt = _time_oracle(oracle, w, [frames], 1)
+    full = {}
+    for cfg in (1, 2, 3):
+        wc = gen.workload(cfg)
+        allc, allc_dt = _time_oracle(oracle, wc, range(wc["T"]), 0)
+        one, one_dt = _time_oracle(oracle, wc, range(wc["T"]), 1)
+        full[str(cfg)] = dict(workload=wc["name"], pairs=float(wc["T"]) * wc["Na"] * wc["Nb"],
+                              all_core_pairs_per_s=allc, all_core_s=allc_dt,
+                              single_thread_pairs_per_s=one, single_thread_s=one_dt)
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
     base = dict(value=pairs / dt, unit="point-pairs/s", cores=threads, kind="oracle",
-                sample=f"the first {frames} of {w['T']} frames of the workload, each fully "
-                       f"processed (sampling, exhaustive nearest neighbours both ways, gradients): "
-                       f"{pairs:.3e} pairs in {dt:.1f} s on {threads} threads")
+                sample=f"all cores: the first {frames} of {w['T']} frames of the headline "
+                       f"workload, each fully processed (sampling, exhaustive nearest neighbours "
+                       f"both ways, gradients): {pairs:.3e} pairs in {dt:.1f} s on {threads} "
+                       f"threads",
+                single_thread_value=single,
+                single_thread_sample=f"frame {frames} of the headline workload on one thread "
+                                     f"({float(w['Na']) * w['Nb']:.3e} pairs in "
+                                     f"{single_dt:.1f} s)",
+                nproc=nproc, cpu_model=_cpu_model(), full_workloads=full)
     if gpu is None:
         return base, None
     h = {k: v[:frames].cpu().numpy() for k, v in gpu.items() if v is not None}
     acc = dict(frames=frames, point_mismatches=0, idx_a_mismatches=0, idx_b_mismatches=0,
                dist_max_rel_err_vs_f64=0.0, loss_max_rel_err=0.0, grad_max_err_rel_to_abs_sum=0.0)
+    acc2 = None
+    h2 = None
+    if gpu_eq2 is not None:
+        h2 = {k: v[:frames].cpu().numpy() for k, v in gpu_eq2.items() if v is not None}
+        acc2 = dict(frames=frames, idx_a_mismatches=0, dist_a_bit_mismatches=0,
+                    dist_max_rel_err_vs_f64=0.0, loss_max_rel_err=0.0,
+                    grad_max_err_rel_to_abs_sum=0.0)
     for t, (pts, fi, ba, ch, g) in enumerate(kept):
         acc["point_mismatches"] += int((h["points"][t].view(np.uint32)
                                         != pts[0].view(np.uint32)).any(axis=-1).sum())
@@ -170,16 +269,54 @@ def cpu_baseline(w, seconds, gpu=None):
             acc["dist_max_rel_err_vs_f64"] = max(acc["dist_max_rel_err_vs_f64"], float(rel.max()))
         acc["loss_max_rel_err"] = max(acc["loss_max_rel_err"],
                                       float(abs(h["loss"][t] - ch["loss"][0]) / ch["loss"][0]))
-        gv, gva = oracle.sample_grad(g["ga"], faces, fi, ba, w["V"], g["ga_abs"])
+        gv, gva = oracle.sample_grad(g["ga"], w["faces"], fi, ba, w["V"], g["ga_abs"])
         err = np.abs(h["grad_verts"][t] - gv[0]) / np.maximum(gva[0], 1e-300)
         acc["grad_max_err_rel_to_abs_sum"] = max(acc["grad_max_err_rel_to_abs_sum"],
                                                  float(err.max()))
+        if h2 is None:
+            continue
+        # Eq. 2: the same neighbours a -> b; the loss is the plain sum, the gradient goes
+        # through idx_a only
+        acc2["idx_a_mismatches"] += int((h2["idx_a"][t] != ch["idx_a"][0]).sum())
+        acc2["dist_a_bit_mismatches"] += int((h2["dist_a"][t].view(np.uint32)
+                                              != ch["d32a"][0].view(np.uint32)).sum())
+        nz = ch["d64a"][0] > 0
+        rel = np.abs(h2["dist_a"][t][nz] - ch["d64a"][0][nz]) / ch["d64a"][0][nz]
+        acc2["dist_max_rel_err_vs_f64"] = max(acc2["dist_max_rel_err_vs_f64"], float(rel.max()))
+        loss2 = float(np.sum(ch["d64a"][0]))
+        acc2["loss_max_rel_err"] = max(acc2["loss_max_rel_err"],
+                                       abs(float(h2["loss"][t]) - loss2) / loss2)
+        g2 = oracle.chamfer_grad(pts, w["observed"][t:t + 1], ch["idx_a"], ch["idx_b"], 1)
+        gv2, gva2 = oracle.sample_grad(g2["ga"], w["faces"], fi, ba, w["V"], g2["ga_abs"])
+        err = np.abs(h2["grad_verts"][t] - gv2[0]) / np.maximum(gva2[0], 1e-300)
+        acc2["grad_max_err_rel_to_abs_sum"] = max(acc2["grad_max_err_rel_to_abs_sum"],
+                                                  float(err.max()))
+    if acc2 is not None:
+        acc["eq2"] = acc2
     return base, acc
 
 
 def _frame_words(oracle, seed, t, N):
     """Philox words of frame t alone (the generator is keyed by (seed, t, i))."""
     return oracle.words_from_seed(seed, t + 1, N)[t:t + 1]
+
+
+def run_config_legs(p, torch, steps, warmup):
+    """The single-frame (2,048 x 2,048 points) and 40-frame (8,192 x 8,192) workloads through the
+    same whole step (Eq. 1), in both precisions: ms per step and pairs per second."""
+    from workloads import gen
+    out = {}
+    for cfg in (1, 2):
+        w = gen.workload(cfg)
+        pairs = float(w["T"]) * w["Na"] * w["Nb"]
+        leg = dict(workload=w["name"], pairs_per_step=pairs)
+        for name, prec in (("fp32", 0), ("bf16_refine", 1)):
+            n = max(steps, 50) if cfg == 1 else steps
+            ms, kt, _, _, _ = run_path(p, torch, w, prec, n, warmup)
+            leg[name] = dict(ms_per_step=ms, pairs_per_s=pairs / (ms * 1e-3),
+                             kernel_ms={k: v[0] / n for k, v in kt.items()})
+        out[str(cfg)] = leg
+    return out
 
 
 def run_serving(p, torch, rate_hz=None, n_requests=None, budget_bytes=64 << 30, max_slots=64,
@@ -301,14 +438,13 @@ def main():
         try:
             ms, kt, stats, loss, outs = run_path(p, torch, w, prec, a.steps, a.warmup,
                                                  reduction=red)
-            if red == 0:
-                gpu_outs[name] = outs
+            gpu_outs[name] = outs
         except p.DCError as e:
             paths[name] = dict(error=str(e))
             continue
         nn_ms, nn_n = kt["all_pairs"]
-        # every all-pairs launch covers every pair of every frame: the fp32 path launches once
-        # per direction, the screen once for both directions
+        # every all-pairs launch covers every pair of every frame: the fp32 path launches its
+        # one-pass search (and its column merge) once, the screen once for both directions
         per_launch_pairs = pairs
         avg = nn_ms / max(nn_n, 1)
         paths[name] = dict(pairs_per_s=pairs / (ms * 1e-3), ms_per_step=ms,
@@ -332,18 +468,36 @@ def main():
                 frac=achieved / FP32_VECTOR_PEAK_TFLOPS, flops_per_pair=FLOPS_PER_PAIR)
     if best == "bf16_refine":
         mf = MFMA_FLOPS_PER_PAIR * pps / 1e12
+        code = kernel_code_sha256(LIB, SCREEN_SYMBOL)
         roof.update(traffic=_screen_traffic(),
-                    kernel="k_screen: bf16 matrix-core screen, both directions in one launch over "
-                           "all frames",
+                    traffic_key=dict(kernel_code_sha256=code[0] if code else None,
+                                     counters_taken_on=SCREEN_TRAFFIC["code_sha256"]),
+                    kernel="k_screen<true>: bf16 matrix-core screen, both directions in one "
+                           "launch over all frames",
                     launch_ms=bp["all_pairs_avg_launch_ms"],
+                    binding_unit=dict(
+                        unit="vector issue (one MFMA issue + four v_min3 per 256 pairs per SIMD, "
+                             "4 cycles each)",
+                        ceiling_pairs_per_s=SCREEN_ISSUE_CEILING, clock_ghz=PEAK_CLOCK_HZ / 1e9,
+                        frac=pps / SCREEN_ISSUE_CEILING),
                     issue_ceiling_pairs_per_s=SCREEN_ISSUE_CEILING,
                     frac_of_issue_ceiling=pps / SCREEN_ISSUE_CEILING,
                     mfma=dict(executed_flops_per_pair=MFMA_FLOPS_PER_PAIR, achieved=mf,
                               peak=BF16_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
                               frac=mf / BF16_MFMA_PEAK_TFLOPS))
+        eq2 = paths.get("bf16_refine_eq2")
+        if eq2 and "error" not in eq2 and eq2.get("all_pairs_pairs_per_s"):
+            # the rows-only screen of Eq. 2 is bound by the matrix pipe: one K=32 bf16 MFMA per
+            # 256 pairs, 64 executed flops per pair against the dense bf16 peak
+            e_mf = MFMA_FLOPS_PER_PAIR * eq2["all_pairs_pairs_per_s"] / 1e12
+            roof["eq2_screen"] = dict(kernel="k_screen<false>", bound="mfma", achieved=e_mf,
+                                      peak=BF16_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                                      frac=e_mf / BF16_MFMA_PEAK_TFLOPS,
+                                      launch_ms=eq2["all_pairs_avg_launch_ms"])
     else:
         roof.update(traffic=None,
-                    kernel="k_nn_exact: exact fp32 search, one direction over all frames",
+                    kernel="k_nn_bidir + k_bidir_merge: exact fp32 search, both directions in one "
+                           "pass over all frames",
                     launch_ms=bp["all_pairs_avg_launch_ms"])
     # the pair roofline: fp32 vector peak / 8 flops per pair, for the whole bidirectional step
     pair_peak = FP32_VECTOR_PEAK_TFLOPS * 1e12 / FLOPS_PER_PAIR
@@ -359,11 +513,13 @@ def main():
                            note="fp32 vector peak / 8 flops per pair; whole fwd+bwd step"),
         paths=paths,
     )
+    if not a.no_configs and a.workload == 4 and a.frames is None:
+        line["other_workloads"] = run_config_legs(p, torch, a.steps, a.warmup)
     if not a.no_serving:
         line["serving"] = run_serving(p, torch)
     if a.cpu_seconds > 0:
         line["cpu_baseline"], line["accuracy_vs_oracle"] = cpu_baseline(
-            w, a.cpu_seconds, {k: v for k, v in gpu_outs.items() if k == best}.get(best))
+            w, a.cpu_seconds, gpu_outs.get(best), gpu_outs.get(best + "_eq2"))
     print(json.dumps(line), flush=True)
 
 
