@@ -12,13 +12,17 @@
 // slice order with the same strict-less rule.
 //
 // k_nn_bidir: both directions in one pass, each pair's canonical distance evaluated once.  A lane
-// owns BD_QPT consecutive rows of a; targets b stream through LDS.  Rows keep k_nn_exact's
+// owns 8 (or 4) consecutive rows of a; targets b stream through LDS.  Rows keep k_nn_exact's
 // sub-tile minima (and its rescan); for the columns each lane folds its rows into one value per
-// target, the lanes' values of a 64-target block meet in LDS, and four lanes per target reduce
-// them to the workgroup's (minimum, first lane reaching it), written as one 64-bit key (distance
-// bits, lane).  k_bidir_merge takes the smallest key over the workgroups of a frame (the smallest
-// distance, then the first lane in row order) and evaluates that lane's rows again for the first
-// one whose distance equals the minimum: the exact argmin with the smallest-index rule.
+// target, each wave reads its lanes' values of a 16-target block back transposed from its own
+// LDS region and reduces them to (minimum, first lane reaching it) as one 64-bit key (distance
+// bits, lane), and an LDS atomic minimum combines the four waves.  k_bidir_merge takes the smallest
+// key over the row blocks of a frame (the smallest distance, then the first lane in row order) and
+// evaluates that lane's rows again for the first one whose distance equals the minimum: the exact
+// argmin with the smallest-index rule.  The targets may be split over slices, whose row results
+// merge in slice order like k_nn_exact's.
+#include <cmath>
+
 #include "batch.h"
 
 namespace dc {
@@ -348,36 +352,43 @@ __global__ __launch_bounds__(LOSS_THREADS) void k_loss(LossParams p) { loss_body
 
 // ---------------------------------------------------------------- one pass, both directions
 constexpr int BD_THREADS = 256;
-constexpr int BD_TILE = 256;    // targets staged in LDS per step
-constexpr int BD_SUB = 64;      // targets per column block = the rows' sub-tile
-constexpr int BD_PITCH = BD_SUB + 4;             // a lane's block of column values, padded
-constexpr int BD_WAVE_SKEW = 16;                 // per-wave offset: the four waves' values of one
-constexpr int BD_WAVE_STRIDE = 64 * BD_PITCH + BD_WAVE_SKEW;  // target fall in distinct banks
+constexpr int BD_TILE = 256;   // targets staged in LDS per step, one per thread
+constexpr int BD_SUB = 64;     // the rows' sub-tile, as in k_nn_exact
+constexpr int BD_BLK = 16;     // targets per column block, reduced inside the wave
+constexpr int BD_CPITCH = BD_BLK + 4;  // a lane's column values of one block, padded
+// lane l's values start at l * BD_CPITCH + (l / 16) * 8, so the 64 lanes of one step of the
+// transposed scan (16 targets x 4 quarters of the wave) spread evenly over the banks
+constexpr int BD_CBUF = 64 * BD_CPITCH + 3 * 8;  // floats per wave
 
 struct BidirParams {
     const float *A;  // rows [T,Na,3]
     const float *B;  // targets [T,Nb,3]
-    int32_t *idx_a;
+    int32_t *idx_a;  // row results, or slice partials [S][T][Na] when the targets are sliced
     float *dist_a;
     unsigned long long *colkey;  // [T][row blocks][Nb]: (distance bits << 32) | global lane
-    int Na, Nb;
+    size_t slice_stride;         // T * Na with slices, 0 without
+    int Na, Nb, slice_len;
 };
 
+// logical workgroup: x = row block, y = frame, z = target slice
 template <int QPT>
 __device__ __forceinline__ void bidir_body(const BidirParams &pr, const Blk &blk) {
-    constexpr int ROWS = BD_THREADS * QPT;
     const float *__restrict__ A = pr.A;
     const float *__restrict__ B = pr.B;
     const int Na = pr.Na, Nb = pr.Nb;
-    __shared__ float4 tile[BD_TILE];
-    __shared__ __align__(16) float colbuf[4 * BD_WAVE_STRIDE];
+    __shared__ float4 tile[2][BD_TILE];
+    __shared__ __align__(16) float colbuf[4][BD_CBUF];
+    __shared__ unsigned long long colres[2][BD_TILE];
     const int t = blk.y, wg = blk.x, nwg = blk.gx;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const float *At = A + (size_t)t * Na * 3;
     const float *Bt = B + (size_t)t * Nb * 3;
+    const int j_begin = blk.z * pr.slice_len;
+    const int j_end = min(Nb, j_begin + pr.slice_len);
     const int glane = wg * BD_THREADS + (int)threadIdx.x;  // lanes in row order over the frame
     const int r0 = glane * QPT;
     const float nan = __builtin_nanf("");
+    const unsigned long long none = ~0ull;
     // rows past Na are NaN: their distances never win a minimum in either direction
     float qx[QPT], qy[QPT], qz[QPT], best[QPT];
     int bsub[QPT];
@@ -389,48 +400,81 @@ __device__ __forceinline__ void bidir_body(const BidirParams &pr, const Blk &blk
         qy[k] = ok ? q[1] : nan;
         qz[k] = ok ? q[2] : nan;
         best[k] = __builtin_inff();
-        bsub[k] = 0;
+        bsub[k] = j_begin;
     }
-    float *mycol = colbuf + wave * BD_WAVE_STRIDE + lane * BD_PITCH;
-    // column reduction: four lanes per target, lane `part` scanning the 64 lanes of wave `part`
-    const int jr = threadIdx.x >> 2, part = threadIdx.x & 3;
-    const float *rdcol = colbuf + part * BD_WAVE_STRIDE + (jr & (BD_SUB - 1));
+    // the transposed scan of a block: lane (quarter qd, target jt) reads the 16 lanes 16 qd ..
+    float *mycol = &colbuf[wave][lane * BD_CPITCH + (lane >> 4) * 8];
+    const int jt = lane & (BD_BLK - 1), qd = lane >> 4;
+    const float *rdcol = &colbuf[wave][16 * qd * BD_CPITCH + qd * 8 + jt];
     unsigned long long *keyrow = pr.colkey + ((size_t)t * nwg + wg) * Nb;
-    for (int base = 0; base < Nb; base += BD_TILE) {
-        const int n = min(BD_TILE, Nb - base);
-        __syncthreads();  // the previous tile is no longer read
-        for (int j = threadIdx.x; j < BD_TILE; j += BD_THREADS) {
-            float4 v = make_float4(nan, nan, nan, 0.f);  // padding targets: NaN distances
-            if (j < n) {
-                const float *p = Bt + 3 * (size_t)(base + j);
-                v = make_float4(p[0], p[1], p[2], 0.f);
-            }
-            tile[j] = v;
+    auto load_target = [&](int j) {
+        if (j < j_end) {
+            const float *p = Bt + 3 * (size_t)j;
+            return make_float4(p[0], p[1], p[2], 0.f);
         }
+        return make_float4(nan, nan, nan, 0.f);  // padding targets: NaN distances
+    };
+    const int ntiles = (j_end - j_begin + BD_TILE - 1) / BD_TILE;
+    colres[0][threadIdx.x] = none;
+    colres[1][threadIdx.x] = none;
+    tile[0][threadIdx.x] = load_target(j_begin + (int)threadIdx.x);
+    float4 nxt = make_float4(nan, nan, nan, 0.f);
+    if (ntiles > 1) nxt = load_target(j_begin + BD_TILE + (int)threadIdx.x);
+    __syncthreads();
+    for (int it = 0; it < ntiles; ++it) {
+        const int base = j_begin + it * BD_TILE;
+        const int n = min(BD_TILE, j_end - base);
+        const int buf = it & 1;
+        const float4 *tl = tile[buf];
         for (int s0 = 0; s0 < n; s0 += BD_SUB) {
-            __syncthreads();  // the tile is staged / the previous block's values were reduced
             float m[QPT];
 #pragma unroll
             for (int k = 0; k < QPT; ++k) m[k] = __builtin_inff();
+#pragma unroll 1
+            for (int b0 = s0; b0 < s0 + BD_SUB; b0 += BD_BLK) {
+                // two groups of four targets per iteration (a full unroll spills registers)
 #pragma unroll 2
-            for (int jj = 0; jj < BD_SUB; jj += 4) {
-                const float4 p0 = tile[s0 + jj], p1 = tile[s0 + jj + 1];
-                const float4 p2 = tile[s0 + jj + 2], p3 = tile[s0 + jj + 3];
-                float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
+                for (int jj = 0; jj < BD_BLK; jj += 4) {
+                    const float4 p0 = tl[b0 + jj], p1 = tl[b0 + jj + 1];
+                    const float4 p2 = tl[b0 + jj + 2], p3 = tl[b0 + jj + 3];
+                    float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
 #pragma unroll
-                for (int k = 0; k < QPT; ++k) {
-                    const float d0 = canon_d2(qx[k], qy[k], qz[k], p0.x, p0.y, p0.z);
-                    const float d1 = canon_d2(qx[k], qy[k], qz[k], p1.x, p1.y, p1.z);
-                    const float d2 = canon_d2(qx[k], qy[k], qz[k], p2.x, p2.y, p2.z);
-                    const float d3 = canon_d2(qx[k], qy[k], qz[k], p3.x, p3.y, p3.z);
-                    m[k] = __builtin_fminf(__builtin_fminf(m[k], d0), d1);
-                    m[k] = __builtin_fminf(__builtin_fminf(m[k], d2), d3);
-                    c0 = k ? __builtin_fminf(c0, d0) : d0;
-                    c1 = k ? __builtin_fminf(c1, d1) : d1;
-                    c2 = k ? __builtin_fminf(c2, d2) : d2;
-                    c3 = k ? __builtin_fminf(c3, d3) : d3;
+                    for (int k = 0; k < QPT; ++k) {
+                        const float d0 = canon_d2(qx[k], qy[k], qz[k], p0.x, p0.y, p0.z);
+                        const float d1 = canon_d2(qx[k], qy[k], qz[k], p1.x, p1.y, p1.z);
+                        const float d2 = canon_d2(qx[k], qy[k], qz[k], p2.x, p2.y, p2.z);
+                        const float d3 = canon_d2(qx[k], qy[k], qz[k], p3.x, p3.y, p3.z);
+                        m[k] = __builtin_fminf(__builtin_fminf(m[k], d0), d1);
+                        m[k] = __builtin_fminf(__builtin_fminf(m[k], d2), d3);
+                        c0 = k ? __builtin_fminf(c0, d0) : d0;
+                        c1 = k ? __builtin_fminf(c1, d1) : d1;
+                        c2 = k ? __builtin_fminf(c2, d2) : d2;
+                        c3 = k ? __builtin_fminf(c3, d3) : d3;
+                    }
+                    *reinterpret_cast<float4 *>(mycol + jj) = make_float4(c0, c1, c2, c3);
                 }
-                *reinterpret_cast<float4 *>(mycol + jj) = make_float4(c0, c1, c2, c3);
+                // the wave reads its own block back transposed (a wave's LDS accesses take
+                // effect in program order; the fences keep the compiler to it)
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                float v = __builtin_inff();
+                int vl = 0;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const float x = rdcol[i * BD_CPITCH];
+                    if (x < v) {  // the first lane of the quarter on ties
+                        v = x;
+                        vl = i;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                unsigned long long key = ((unsigned long long)__float_as_uint(v) << 32) |
+                                         (unsigned)(wg * BD_THREADS + wave * 64 + 16 * qd + vl);
+                unsigned long long o = __shfl_xor(key, 16, 64);
+                key = o < key ? o : key;
+                o = __shfl_xor(key, 32, 64);
+                key = o < key ? o : key;
+                // the workgroup's minimum per target, the first lane in row order on ties
+                if (qd == 0) atomicMin(&colres[buf][b0 + jt], key);
             }
             // rows: the first sub-tile with a strictly smaller minimum is remembered
 #pragma unroll
@@ -439,28 +483,15 @@ __device__ __forceinline__ void bidir_body(const BidirParams &pr, const Blk &blk
                     best[k] = m[k];
                     bsub[k] = base + s0;
                 }
-            __syncthreads();  // the block's column values are complete
-            // columns: the smallest value over the 64 lanes of wave `part`, the first lane on ties
-            float v = __builtin_inff();
-            int vl = 0;
-#pragma unroll 8
-            for (int l = 0; l < 64; ++l) {
-                const float x = rdcol[l * BD_PITCH];
-                if (x < v) {
-                    v = x;
-                    vl = l;
-                }
-            }
-            unsigned long long key = ((unsigned long long)__float_as_uint(v) << 32) |
-                                     (unsigned)(wg * BD_THREADS + part * 64 + vl);
-#pragma unroll
-            for (int off = 1; off < 4; off <<= 1) {
-                const unsigned long long o = __shfl_xor(key, off, 64);
-                key = o < key ? o : key;
-            }
-            const int j = base + s0 + jr;
-            if (part == 0 && jr < BD_SUB && s0 + jr < n) keyrow[j] = key;
         }
+        // stage the prefetched next tile, prefetch the one after
+        if (it + 1 < ntiles) {
+            tile[buf ^ 1][threadIdx.x] = nxt;
+            if (it + 2 < ntiles) nxt = load_target(base + 2 * BD_TILE + (int)threadIdx.x);
+        }
+        __syncthreads();  // the tile's column keys are complete; the next tile is staged
+        if ((int)threadIdx.x < n) keyrow[base + threadIdx.x] = colres[buf][threadIdx.x];
+        colres[buf][threadIdx.x] = none;  // ready for tile it + 2 (after the next barrier)
     }
     // rows: rescan the winning sub-tile for the first exact match
 #pragma unroll
@@ -468,7 +499,7 @@ __device__ __forceinline__ void bidir_body(const BidirParams &pr, const Blk &blk
         const int r = r0 + k;
         if (r >= Na) continue;
         const int js = bsub[k];
-        const int je = min(js + BD_SUB, Nb);
+        const int je = min(js + BD_SUB, j_end);
         int found = js;
         for (int j = js; j < je; ++j) {
             const float *p = Bt + 3 * (size_t)j;
@@ -477,13 +508,14 @@ __device__ __forceinline__ void bidir_body(const BidirParams &pr, const Blk &blk
                 break;
             }
         }
-        pr.idx_a[(size_t)t * Na + r] = found;
-        pr.dist_a[(size_t)t * Na + r] = best[k];
+        const size_t o = (size_t)blk.z * pr.slice_stride + (size_t)t * Na + r;
+        pr.idx_a[o] = found;
+        pr.dist_a[o] = best[k];
     }
 }
 
 template <int QPT>
-__global__ __launch_bounds__(BD_THREADS) void k_nn_bidir(BidirParams p) {
+__global__ __launch_bounds__(BD_THREADS, 4) void k_nn_bidir(BidirParams p) {
     bidir_body<QPT>(p, grid_blk_xcd());
 }
 
@@ -544,39 +576,94 @@ __global__ __launch_bounds__(BM_THREADS) void k_bidir_merge(BidirMergeParams p) 
 }  // namespace
 
 // One pass for both directions pays when there are enough row blocks to fill the chip; smaller
-// problems use the two searches of k_nn_exact, which split targets over slices.
-static int bidir_qpt(int Na, int T) {
+// problems use the two searches of k_nn_exact.  The targets are split over S slices (rows merged
+// in slice order afterwards, like k_nn_exact's slices) so that the workgroups, all of the same
+// length, fill whole rounds of the chip: S minimises ceil(x_S) / S, x_S = workgroups / resident
+// workgroups.
+struct BidirPlan {
+    int qpt = 0, nwg = 0, slices = 1, slice_len = 0;
+};
+
+static BidirPlan bidir_plan(int Na, int Nb, int T) {
+    BidirPlan p;
     const long wg8 = (long)T * ((Na + BD_THREADS * 8 - 1) / (BD_THREADS * 8));
     const long wg4 = (long)T * ((Na + BD_THREADS * 4 - 1) / (BD_THREADS * 4));
-    if (wg8 >= 1024) return 8;
-    if (wg4 >= 256) return 4;
-    return 0;
+    if (wg8 >= 512)
+        p.qpt = 8;
+    else if (wg4 >= 256)
+        p.qpt = 4;
+    else
+        return p;
+    p.nwg = (Na + BD_THREADS * p.qpt - 1) / (BD_THREADS * p.qpt);
+    const double resident = 256.0 * 4;  // compute units x workgroups per compute unit
+    const long blocks = (long)T * p.nwg;
+    double best_cost = 0;
+    for (int s = 1; s <= 16; s *= 2) {
+        const int len = ((Nb + s - 1) / s + BD_TILE - 1) / BD_TILE * BD_TILE;
+        if (s > 1 && len < 2 * BD_TILE) break;
+        const double x = blocks * (double)((Nb + len - 1) / len) / resident;
+        const double cost = std::ceil(x) * len;  // rounds x work per workgroup
+        if (s == 1 || cost < best_cost * 0.98) {
+            best_cost = cost;
+            p.slices = (Nb + len - 1) / len;
+            p.slice_len = len;
+        }
+    }
+    return p;
 }
 
 size_t nn_bidir_scratch_bytes(int T, int Na, int Nb) {
-    const int qpt = bidir_qpt(Na, T);
-    if (!qpt) return 0;
-    const size_t nwg = (size_t)(Na + BD_THREADS * qpt - 1) / (BD_THREADS * qpt);
-    return Arena::need((size_t)T * nwg * Nb, sizeof(unsigned long long));
+    const BidirPlan p = bidir_plan(Na, Nb, T);
+    if (!p.qpt) return 0;
+    size_t b = Arena::need((size_t)T * p.nwg * Nb, sizeof(unsigned long long));
+    if (p.slices > 1) b += Arena::need((size_t)p.slices * T * Na, 4) * 2;
+    return b;
 }
 
 bool launch_nn_bidir(const float *A, int Na, const float *B, int Nb, int T, int32_t *idx_a,
                      float *dist_a, int32_t *idx_b, float *dist_b, char *scratch, hipStream_t st) {
-    const int qpt = bidir_qpt(Na, T);
-    if (!qpt) return false;
-    const int nwg = (Na + BD_THREADS * qpt - 1) / (BD_THREADS * qpt);
+    const BidirPlan pl = bidir_plan(Na, Nb, T);
+    if (!pl.qpt) return false;
+    Arena ar;
+    ar.base = scratch;
+    ar.cap = nn_bidir_scratch_bytes(T, Na, Nb);
     BidirParams bp;
     bp.A = A;
     bp.B = B;
+    bp.colkey = ar.take<unsigned long long>((size_t)T * pl.nwg * Nb);
     bp.idx_a = idx_a;
     bp.dist_a = dist_a;
-    bp.colkey = reinterpret_cast<unsigned long long *>(scratch);
+    bp.slice_stride = 0;
+    if (pl.slices > 1) {
+        bp.idx_a = ar.take<int32_t>((size_t)pl.slices * T * Na);
+        bp.dist_a = ar.take<float>((size_t)pl.slices * T * Na);
+        bp.slice_stride = (size_t)T * Na;
+    }
     bp.Na = Na;
     bp.Nb = Nb;
-    if (qpt == 8)
-        dispatch(KT_BIDIR8, k_nn_bidir<8>, dim3(nwg, T), BD_THREADS, bp, st);
+    bp.slice_len = pl.slice_len;
+    const dim3 grid(pl.nwg, T, pl.slices);
+    if (pl.qpt == 8)
+        dispatch(KT_BIDIR8, k_nn_bidir<8>, grid, BD_THREADS, bp, st);
     else
-        dispatch(KT_BIDIR4, k_nn_bidir<4>, dim3(nwg, T), BD_THREADS, bp, st);
+        dispatch(KT_BIDIR4, k_nn_bidir<4>, grid, BD_THREADS, bp, st);
+    if (pl.slices > 1) {
+        const size_t total = (size_t)T * Na;
+        NNMergeParams mp;
+        mp.pidx = bp.idx_a;
+        mp.pdist = bp.dist_a;
+        mp.idx = idx_a;
+        mp.dist = dist_a;
+        mp.qlist = nullptr;
+        mp.qcount = nullptr;
+        mp.slice_stride = total;
+        mp.slices = pl.slices;
+        mp.Nq = Na;
+        mp.T = T;
+        dispatch(KT_NN_MERGE, k_nn_merge,
+                 dim3((unsigned)((total + MERGE_THREADS - 1) / MERGE_THREADS)), MERGE_THREADS, mp,
+                 st);
+    }
     BidirMergeParams mp;
     mp.A = A;
     mp.B = B;
@@ -585,8 +672,8 @@ bool launch_nn_bidir(const float *A, int Na, const float *B, int Nb, int T, int3
     mp.dist_b = dist_b;
     mp.Na = Na;
     mp.Nb = Nb;
-    mp.nwg = nwg;
-    mp.qpt = qpt;
+    mp.nwg = pl.nwg;
+    mp.qpt = pl.qpt;
     dispatch(KT_BIDIR_MERGE, k_bidir_merge, dim3((Nb + BM_THREADS - 1) / BM_THREADS, T),
              BM_THREADS, mp, st);
     return true;
@@ -710,8 +797,9 @@ void register_nn_kernels(BatchedKernel *table) {
     table[KT_NN8] = batched_kernel<NNParams, nn_exact_body<8>, NN_THREADS, 1024>();
     table[KT_NN_MERGE] = batched_kernel<NNMergeParams, nn_merge_body, MERGE_THREADS, 512>();
     table[KT_LOSS] = batched_kernel<LossParams, loss_body, LOSS_THREADS, 256>();
-    table[KT_BIDIR8] = batched_kernel<BidirParams, bidir_body<8>, BD_THREADS, 512>();
-    table[KT_BIDIR4] = batched_kernel<BidirParams, bidir_body<4>, BD_THREADS, 512>();
+    // four workgroups per compute unit, like the direct kernel
+    table[KT_BIDIR8] = batched_kernel<BidirParams, bidir_body<8>, BD_THREADS, 1024, 4>();
+    table[KT_BIDIR4] = batched_kernel<BidirParams, bidir_body<4>, BD_THREADS, 1024, 4>();
     table[KT_BIDIR_MERGE] = batched_kernel<BidirMergeParams, bidir_merge_body, BM_THREADS, 1024>();
 }
 

@@ -108,7 +108,7 @@ void fill_f64(double *p, int n, double v, hipStream_t s) {
 const int PROGRAM[] = {
     KT_FILL_U32,  KT_AREA_CDF, KT_SAMPLE,                                      // sampling
     KT_NORM_MAX,  KT_NORM_MAX, KT_PACK,     KT_SCREEN, KT_SCREEN_ROWS, KT_REFINE,  // screen
-    KT_BIDIR8,    KT_BIDIR4,   KT_BIDIR_MERGE,             // exact, both directions in one pass
+    KT_BIDIR8,    KT_BIDIR4,   KT_NN_MERGE, KT_BIDIR_MERGE,  // exact, both directions in one pass
     KT_NN8,       KT_NN4,      KT_NN1,      KT_NN_MERGE,   // exact a -> b (or its heavy rows)
     KT_COLMERGE,  KT_COLREFINE,                            // screen, columns
     KT_NN8,       KT_NN4,      KT_NN1,      KT_NN_MERGE,   // exact b -> a (or its heavy columns)
