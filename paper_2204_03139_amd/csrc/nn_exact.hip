@@ -575,6 +575,36 @@ __global__ __launch_bounds__(BM_THREADS) void k_bidir_merge(BidirMergeParams p) 
 
 }  // namespace
 
+// Workgroups of one launch that are resident on the chip at once (occupancy x compute units),
+// for the current device; callers keep the answer (the library drives one kind of GPU).
+template <class K>
+static long resident_blocks(K kern, int threads) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    return (long)std::max(per_cu, 1) * std::max(cus, 1);
+}
+
+// Equal-length workgroups run in whole rounds of `resident`: the number of target slices S (a
+// power of two, at most max_s, each slice at least min_len targets) that minimises the time
+// ceil(blocks * S / resident) / S; a larger S must gain more than 2%.
+static int round_slices(long blocks, long resident, int Np, int min_len, int max_s) {
+    int best = 1;
+    double best_cost = std::ceil((double)blocks / resident);
+    for (int s = 2; s <= max_s && (long)Np / s >= min_len; s *= 2) {
+        const double cost = std::ceil((double)blocks * s / resident) / s;
+        if (cost < best_cost * 0.98) {
+            best_cost = cost;
+            best = s;
+        }
+    }
+    return best;
+}
+
 // One pass for both directions pays when there are enough row blocks to fill the chip; smaller
 // problems use the two searches of k_nn_exact.  The targets are split over S slices (rows merged
 // in slice order afterwards, like k_nn_exact's slices) so that the workgroups, all of the same
@@ -595,20 +625,13 @@ static BidirPlan bidir_plan(int Na, int Nb, int T) {
     else
         return p;
     p.nwg = (Na + BD_THREADS * p.qpt - 1) / (BD_THREADS * p.qpt);
-    const double resident = 256.0 * 4;  // compute units x workgroups per compute unit
-    const long blocks = (long)T * p.nwg;
-    double best_cost = 0;
-    for (int s = 1; s <= 16; s *= 2) {
-        const int len = ((Nb + s - 1) / s + BD_TILE - 1) / BD_TILE * BD_TILE;
-        if (s > 1 && len < 2 * BD_TILE) break;
-        const double x = blocks * (double)((Nb + len - 1) / len) / resident;
-        const double cost = std::ceil(x) * len;  // rounds x work per workgroup
-        if (s == 1 || cost < best_cost * 0.98) {
-            best_cost = cost;
-            p.slices = (Nb + len - 1) / len;
-            p.slice_len = len;
-        }
-    }
+    static const long res8 = resident_blocks(k_nn_bidir<8>, BD_THREADS);
+    static const long res4 = resident_blocks(k_nn_bidir<4>, BD_THREADS);
+    const long resident = p.qpt == 8 ? res8 : res4;
+    const int s = round_slices((long)T * p.nwg, resident, Nb, 2 * BD_TILE, 16);
+    // slices are whole tiles; rounding them up may leave fewer slices than asked for
+    p.slice_len = ((Nb + s - 1) / s + BD_TILE - 1) / BD_TILE * BD_TILE;
+    p.slices = (Nb + p.slice_len - 1) / p.slice_len;
     return p;
 }
 
@@ -679,13 +702,15 @@ bool launch_nn_bidir(const float *A, int Na, const float *B, int Nb, int T, int3
     return true;
 }
 
-// scratch for the slice partials (0 when no slicing is needed)
+// target slices of the one-direction search: enough workgroups to fill the chip, in whole rounds
 static int nn_slices(int Nq, int Np, int T, int qpt) {
     const long qblocks = (Nq + NN_THREADS * qpt - 1) / (NN_THREADS * qpt);
     const long blocks = qblocks * T;
-    int s = 1;
-    while (blocks * s < 2048 && (long)Np / (s * 2) >= 2 * NN_TILE) s *= 2;
-    return s;
+    static const long res8 = resident_blocks(k_nn_exact<8>, NN_THREADS);
+    static const long res4 = resident_blocks(k_nn_exact<4>, NN_THREADS);
+    static const long res1 = resident_blocks(k_nn_exact<1>, NN_THREADS);
+    const long resident = qpt == 8 ? res8 : qpt == 4 ? res4 : res1;
+    return round_slices(blocks, resident, Np, 2 * NN_TILE, 64);
 }
 
 static int nn_qpt(int Nq) { return Nq >= 16384 ? 8 : (Nq >= 4096 ? 4 : 1); }
