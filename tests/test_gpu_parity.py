@@ -384,6 +384,50 @@ def test_one_pass_both_directions(shape):
             assert np.array_equal(whole[k][t].view(np.uint32), part[k][0].view(np.uint32)), (t, k)
 
 
+def test_maximum_frame_count():
+    """T = 65,535 frames (the largest the ABI takes) of a single triangle: sampling, both Chamfer
+    directions in both precisions, and the backward to vertices, element by element against the
+    oracle (grids of 65,535 frames in every kernel)."""
+    p = gpu()
+    say("[limits] 65535 frames")
+    T, N, Nb = 65535, 5, 3
+    r = np.random.default_rng(81)
+    verts = r.uniform(-.5, .5, (T, 3, 3)).astype(np.float32)
+    faces = np.array([[0, 1, 2]], np.int32)
+    obs = r.uniform(-.5, .5, (T, Nb, 3)).astype(np.float32)
+    gp, gf, gb = p.sample_surface(dev(verts), dev(faces), N, seed=99)
+    op, of, ob = oracle.sample_surface(verts, faces, N, seed=99)
+    assert np.array_equal(host(gf), of)
+    assert np.array_equal(host(gp).view(np.uint32), op.view(np.uint32))
+    o = oracle.chamfer(op, obs)
+    og = oracle.chamfer_grad(op, obs, o["idx_a"], o["idx_b"])
+    ogv, ogva = oracle.sample_grad(og["ga"], faces, of, ob, 3, og["ga_abs"])
+    for precision in (0, 1):
+        f = p.chamfer_fwd(gp, dev(obs), precision=precision)
+        ga, _ = p.chamfer_bwd(torch.ones(T, dtype=torch.float64, device="cuda"), gp, dev(obs),
+                              f["idx_a"], f["idx_b"])
+        gv = p.sample_surface_bwd(ga, dev(faces), gf, gb, 3)
+        torch.cuda.synchronize()
+        _check_chamfer({k: host(v) for k, v in f.items()}, o)
+        assert_grad(host(gv), ogv, ogva, what="grad_verts")
+
+
+@pytest.mark.parametrize("shape", [((1 << 24), 7), (7, (1 << 24))])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_maximum_point_count(shape, precision):
+    """2^24 points (the largest count the ABI takes) against a handful on the other side, both
+    ways round, both precisions: indices exact and float distances bit for bit in both
+    directions."""
+    p = gpu()
+    Na, Nb = shape
+    say(f"[limits] {Na} x {Nb} precision={precision}")
+    r = np.random.default_rng(83)
+    A = r.uniform(-.5, .5, (1, Na, 3)).astype(np.float32)
+    B = r.uniform(-.5, .5, (1, Nb, 3)).astype(np.float32)
+    g, o = _chamfer_both(p, A, B, precision=precision)
+    _check_chamfer(g, o)
+
+
 @pytest.mark.parametrize("reduction", [0, 1])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_loss_reductions_and_weights(reduction, precision):
