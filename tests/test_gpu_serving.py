@@ -250,42 +250,50 @@ def _mix_extremes():
     return out
 
 
-def _oracle_frame(verts, faces, obs, seed, t, Na, reduction):
+def _oracle_frame(verts, faces, obs, seed, t, Na, reduction, frame_w=None):
     """Frame t of a served request through the oracle: its sampler words come from (seed, t)."""
     words = oracle.words_from_seed(seed, t + 1, Na)[t:t + 1]
     op, ofi, oba = oracle.sample_surface(verts[t:t + 1], faces, Na, words=words)
-    och = oracle.chamfer(op, obs[t:t + 1], reduction)
-    og = oracle.chamfer_grad(op, obs[t:t + 1], och["idx_a"], och["idx_b"], reduction)
+    fw = None if frame_w is None else frame_w[t:t + 1]
+    och = oracle.chamfer(op, obs[t:t + 1], reduction, fw)
+    og = oracle.chamfer_grad(op, obs[t:t + 1], och["idx_a"], och["idx_b"], reduction, fw)
     gv, gva = oracle.sample_grad(og["ga"], faces, ofi, oba, verts.shape[1], og["ga_abs"])
     return och["loss"][0], gv[0], gva[0]
 
 
 def test_served_results_match_the_oracle():
     """Requests of the serving mix's extreme sizes, each in both precisions and both reductions
-    (Eq. 1 and Eq. 2), all submitted together so that they are batched and overlap on the device:
-    on two whole frames of every request (the first and one drawn at random) the served loss is
-    within 1e-5 of the oracle's and the served vertex gradient within 1e-5 of the sum of absolute
-    contributions, component by component (Sec. III-A Eq. 1-2, Sec. III-B Eq. 3-4); every
-    frame's loss is finite and positive."""
+    (Eq. 1 and Eq. 2), some with frame weights and some without a gradient, all submitted together
+    so that they are batched and overlap on the device: on two whole frames of every request (the
+    first and one drawn at random) the served loss is within 1e-5 of the oracle's and the served
+    vertex gradient within 1e-5 of the sum of absolute contributions, component by component
+    (Sec. III-A Eq. 1-2, Sec. III-B Eq. 3-4); every frame's loss is finite and positive."""
     gpu()
     from paper_2204_03139_amd.serving import Server
     srv = Server(hbm_budget_bytes=16 << 30)
     cases = []
     for k, req in enumerate(_mix_extremes()):
         verts, faces, obs = gen.request_inputs(req)
-        for prec, red in ((0, 0), (1, 0), (0, 1), (1, 1)):
-            say(f"[serving] submit {req} precision={prec} reduction={red}")
-            tk = srv.submit(verts, faces, obs, req["Na"], req["seed"], prec, red)
-            cases.append((req, verts, faces, obs, prec, red, tk))
+        # frame weights on some requests (frame selection, Sec. III-C), loss-only on others
+        fw = (np.linspace(0.25, 2.0, req["T"]).astype(np.float32) if k % 2 else None)
+        for c, (prec, red) in enumerate(((0, 0), (1, 0), (0, 1), (1, 1))):
+            want = (k + c) % 4 != 3
+            say(f"[serving] submit {req} precision={prec} reduction={red} weights={fw is not None}"
+                f" grad={want}")
+            tk = srv.submit(verts, faces, obs, req["Na"], req["seed"], prec, red, fw,
+                            want_grad=want)
+            cases.append((req, verts, faces, obs, prec, red, fw, want, tk))
     rng = np.random.default_rng(12)
-    for req, verts, faces, obs, prec, red, tk in cases:
+    for req, verts, faces, obs, prec, red, fw, want, tk in cases:
         st, loss, grad, _ = srv.wait(tk, timeout=300)
         assert st == 0, (req, prec, red)
         assert np.all(np.isfinite(loss)) and np.all(loss > 0)
+        assert (grad is not None) == want
         frames = sorted({0, int(rng.integers(req["T"]))})
         say(f"[serving] check {req} precision={prec} reduction={red} frames={frames}")
         for t in frames:
-            ol, ogv, ogva = _oracle_frame(verts, faces, obs, req["seed"], t, req["Na"], red)
+            ol, ogv, ogva = _oracle_frame(verts, faces, obs, req["seed"], t, req["Na"], red, fw)
             assert_rel(loss[t:t + 1], [ol], 1e-5, "served loss")
-            assert_grad(grad[t], ogv, ogva, what="served grad_verts")
+            if want:
+                assert_grad(grad[t], ogv, ogva, what="served grad_verts")
     srv.close()
