@@ -71,8 +71,10 @@ int dc_create(dc_ctx **out, int device, size_t hbm_budget_bytes, int max_slots);
 /* Wait for the serving loop to drain, free everything the context owns, destroy it. */
 int dc_destroy(dc_ctx *ctx);
 
-/* Text of the calling thread's last error ("" if none); valid until the thread's next call. */
-const char *dc_last_error(void);
+/* Text of the calling thread's last error ("" if none); valid until the thread's next call into
+ * the library.  Messages are kept per thread, not per context: `ctx` may be NULL and is not read
+ * (it is part of the signature so that a caller can name the context it is asking about). */
+const char *dc_last_error(const dc_ctx *ctx);
 
 /* Wait for `stream`, then report and clear device-detected errors of earlier direct calls:
  * DC_OK, DC_ERR_DEGENERATE (a frame with zero or non-finite total area; its points are NaN and

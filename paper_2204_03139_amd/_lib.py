@@ -88,6 +88,7 @@ def load():
     vp, i, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64
     L.dc_create.argtypes = [ctypes.POINTER(vp), i, ctypes.c_size_t, i]
     L.dc_destroy.argtypes = [vp]
+    L.dc_last_error.argtypes = [vp]
     L.dc_last_error.restype = ctypes.c_char_p
     L.dc_sync.argtypes = [vp, vp]
     L.dc_sample_surface.argtypes = [vp, vp, vp, i, i, i, i, u64, vp, vp, vp, vp, vp]
@@ -114,7 +115,7 @@ def load():
 
 def _check(rc: int, where: str):
     if rc < 0:
-        raise DCError(rc, where, load().dc_last_error().decode())
+        raise DCError(rc, where, load().dc_last_error(None).decode())
     return rc
 
 

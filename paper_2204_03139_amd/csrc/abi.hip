@@ -204,7 +204,7 @@ extern "C" {
 
 int dc_version(void) { return 100; }
 
-const char *dc_last_error(void) { return g_err.c_str(); }
+const char *dc_last_error(const dc_ctx *) { return g_err.c_str(); }
 
 int dc_create(dc_ctx **out, int device, size_t hbm_budget_bytes, int max_slots) {
     clear_error();
