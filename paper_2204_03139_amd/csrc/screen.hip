@@ -287,18 +287,41 @@ __device__ __forceinline__ void pack_body(const PackParams &pr, const Blk &blk) 
 
 __global__ __launch_bounds__(256) void k_pack_targets(PackParams p) { pack_body(p, grid_blk()); }
 
-// Column partial minima are stored as the upper 16 bits of the float (a bf16 bit pattern), rounded
-// toward minus infinity, so the stored value is a lower bound of the partial.
-__device__ __forceinline__ uint16_t lower_bf16_bits(float v) {
-    const unsigned b = __float_as_uint(v);
-    const unsigned hi = b >> 16;
-    return (uint16_t)(hi + (((b >> 31) & ((b & 0xFFFFu) != 0u)) ? 1u : 0u));
+// Column partials are one 16-bit word per (row workgroup, target): a 12-bit code of the
+// workgroup's minimum over the target, then the ambiguous flag (bit 3) and the winning row group
+// (bits 0-2).  The code is the bf16 pattern of max(v, 0) (the float truncated to 16 bits: rounded
+// down) less a per-frame bias, clamped to [0, 4095]: monotone in v, with bf16's 7 mantissa bits
+// over 32 binades that end above every squared distance of the frame (at most 4 max|x|^2).  Code 0
+// covers everything below the range and negative screened values, code 4095 everything above it.
+// Words compare like their codes.
+constexpr int PC_MAX = 4095;
+
+// bias of the frame's codes: the top binade of the range is that of 8 max(|a|^2, |b|^2)
+__device__ __forceinline__ int part_bias(float nqmax, float npmax) {
+    const unsigned et = (__float_as_uint(8.0f * fmaxf(nqmax, npmax)) >> 23) & 0xFFu;
+    return et > 31u ? (int)((et - 31u) << 7) : 0;
 }
 
-// an upper bound of any float whose rounded-down bf16 pattern is x: one bf16 step (at most 2^-7
-// relative, or the bf16 denormal step) above x, rounded up in float
-__device__ __forceinline__ float bf16_step_up(float x) {
-    return x + fabsf(x) * (0.0078125f + 1e-6f) + SCREEN_TAU;
+__device__ __forceinline__ int part_code(float v, int bias) {
+    const int hb = (int)(__float_as_uint(fmaxf(v, 0.f)) >> 16);
+    return min(max(hb - bias, 0), PC_MAX);
+}
+
+// the smallest value a code can stand for (0 for code 0, whose values may even be negative)
+__device__ __forceinline__ float part_lo(int c, int bias) {
+    return c <= 0 ? 0.f : __uint_as_float((unsigned)(c + bias) << 16);
+}
+
+// a value above everything a code can stand for (infinite for the saturated code)
+__device__ __forceinline__ float part_hi(int c, int bias) {
+    return c >= PC_MAX ? __builtin_inff() : __uint_as_float((unsigned)(c + 1 + bias) << 16);
+}
+
+// the largest word whose code can stand for a value <= th (-1: none; a NaN passes everything)
+__device__ __forceinline__ int part_word_limit(float th, int bias) {
+    if (th < 0.f) return -1;
+    const int c = (th >= 0.f) ? part_code(th, bias) : PC_MAX;
+    return (c << 4) | 15;
 }
 
 // Column row groups per workgroup: (wave, h), h in {0, 1}, holding the rows 16a + 4g + r of the
@@ -307,8 +330,8 @@ __device__ __forceinline__ float bf16_step_up(float x) {
 constexpr int SC_GROUPS = SC_WAVES * 2;
 constexpr int CP_PAD = SC_TPS + 1;       // column partial buffer: [group][column][tile], padded
 
-// Column partials (16-bit value, 1-byte tag) of every (row workgroup w, target j) of a frame, laid
-// out in blocks of CP_BLOCK targets: [frame][j / CP_BLOCK][w][j % CP_BLOCK].  The merge reads one
+// Column partial words of every (row workgroup w, target j) of a frame, laid out in blocks of
+// CP_BLOCK targets: [frame][j / CP_BLOCK][w][j % CP_BLOCK].  The merge reads one
 // block's rows as one contiguous stream; a screen workgroup's stores stay runs of 16 targets.
 constexpr int CP_BLOCK = 128;
 static_assert(SC_CHUNK % CP_BLOCK == 0, "padded target counts are whole blocks");
@@ -321,12 +344,12 @@ struct ScreenParams {
     const float *Q;
     const bf16x8 *packed;
     const float *slack;
-    const float *npmax;
+    const float *npmax;  // per frame: largest squared norm of the targets
+    const float *nqmax;  // and of the queries
     int32_t *rec;
     int32_t *heavy_cnt;
     int32_t *heavy_list;
     uint16_t *cpart;
-    uint8_t *ctag;
     int Nq, Np, Np_pad;
 };
 
@@ -343,7 +366,6 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
     int32_t *__restrict__ heavy_cnt = pr.heavy_cnt;
     int32_t *__restrict__ heavy_list = pr.heavy_list;
     uint16_t *__restrict__ cpart = pr.cpart;
-    uint8_t *__restrict__ ctag = pr.ctag;
     // [buffer][K-chunk][entry] -> 16 bytes.  Entry 17*bt + c holds tile bt, result column c: the
     // operand reads (16 columns of one tile) are consecutive and the staging stores (8 tiles of
     // one column, 272 bytes apart) fall in distinct banks; the read address is a per-lane base
@@ -429,6 +451,7 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
 #pragma unroll
     for (int u = 0; u < SC_PER_THREAD; ++u)
         pbase[u] = COLS ? part_index(t, nwg, Np_pad, wgx, soff[u]) : 0;
+    const int pbias = COLS ? part_bias(pr.nqmax[t], pr.npmax[t]) : 0;
     // reduce the workgroup's row groups per target of stage sm and write its partial
     // reduce the workgroup's row groups per target of stage sm and write its partial (padding
     // targets too: the partial arrays span the padded target range)
@@ -455,8 +478,8 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
             // plus a uniform step
             const size_t o = pbase[u] + (size_t)(sm / SPC) * (SC_CHUNK / CP_BLOCK) * nwg * CP_BLOCK +
                              SC_TPS * (sm % SPC);
-            cpart[o] = lower_bf16_bits(best);
-            ctag[o] = (uint8_t)(bg | (amb ? 0x80 : 0));
+            cpart[o] = (uint16_t)(((unsigned)part_code(best, pbias) << 4) | (amb ? 8u : 0u) |
+                                  (unsigned)bg);
         }
     };
     for (int st = 0; st < nstage; ++st) {
@@ -626,7 +649,7 @@ __global__ __launch_bounds__(SC_THREADS, sc_atiles<COLS>() <= 4 ? 3 : 2) void k_
 // workgroups whose partial passed the (affine, never smaller) threshold of the minimum seen so far;
 // at the end the list is filtered by the certificate at the final minimum.  Candidates are the
 // workgroups passing it; more than CMAXC makes the target heavy.  Record per target: n (or -1 =
-// heavy) and up to CMAXC entries (workgroup << 8 | tag).
+// heavy) and up to CMAXC entries (workgroup << 8 | tag), tag = row group | 0x80 if ambiguous.
 constexpr int CMAXC = 12;
 constexpr int CREC_INTS = 1 + CMAXC + 1;
 
@@ -638,8 +661,8 @@ struct ColmergeParams {
     const float *P;
     const float *slack;  // per-target affine threshold slack (k_pack_targets)
     const uint16_t *cpart;
-    const uint8_t *ctag;
-    const float *nqmax;
+    const float *nqmax;  // per frame: largest squared norm of the rows (a)
+    const float *npmax;  // and of the targets (b)
     int32_t *crec;
     int32_t *heavy_cnt;
     int32_t *heavy_list;
@@ -650,26 +673,25 @@ __device__ __forceinline__ void colmerge_body(const ColmergeParams &pr, const Bl
     const float *__restrict__ P = pr.P;
     const int Np = pr.Np, Np_pad = pr.Np_pad, nwg = pr.nwg;
     const uint16_t *__restrict__ cpart = pr.cpart;
-    const uint8_t *__restrict__ ctag = pr.ctag;
-    const float *__restrict__ nqmax = pr.nqmax;
     int32_t *__restrict__ crec = pr.crec;
     int32_t *__restrict__ heavy_cnt = pr.heavy_cnt;
     int32_t *__restrict__ heavy_list = pr.heavy_list;
-    // pending entries (workgroup << 16) | 16-bit partial; point counts are at most 2^24, so there
+    // pending entries (workgroup << 16) | partial word; point counts are at most 2^24, so there
     // are at most 2^16 row workgroups
     __shared__ uint32_t pend[CM_CAP][CM_TPT][CM_THREADS];
     const int t = blk.y;
     const int tid = threadIdx.x;
     const int j0 = (blk.x * CM_THREADS + tid) * CM_TPT;
     if (j0 >= Np) return;
-    const float inf = __builtin_inff();
-    float best[CM_TPT], thr[CM_TPT], slk[CM_TPT];
-    int cnt[CM_TPT];
+    const float nqm = pr.nqmax[t];
+    const int bias = part_bias(nqm, pr.npmax[t]);
+    int best[CM_TPT], lim[CM_TPT], cnt[CM_TPT];
+    float slk[CM_TPT];
     bool over[CM_TPT];
 #pragma unroll
     for (int u = 0; u < CM_TPT; ++u) {
-        best[u] = inf;
-        thr[u] = inf;
+        best[u] = PC_MAX + 1;
+        lim[u] = 0x7fffffff;
         cnt[u] = 0;
         over[u] = false;
         slk[u] = pr.slack[(size_t)t * Np_pad + j0 + u];
@@ -679,28 +701,29 @@ __device__ __forceinline__ void colmerge_body(const ColmergeParams &pr, const Bl
     const int jb = __builtin_amdgcn_readfirstlane(j0 / CP_BLOCK);  // the same for the whole wave
     const uint16_t *block = cpart + part_index(t, nwg, Np_pad, 0, jb * CP_BLOCK);
     // a partial passing the threshold of the running minimum goes on the list; the rest are
-    // skipped with one compare.  A full list drops the entries the current threshold excludes;
-    // if none can be dropped the target is made heavy (always correct: it is searched exhaustively).
-    auto consider = [&](int u, unsigned bits, int w) {
-        const float v = __uint_as_float(bits << 16);
-        if (v <= thr[u]) {
+    // skipped with one compare.  The threshold is taken at a value above the running minimum
+    // (the top of its code), and a partial passes when the bottom of its code does.  A full list
+    // drops the entries the current threshold excludes; if none can be dropped the target is made
+    // heavy (always correct: it is searched exhaustively).
+    auto consider = [&](int u, unsigned word, int w) {
+        if ((int)word <= lim[u]) {
             if (cnt[u] == CM_CAP) {
                 int n = 0;
 #pragma unroll 1
                 for (int k = 0; k < CM_CAP; ++k) {
                     const uint32_t e = pend[k][u][tid];
-                    if (__uint_as_float(e << 16) <= thr[u]) pend[n++][u][tid] = e;
+                    if ((int)(e & 0xFFFFu) <= lim[u]) pend[n++][u][tid] = e;
                 }
                 cnt[u] = n;
                 if (n == CM_CAP) {
                     over[u] = true;
-                    thr[u] = -inf;
+                    lim[u] = -1;
                     return;
                 }
             }
-            pend[cnt[u]++][u][tid] = ((uint32_t)w << 16) | bits;
-            best[u] = fminf(best[u], v);
-            thr[u] = threshold_affine(bf16_step_up(best[u]), slk[u]);
+            pend[cnt[u]++][u][tid] = ((uint32_t)w << 16) | word;
+            best[u] = min(best[u], (int)(word >> 4));
+            lim[u] = part_word_limit(threshold_affine(part_hi(best[u], bias), slk[u]), bias);
         }
     };
     // the two 16-bit partials of one workgroup for this thread's targets, as one word
@@ -738,28 +761,27 @@ __device__ __forceinline__ void colmerge_body(const ColmergeParams &pr, const Bl
     }
     for (; w < nwg; ++w)
         merge2(*reinterpret_cast<const unsigned *>(block + (size_t)w * CP_BLOCK + j0 % CP_BLOCK), w);
-    const float nqm = nqmax[t];
 #pragma unroll
     for (int u = 0; u < CM_TPT; ++u) {
         const int j = j0 + u;
         if (j >= Np) break;
         const float *pj = P + ((size_t)t * Np + j) * 3;
         const float np = norm2(pj[0], pj[1], pj[2]);
-        // the partials are lower bounds within one bf16 step; the threshold is taken at an upper
-        // bound of the true minimum, and a workgroup is kept when its lower bound passes it
-        const float theta = threshold(bf16_step_up(best[u]), np, nqm);
-        const bool finite = __builtin_isfinite(best[u]) && __builtin_isfinite(theta) &&
-                            __builtin_isfinite(nqm);
+        // the certificate at a value above the true minimum (the top of the smallest code); a
+        // workgroup is kept when the bottom of its code passes it
+        const float theta = threshold(part_hi(best[u], bias), np, nqm);
+        const bool finite = __builtin_isfinite(theta) && __builtin_isfinite(nqm);
+        const int wlim = part_word_limit(theta, bias);
         int32_t *rr = crec + ((size_t)t * Np + j) * CREC_INTS;
         int n = 0;
         if (finite && !over[u]) {
 #pragma unroll 1
             for (int k = 0; k < cnt[u]; ++k) {
                 const uint32_t e = pend[k][u][tid];
-                if (__uint_as_float(e << 16) <= theta) {
+                if ((int)(e & 0xFFFFu) <= wlim) {
                     const int wk = (int)(e >> 16);
-                    if (n < CMAXC)
-                        rr[1 + n] = (wk << 8) | ctag[part_index(t, nwg, Np_pad, wk, j)];
+                    const int tag = (int)(e & 7u) | ((e & 8u) ? 0x80 : 0);
+                    if (n < CMAXC) rr[1 + n] = (wk << 8) | tag;
                     ++n;
                 }
             }
@@ -1017,8 +1039,7 @@ size_t screen_scratch_bytes(int T, int Na, int Nb) {
            Arena::need((size_t)T * Nb * CREC_INTS, 4) +               // column records
            Arena::need((size_t)T * Nb_pad * 3, sizeof(bf16x8)) +      // packed b operands
            Arena::need((size_t)T * Nb_pad, 4) +                       // their threshold slack
-           Arena::need((size_t)T * nwg * Nb_pad, 2) +                 // column partial minima
-           Arena::need((size_t)T * nwg * Nb_pad, 1) +                 // their tags
+           Arena::need((size_t)T * nwg * Nb_pad, 2) +                 // column partial words
            std::max(nn_exact_list_scratch_bytes(T, Na, Nb), nn_exact_list_scratch_bytes(T, Nb, Na));
 }
 
@@ -1043,7 +1064,6 @@ void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int
     bf16x8 *packed = ar.take<bf16x8>((size_t)T * Nb_pad * 3);
     float *slack = ar.take<float>((size_t)T * Nb_pad);
     uint16_t *cpart = ar.take<uint16_t>((size_t)T * nwg * Nb_pad);
-    uint8_t *ctag = ar.take<uint8_t>((size_t)T * nwg * Nb_pad);
     char *exact_scratch = ar.take<char>(
         std::max(nn_exact_list_scratch_bytes(T, Na, Nb), nn_exact_list_scratch_bytes(T, Nb, Na)));
     NormMaxParams nm;
@@ -1074,11 +1094,11 @@ void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int
         sp.packed = packed;
         sp.slack = slack;
         sp.npmax = nbmax;
+        sp.nqmax = namax;
         sp.rec = rec;
         sp.heavy_cnt = hcnt_a;
         sp.heavy_list = hlist_a;
         sp.cpart = cpart;
-        sp.ctag = ctag;
         sp.Nq = Na;
         sp.Np = Nb;
         sp.Np_pad = Nb_pad;
@@ -1106,8 +1126,8 @@ void launch_chamfer_screened(const float *a, int Na, const float *b, int Nb, int
         cm.P = b;
         cm.slack = slack;
         cm.cpart = cpart;
-        cm.ctag = ctag;
         cm.nqmax = namax;
+        cm.npmax = nbmax;
         cm.crec = crec;
         cm.heavy_cnt = hcnt_b;
         cm.heavy_list = hlist_b;
