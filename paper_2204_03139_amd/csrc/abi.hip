@@ -237,9 +237,9 @@ int dc_create(dc_ctx **out, int device, size_t hbm_budget_bytes, int max_slots) 
         return DC_ERR_BUDGET;
     }
     hipError_t e = hipMalloc(&c->d_status, sizeof(unsigned) * 4);
-    if (e == hipSuccess) e = hipMalloc(&c->d_stats, sizeof(unsigned long long) * 4);
+    if (e == hipSuccess) e = hipMalloc(&c->d_stats, STATS_BYTES);
     if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(unsigned) * 4);
-    if (e == hipSuccess) e = hipMemset(c->d_stats, 0, sizeof(unsigned long long) * 4);
+    if (e == hipSuccess) e = hipMemset(c->d_stats, 0, STATS_BYTES);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->arena_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     const int rc = e == hipSuccess ? noalloc_init(device) : hip_fail(e, "dc_create");
@@ -298,11 +298,14 @@ int dc_get_stats(dc_ctx *ctx, dc_stats *out) {
     clear_error();
     if (!ctx || !out) return DC_ERR_INVALID;
     DC_HIP(hipSetDevice(ctx->device));
-    unsigned long long v[4] = {0, 0, 0, 0};
-    DC_HIP(hipMemcpy(v, ctx->d_stats, sizeof(v), hipMemcpyDeviceToHost));
-    out->queries = v[0];
-    out->candidates = v[1];
-    out->fallbacks = v[2];
+    std::vector<unsigned long long> v((size_t)STATS_SLOTS * STATS_SLOT_WORDS);
+    DC_HIP(hipMemcpy(v.data(), ctx->d_stats, STATS_BYTES, hipMemcpyDeviceToHost));
+    out->queries = out->candidates = out->fallbacks = 0;
+    for (int k = 0; k < STATS_SLOTS; ++k) {
+        out->queries += v[(size_t)k * STATS_SLOT_WORDS];
+        out->candidates += v[(size_t)k * STATS_SLOT_WORDS + 1];
+        out->fallbacks += v[(size_t)k * STATS_SLOT_WORDS + 2];
+    }
     return DC_OK;
 }
 

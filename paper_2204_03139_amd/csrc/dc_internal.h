@@ -67,7 +67,7 @@ struct dc_ctx {
     hipStream_t arena_stream = nullptr;   // the stream of the last direct call
     bool arena_used = false;
     unsigned *d_status = nullptr;           // sticky device status word
-    unsigned long long *d_stats = nullptr;  // [3] screen counters
+    unsigned long long *d_stats = nullptr;  // screen counters: [STATS_SLOTS][STATS_SLOT_WORDS]
     dc::Scheduler *sched = nullptr;
     int fail_next_alloc = 0;      // test hook: make the next N allocations fail
     bool prof = false;            // record events around profiled launches
@@ -82,8 +82,15 @@ namespace dc {
 // reserve `bytes` of the budget; DC_ERR_BUDGET if it cannot fit
 int budget_take(dc_ctx *ctx, size_t bytes);
 void budget_give(dc_ctx *ctx, size_t bytes);
+// The screen's counters (queries, candidate groups, fallbacks) are spread over STATS_SLOTS slots of
+// STATS_SLOT_WORDS 64-bit words (one 128-byte cache line per slot); a workgroup adds its counts to
+// the slot of its hardware id and the host sums the slots.  One shared counter would serialise
+// the atomics of every workgroup on one address.
+constexpr int STATS_SLOTS = 64;
+constexpr int STATS_SLOT_WORDS = 16;
+constexpr size_t STATS_BYTES = sizeof(unsigned long long) * STATS_SLOTS * STATS_SLOT_WORDS;
 // device bytes of the context's status and counter words (held from dc_create on)
-constexpr size_t CTX_WORDS_BYTES = sizeof(unsigned) * 4 + sizeof(unsigned long long) * 4;
+constexpr size_t CTX_WORDS_BYTES = sizeof(unsigned) * 4 + STATS_BYTES;
 // test hook: true (and one fewer pending) when the next allocation is to fail
 bool forced_alloc_failure(dc_ctx *ctx);
 // device allocation counted against the budget; dev_alloc honours the test hook, dev_alloc_raw

@@ -396,20 +396,25 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
         A[a] = pick8(v, g);
     }
 
-    // per (lane, row): running minimum of the current chunk, the three best chunk minima, and
-    // the chunks of the best two packed as (best << 16) | second (0xFFFF = none)
+    // per (lane, row): running minimum of the current chunk and the three best chunk minima.  A
+    // chunk's minimum carries the chunk's index in its kbits lowest mantissa bits, so the three
+    // smallest values travel with their chunks through plain minimum instructions; every value is
+    // then within 2^(kbits-22) relative of the minimum it stands for.  The running minimum starts
+    // at the largest finite float, so an encoded value is never a NaN.
     const float inf = __builtin_inff();
+    const float big = __FLT_MAX__;
+    const int nchunk = Np_pad / SC_CHUNK;
+    const int kbits = nchunk > 1 ? 32 - __builtin_clz((unsigned)(nchunk - 1)) : 0;
+    const unsigned kmask = (1u << kbits) - 1u;
     float m[ATILES][4], b1[ATILES][4], b2[ATILES][4], b3[ATILES][4];
-    unsigned cc[ATILES][4];
 #pragma unroll
     for (int a = 0; a < ATILES; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            m[a][r] = inf;
+            m[a][r] = big;
             b1[a][r] = inf;
             b2[a][r] = inf;
             b3[a][r] = inf;
-            cc[a][r] = 0xFFFFFFFFu;
         }
     const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
     const int nstage = Np_pad / SC_STAGE;
@@ -445,8 +450,10 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
     }
     const int gk = (g == 3) ? 0 : g;
     // the column partial offsets of this thread's staged targets in stage 0: a stage's targets
-    // lie in its chunk's slot groups, one CP_BLOCK block per slot group
-    static_assert(SC_RUN == CP_BLOCK, "a slot group is one partial block");
+    // lie in one slot group of its chunk, and a slot group lies inside one CP_BLOCK block, so the
+    // offset moves by a uniform step from stage to stage
+    static_assert(CP_BLOCK % SC_RUN == 0 && SC_CHUNK % CP_BLOCK == 0,
+                  "a slot group lies inside one partial block");
     size_t pbase[SC_PER_THREAD];
 #pragma unroll
     for (int u = 0; u < SC_PER_THREAD; ++u)
@@ -556,17 +563,11 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
             for (int a = 0; a < ATILES; ++a)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const float x = m[a][r];
-                    const bool t1 = x < b1[a][r];
-                    const bool t2 = x < b2[a][r];
+                    const float x = __uint_as_float((__float_as_uint(m[a][r]) & ~kmask) | k);
                     b3[a][r] = __builtin_amdgcn_fmed3f(x, b2[a][r], b3[a][r]);
                     b2[a][r] = __builtin_amdgcn_fmed3f(x, b1[a][r], b2[a][r]);
                     b1[a][r] = fminf(x, b1[a][r]);
-                    const unsigned c1 = cc[a][r] >> 16;
-                    const unsigned up1 = (k << 16) | c1;       // x becomes best, old best second
-                    const unsigned up2 = (c1 << 16) | k;       // x becomes second
-                    cc[a][r] = t1 ? up1 : (t2 ? up2 : cc[a][r]);
-                    m[a][r] = inf;
+                    m[a][r] = big;
                 }
         }
 #pragma unroll
@@ -580,8 +581,12 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
         merge_stage(nstage - 1);
     }
 
-    // row certificate and candidate records; the 16 lanes of a group share one row per (a, r)
+    // row certificate and candidate records; the 16 lanes of a group share one row per (a, r).
+    // The encoded chunk minima stand for values within a relative kslack of themselves: the
+    // certificate is taken at a value above the row's minimum, and a chunk passes when its value
+    // does not exceed the threshold widened by the same amount.
     const float npm = pr.npmax[t];
+    const float kslack = __uint_as_float((unsigned)(127 + kbits - 21) << 23);  // 2^(kbits-21)
     const unsigned long long gmask = 0xFFFFull << (16 * g);
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
@@ -595,13 +600,16 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
             float nq = 0.f;
             if (row < Nq)
                 nq = norm2(Qt[3 * (size_t)row], Qt[3 * (size_t)row + 1], Qt[3 * (size_t)row + 2]);
-            const float theta = threshold(mi, nq, npm);
+            const float theta =
+                threshold(mi + fabsf(mi) * kslack + SCREEN_TAU, nq, npm);
+            const float thp = theta + fabsf(theta) * kslack + SCREEN_TAU;
             const bool finite = __builtin_isfinite(mi) && __builtin_isfinite(theta) &&
                                 __builtin_isfinite(npm);
-            const int c1 = (int)(cc[a][r] >> 16), c2 = (int)(cc[a][r] & 0xFFFFu);
-            const bool k1 = finite && c1 != 0xFFFF && b1[a][r] <= theta;
-            const bool k2 = finite && c2 != 0xFFFF && b2[a][r] <= theta;
-            const bool over = finite && b3[a][r] <= theta;
+            const bool k1 = finite && b1[a][r] <= thp;
+            const bool k2 = finite && b2[a][r] <= thp;
+            const bool over = finite && b3[a][r] <= thp;
+            const int c1 = (int)(__float_as_uint(b1[a][r]) & kmask);
+            const int c2 = (int)(__float_as_uint(b2[a][r]) & kmask);
             const unsigned long long m1 = __ballot(k1) & gmask;
             const unsigned long long m2 = __ballot(k2) & gmask;
             const unsigned long long mo = __ballot(over) & gmask;
@@ -812,39 +820,72 @@ static_assert(SC_RUN % RF_STEP == 0, "slot groups are whole refine steps");
 constexpr int RF_TEAMS = RF_THREADS / RF_TEAM;
 constexpr int RF_QUERIES = 256;                     // queries per workgroup (16 per team)
 
-__device__ __forceinline__ void lex_min(float &best, int &bj, float d, int j) {
-    if (d < best || (d == best && j < bj)) {
-        best = d;
-        bj = j;
-    }
+// Every lane keeps the smallest (distance, index) key over the points it evaluates: the distance
+// as its float bits in the high word, the point's index in the low word.  A canonical distance is a
+// non-negative float or a NaN; non-negative floats order like their bits and every NaN pattern
+// orders above +inf, so a NaN never wins.  The initial key is +inf with the largest index, so an
+// infinite distance can still win on its index (the smallest index at +inf), as the exhaustive
+// search's first-smallest rule gives when no distance is finite.
+constexpr unsigned long long RF_NONE = (0x7F800000ull << 32) | 0xFFFFFFFFull;
+
+__device__ __forceinline__ unsigned canon_bits(float qx, float qy, float qz, float px, float py,
+                                               float pz) {
+    const float dx = qx - px;
+    const float dy = qy - py;
+    const float dz = qz - pz;
+    return __float_as_uint(__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)));
 }
 
-// rows i0 .. i0 + 3 (those below Na) of the point array P, as three 16-byte loads when whole
-__device__ __forceinline__ void run4(float &best, int &bj, float qx, float qy, float qz,
-                                     const float *P, int i0, int Na) {
-    float c[12];
-    if (i0 + 3 < Na) {
+// the points i0 .. i0 + 3 (those below Np) of P: their smallest key (the run's minimum and the
+// first of its indices that reaches it) folded into `key`
+__device__ __forceinline__ void run4_key(unsigned long long &key, float qx, float qy, float qz,
+                                         const float *P, int i0, int Np) {
+    unsigned d0, d1, d2, d3;
+    if (i0 + 3 < Np) {  // a whole run: three 16-byte loads
         const float4 *p4 = reinterpret_cast<const float4 *>(P + 3 * (size_t)i0);
         const float4 u0 = p4[0], u1 = p4[1], u2 = p4[2];
-        c[0] = u0.x; c[1] = u0.y; c[2] = u0.z; c[3] = u0.w;
-        c[4] = u1.x; c[5] = u1.y; c[6] = u1.z; c[7] = u1.w;
-        c[8] = u2.x; c[9] = u2.y; c[10] = u2.z; c[11] = u2.w;
-    } else {
-#pragma unroll
-        for (int k = 0; k < 12; ++k) c[k] = (i0 + k / 3 < Na) ? P[3 * (size_t)i0 + k] : 0.f;
+        d0 = canon_bits(qx, qy, qz, u0.x, u0.y, u0.z);
+        d1 = canon_bits(qx, qy, qz, u0.w, u1.x, u1.y);
+        d2 = canon_bits(qx, qy, qz, u1.z, u1.w, u2.x);
+        d3 = canon_bits(qx, qy, qz, u2.y, u2.z, u2.w);
+    } else {  // the end of the point array
+        const float *p = P + 3 * (size_t)i0;
+        d0 = i0 < Np ? canon_bits(qx, qy, qz, p[0], p[1], p[2]) : 0xFFFFFFFFu;
+        d1 = i0 + 1 < Np ? canon_bits(qx, qy, qz, p[3], p[4], p[5]) : 0xFFFFFFFFu;
+        d2 = i0 + 2 < Np ? canon_bits(qx, qy, qz, p[6], p[7], p[8]) : 0xFFFFFFFFu;
+        d3 = 0xFFFFFFFFu;
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        if (i0 + k < Na) lex_min(best, bj, canon_d2(qx, qy, qz, c + 3 * k), i0 + k);
+    const unsigned m = min(min(d0, d1), min(d2, d3));
+    const int first = d0 == m ? 0 : (d1 == m ? 1 : (d2 == m ? 2 : 3));
+    const unsigned long long k = ((unsigned long long)m << 32) | (unsigned)(i0 + first);
+    key = k < key ? k : key;
 }
 
-__device__ __forceinline__ void team_reduce(float &best, int &bj) {
-#pragma unroll
-    for (int off = RF_TEAM / 2; off > 0; off >>= 1) {
-        const float ob = __shfl_xor(best, off, RF_TEAM);
-        const int oj = __shfl_xor(bj, off, RF_TEAM);
-        lex_min(best, bj, ob, oj);
-    }
+// the smallest key over the 16 lanes of a team (a row of the wave for DPP): rotations by 8, 4, 2
+// and 1 lanes within the row.  Returns false when no key beat the initial one (every candidate
+// distance a NaN).
+template <int CTRL>
+__device__ __forceinline__ unsigned long long row_rotated(unsigned long long k) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)k, CTRL, 0xF, 0xF, false);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(k >> 32), CTRL, 0xF, 0xF, false);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ bool team_result(unsigned long long key, int &idx, float &dist) {
+    static_assert(RF_TEAM == 16, "a team is one DPP row");
+    unsigned long long o;
+    o = row_rotated<0x128>(key);  // row_ror:8
+    key = o < key ? o : key;
+    o = row_rotated<0x124>(key);  // row_ror:4
+    key = o < key ? o : key;
+    o = row_rotated<0x122>(key);  // row_ror:2
+    key = o < key ? o : key;
+    o = row_rotated<0x121>(key);  // row_ror:1
+    key = o < key ? o : key;
+    idx = (int)(unsigned)key;
+    dist = __uint_as_float((unsigned)(key >> 32));
+    return key != RF_NONE;
 }
 
 __device__ __forceinline__ void flush_stats(unsigned *cnt, unsigned long long *stats, int live,
@@ -856,9 +897,11 @@ __device__ __forceinline__ void flush_stats(unsigned *cnt, unsigned long long *s
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        atomicAdd(&stats[0], (unsigned long long)live);
-        atomicAdd(&stats[1], (unsigned long long)cnt[0]);
-        atomicAdd(&stats[2], (unsigned long long)cnt[1]);
+        unsigned long long *slot =
+            stats + (size_t)((blockIdx.x + gridDim.x * blockIdx.y) % STATS_SLOTS) * STATS_SLOT_WORDS;
+        atomicAdd(&slot[0], (unsigned long long)live);
+        atomicAdd(&slot[1], (unsigned long long)cnt[0]);
+        atomicAdd(&slot[2], (unsigned long long)cnt[1]);
     }
 }
 
@@ -883,8 +926,8 @@ __device__ __forceinline__ void stage_queries(const int32_t *rec, const float *Q
 }
 
 // Row refine (a -> b): candidate slot groups of light rows; heavy rows are left to the exact
-// kernel.  A team of 16 lanes takes one query; each 64-target step gives every lane 4 consecutive
-// targets (48 contiguous bytes).
+// kernel.  A team of 16 lanes takes one query; each 64-target step gives every lane one run of 4
+// consecutive targets (48 contiguous bytes).
 struct RefineParams {
     const float *Q;  // queries (rows a for the row refine, targets b for the column refine)
     const float *P;  // points searched (b, or a)
@@ -924,18 +967,19 @@ __device__ __forceinline__ void refine_body(const RefineParams &pr, const Blk &b
             qy = sq[3 * li + 1];
             qz = sq[3 * li + 2];
         }
-        float best = __builtin_inff();
-        int bj = 0x7fffffff;
+        unsigned long long key = RF_NONE;
 #pragma unroll 2
-        for (int e = 0; e < n * (SC_RUN / RF_STEP); ++e) {
-            const int code = rr[2 + e / (SC_RUN / RF_STEP)];
-            const int j = (code >> 4) * SC_CHUNK + SC_RUN * (code & 15) +
-                          RF_STEP * (e % (SC_RUN / RF_STEP)) + 4 * tl;
-            run4(best, bj, qx, qy, qz, Pt, j, Np);
+        for (int c = 0; c < n; ++c) {
+            const int code = rr[2 + c];
+            const int j0 = (code >> 4) * SC_CHUNK + SC_RUN * (code & 15) + 4 * tl;
+#pragma unroll
+            for (int e = 0; e < SC_RUN / RF_STEP; ++e) run4_key(key, qx, qy, qz, Pt, j0 + RF_STEP * e, Np);
         }
-        team_reduce(best, bj);
+        int bj;
+        float best;
+        const bool found = team_result(key, bj, best);
         if (n >= 0 && tl == 0) {
-            if (bj == 0x7fffffff) {  // nothing comparable (non-finite data): first index
+            if (!found) {  // nothing comparable (non-finite data): first index
                 bj = 0;
                 best = canon_d2(qx, qy, qz, Pt);
             }
@@ -955,8 +999,8 @@ __global__ __launch_bounds__(RF_THREADS) void k_refine(RefineParams p) {
     refine_body(p, grid_blk_xcd());
 }
 
-// Column refine (b -> a): each candidate workgroup contributes its winning row group (32 rows:
-// two per lane) or, when flagged ambiguous, all of its rows.
+// Column refine (b -> a): each candidate workgroup contributes its winning row group (48 rows:
+// 12 runs of 4) or, when flagged ambiguous, all of its rows.
 __device__ __forceinline__ void colrefine_body(const RefineParams &pr, const Blk &blk) {
     const float *__restrict__ B = pr.Q;
     const float *__restrict__ A = pr.P;
@@ -986,26 +1030,28 @@ __device__ __forceinline__ void colrefine_body(const RefineParams &pr, const Blk
             qy = sq[3 * lj + 1];
             qz = sq[3 * lj + 2];
         }
-        float best = __builtin_inff();
-        int bi = 0x7fffffff;
+        unsigned long long key = RF_NONE;
+#pragma unroll 2
         for (int e = 0; e < n; ++e) {
             const int code = rr[1 + e];
             const int wg = code >> 8, grp = code & 0x7f;
             const int wv = grp >> 1, h = grp & 1;
             if (code & 0x80) {  // ambiguous: every row of the workgroup, as runs of 4 rows
                 for (int u = tl; u < sc_rows<true>() / 4; u += RF_TEAM)
-                    run4(best, bi, qx, qy, qz, At, wg * sc_rows<true>() + 4 * u, Na);
-            } else {  // the row group: runs of rows 16a + 4g + (0..3) of its wave, g in {h, h+2}
-                for (int u = tl; u < 2 * sc_atiles<true>(); u += RF_TEAM)
-                    run4(best, bi, qx, qy, qz, At,
-                         wg * sc_rows<true>() + wv * (sc_atiles<true>() * 16) + 16 * (u >> 1) +
-                             4 * (h + 2 * (u & 1)),
+                    run4_key(key, qx, qy, qz, At, wg * sc_rows<true>() + 4 * u, Na);
+            } else if (tl < 2 * sc_atiles<true>()) {
+                // the row group: runs of rows 16a + 4g + (0..3) of its wave, g in {h, h + 2}
+                run4_key(key, qx, qy, qz, At,
+                         wg * sc_rows<true>() + wv * (sc_atiles<true>() * 16) + 16 * (tl >> 1) +
+                             4 * (h + 2 * (tl & 1)),
                          Na);
             }
         }
-        team_reduce(best, bi);
+        int bi;
+        float best;
+        const bool found = team_result(key, bi, best);
         if (n >= 0 && tl == 0) {
-            if (bi == 0x7fffffff) {
+            if (!found) {
                 bi = 0;
                 best = canon_d2(qx, qy, qz, At);
             }
@@ -1162,10 +1208,11 @@ void register_screen_kernels(BatchedKernel *table) {
                                       sc_atiles<true>() <= 4 ? 3 : 2>();
     table[KT_SCREEN_ROWS] = batched_kernel<ScreenParams, screen_body<false>, SC_THREADS, 768,
                                            sc_atiles<false>() <= 4 ? 3 : 2>();
-    // eight waves per SIMD (at most 64 registers), like the direct refine kernels: 2,048 blocks
-    table[KT_REFINE] = batched_kernel<RefineParams, refine_body, RF_THREADS, 2048, 8>();
+    // six waves per SIMD (at most 80 registers, which the refine bodies need without spilling):
+    // 1,536 blocks
+    table[KT_REFINE] = batched_kernel<RefineParams, refine_body, RF_THREADS, 1536, 6>();
     table[KT_COLMERGE] = batched_kernel<ColmergeParams, colmerge_body, CM_THREADS, 1024>();
-    table[KT_COLREFINE] = batched_kernel<RefineParams, colrefine_body, RF_THREADS, 2048, 8>();
+    table[KT_COLREFINE] = batched_kernel<RefineParams, colrefine_body, RF_THREADS, 1536, 6>();
 }
 
 }  // namespace dc
