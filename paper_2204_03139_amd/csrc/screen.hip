@@ -662,7 +662,13 @@ constexpr int CMAXC = 12;
 constexpr int CREC_INTS = 1 + CMAXC + 1;
 
 constexpr int CM_TPT = 2;    // targets per thread: one 32-bit word of two 16-bit partials
-constexpr int CM_CAP = 16;   // pending list entries per target, in LDS
+#ifndef DC_CM_CAP
+#define DC_CM_CAP 16
+#endif
+#ifndef DC_CM_BATCH
+#define DC_CM_BATCH 8
+#endif
+constexpr int CM_CAP = DC_CM_CAP;      // pending list entries per target, in LDS
 constexpr int CM_THREADS = 256;
 
 struct ColmergeParams {
@@ -708,43 +714,53 @@ __device__ __forceinline__ void colmerge_body(const ColmergeParams &pr, const Bl
     // row workgroup, the rows consecutive
     const int jb = __builtin_amdgcn_readfirstlane(j0 / CP_BLOCK);  // the same for the whole wave
     const uint16_t *block = cpart + part_index(t, nwg, Np_pad, 0, jb * CP_BLOCK);
-    // a partial passing the threshold of the running minimum goes on the list; the rest are
-    // skipped with one compare.  The threshold is taken at a value above the running minimum
-    // (the top of its code), and a partial passes when the bottom of its code does.  A full list
-    // drops the entries the current threshold excludes; if none can be dropped the target is made
-    // heavy (always correct: it is searched exhaustively).
-    auto consider = [&](int u, unsigned word, int w) {
-        if ((int)word <= lim[u]) {
-            if (cnt[u] == CM_CAP) {
-                int n = 0;
+    // The partials are taken in batches of CM_BATCH workgroups.  First the batch's smallest word
+    // of each target (packed 16-bit minima: words order like their codes) lowers the running
+    // minimum and the threshold is recomputed once, at a value above that minimum (the top of its
+    // code); then every partial of the batch whose word passes goes on the list.  The threshold
+    // only falls, so an entry it excludes at any point is excluded at the end.  A full list drops
+    // the entries the current threshold excludes; if none can be dropped the target is made heavy
+    // (always correct: it is searched exhaustively).
+    auto lower = [&](int u, unsigned mw) {
+        best[u] = min(best[u], (int)(mw >> 4));
+        lim[u] = part_word_limit(threshold_affine(part_hi(best[u], bias), slk[u]), bias);
+    };
+    auto append = [&](int u, unsigned word, int w) {
+        if ((int)word > lim[u] || over[u]) return;
+        if (cnt[u] == CM_CAP) {
+            int n = 0;
 #pragma unroll 1
-                for (int k = 0; k < CM_CAP; ++k) {
-                    const uint32_t e = pend[k][u][tid];
-                    if ((int)(e & 0xFFFFu) <= lim[u]) pend[n++][u][tid] = e;
-                }
-                cnt[u] = n;
-                if (n == CM_CAP) {
-                    over[u] = true;
-                    lim[u] = -1;
-                    return;
-                }
+            for (int k = 0; k < CM_CAP; ++k) {
+                const uint32_t e = pend[k][u][tid];
+                if ((int)(e & 0xFFFFu) <= lim[u]) pend[n++][u][tid] = e;
             }
-            pend[cnt[u]++][u][tid] = ((uint32_t)w << 16) | word;
-            best[u] = min(best[u], (int)(word >> 4));
-            lim[u] = part_word_limit(threshold_affine(part_hi(best[u], bias), slk[u]), bias);
+            cnt[u] = n;
+            if (n == CM_CAP) {
+                over[u] = true;
+                return;
+            }
+        }
+        pend[cnt[u]++][u][tid] = ((uint32_t)w << 16) | word;
+    };
+    typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
+    constexpr int CM_BATCH = DC_CM_BATCH;  // workgroups per batch
+    auto merge_batch = [&](const unsigned *v, int nk, int w) {
+        ushort2_t m = {(unsigned short)0xFFFFu, (unsigned short)0xFFFFu};
+        for (int k = 0; k < nk; ++k) m = __builtin_elementwise_min(m, __builtin_bit_cast(ushort2_t, v[k]));
+        lower(0, m.x);
+        lower(1, m.y);
+        // nothing of the batch passes for either target: the common case, one test per lane
+        if ((int)m.x > lim[0] && (int)m.y > lim[1]) return;
+        for (int k = 0; k < nk; ++k) {
+            append(0, v[k] & 0xFFFFu, w + k);
+            append(1, v[k] >> 16, w + k);
         }
     };
-    // the two 16-bit partials of one workgroup for this thread's targets, as one word
-    auto merge2 = [&](unsigned v, int w) {
-        consider(0, v & 0xFFFFu, w);
-        consider(1, v >> 16, w);
-    };
-    // eight workgroups' partials per batch, the next batch's loads in flight while this batch is
-    // compared.  Each batch reads through a buffer resource based at its first row, so a load's
-    // address is the uniform row offset (scalar) plus the lane's offset: no per-lane 64-bit
-    // address math.  The loads are unconditional (the last whole batch re-reads itself, unused),
-    // so the waits fall on the batch being compared only.
-    constexpr int CM_BATCH = 8;
+    // the next batch's loads in flight while this batch is merged.  Each batch reads through a
+    // buffer resource based at its first row, so a load's address is the uniform row offset
+    // (scalar) plus the lane's offset: no per-lane 64-bit address math.  The loads are
+    // unconditional (the last whole batch re-reads itself, unused), so the waits fall on the
+    // batch being merged only.
     static_assert(CP_BLOCK == 64 * CM_TPT, "one wave reads one block");
     const unsigned row_bytes = (unsigned)CP_BLOCK * 2u;
     const unsigned lane_bytes = (unsigned)(j0 % CP_BLOCK) * 2u;
@@ -764,11 +780,15 @@ __device__ __forceinline__ void colmerge_body(const ColmergeParams &pr, const Bl
 #pragma unroll
         for (int k = 0; k < CM_BATCH; ++k) cur[k] = nxt[k];
         load_batch(w + CM_BATCH < nfull ? w + CM_BATCH : w, nxt);
-#pragma unroll
-        for (int k = 0; k < CM_BATCH; ++k) merge2(cur[k], w + k);
+        merge_batch(cur, CM_BATCH, w);
     }
-    for (; w < nwg; ++w)
-        merge2(*reinterpret_cast<const unsigned *>(block + (size_t)w * CP_BLOCK + j0 % CP_BLOCK), w);
+    if (w < nwg) {  // the last, partial batch
+        unsigned cur[CM_BATCH];
+        const int nk = nwg - w;
+        for (int k = 0; k < nk; ++k)
+            cur[k] = *reinterpret_cast<const unsigned *>(block + (size_t)(w + k) * CP_BLOCK + j0 % CP_BLOCK);
+        merge_batch(cur, nk, w);
+    }
 #pragma unroll
     for (int u = 0; u < CM_TPT; ++u) {
         const int j = j0 + u;
