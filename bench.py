@@ -36,8 +36,8 @@ SCREEN_ISSUE_CEILING = CUS * SIMDS_PER_CU * PEAK_CLOCK_HZ / (5 * 4) * 256
 # valid only for the machine code they were measured on (sha256 of the kernel's bytes in the
 # built library's gfx950 code object).
 SCREEN_SYMBOL = "_ZN2dc12_GLOBAL__N_18k_screenILb1EEEvNS0_12ScreenParamsE"
-SCREEN_TRAFFIC = dict(code_sha256="0ae043d4b324d96073aa4268471a3da68b5f4c49f41313217d634f6aeb47f66f",
-                      bytes=1117925 * 1024 * 2 + 3488129 * 1024)
+SCREEN_TRAFFIC = dict(code_sha256="a5bc054d2d0eb0743e1307b687d7596efe23b327eda35997f861a515d0c74708",
+                      bytes=1117123 * 1024 * 2 + 2393675 * 1024)
 LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2204_03139_amd",
                    "libdiffcloud.so")
 
@@ -443,14 +443,16 @@ def main():
             paths[name] = dict(error=str(e))
             continue
         nn_ms, nn_n = kt["all_pairs"]
-        # every all-pairs launch covers every pair of every frame: the fp32 path launches its
-        # one-pass search (and its column merge) once, the screen once for both directions
-        per_launch_pairs = pairs
+        # the all-pairs launches of one step cover every pair of every frame once: the fp32 path
+        # launches its one-pass search (and its column merge) once, the screen once for both
+        # directions
+        per_launch_pairs = pairs * a.steps / max(nn_n, 1)
         avg = nn_ms / max(nn_n, 1)
         paths[name] = dict(pairs_per_s=pairs / (ms * 1e-3), ms_per_step=ms,
                            kernel_ms={k: v[0] / a.steps for k, v in kt.items()},
                            kernel_launches={k: v[1] // a.steps for k, v in kt.items()},
                            all_pairs_avg_launch_ms=avg,
+                           all_pairs_ms_per_step=nn_ms / a.steps,
                            all_pairs_pairs_per_s=per_launch_pairs / (avg * 1e-3) if avg else None,
                            loss_sum=loss, screen_stats=stats)
     ok = {k: v for k, v in paths.items() if "error" not in v and not k.endswith("_eq2")}
