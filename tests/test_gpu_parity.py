@@ -233,9 +233,13 @@ def test_chamfer_ties_and_identity(precision):
     _check_chamfer(g, o)
 
 
+# query rows per workgroup of the two-direction screen (the column partials are per workgroup)
+WG_ROWS = 384
+
+
 def _periodic_rows(n_rows, period=37, seed=41):
-    """Rows repeating `period` points: every 256-row workgroup holds the same points, so each
-    target's column partials tie exactly across all workgroups."""
+    """Rows repeating `period` points: every row workgroup holds the same points, so each target's
+    column partials tie exactly across all workgroups."""
     r = np.random.default_rng(seed)
     P = r.uniform(-.5, .5, (period, 3)).astype(np.float32)
     A = P[np.arange(n_rows) % period][None]
@@ -244,26 +248,26 @@ def _periodic_rows(n_rows, period=37, seed=41):
 
 
 def _descending_rows(seed=43):
-    """32 workgroups of 256 rows; target 0 (the origin) has one near row per workgroup at a
-    squared distance that falls by 0.15% per workgroup, the other rows lie on a sphere of radius
-    2.  The column merge keeps every near row on its list as it arrives and must drop the early
-    ones once they leave the threshold of the falling minimum."""
+    """32 row workgroups; target 0 (the origin) has one near row per workgroup at a squared
+    distance that falls by 0.15% per workgroup, the other rows lie on a sphere of radius 2.  The
+    column merge keeps every near row on its list as it arrives and must drop the early ones once
+    they leave the threshold of the falling minimum."""
     r = np.random.default_rng(seed)
-    u = r.normal(size=(8192, 3))
+    u = r.normal(size=(32 * WG_ROWS, 3))
     u /= np.linalg.norm(u, axis=1, keepdims=True)
     A = 2.0 * u
     for w in range(32):
-        A[256 * w + 5] = np.sqrt(0.1 * (1 - 0.0015 * w)) * u[256 * w + 5]
+        A[WG_ROWS * w + 5] = np.sqrt(0.1 * (1 - 0.0015 * w)) * u[WG_ROWS * w + 5]
     B = r.uniform(-.5, .5, (1, 100, 3))
     B[0, 0] = 0.0
     return A[None].astype(np.float32), B.astype(np.float32)
 
 
 COLUMN_MERGE_CASES = {
-    "ties-32-workgroups": lambda: _periodic_rows(32 * 256),   # list overflows: heavy
-    "ties-14-workgroups": lambda: _periodic_rows(14 * 256),   # 14 candidates > 12: heavy
-    "ties-12-workgroups": lambda: _periodic_rows(12 * 256),   # 12 candidates, full rescans
-    "descending-minimum": _descending_rows,                   # stale list entries dropped
+    "ties-32-workgroups": lambda: _periodic_rows(32 * WG_ROWS),   # list overflows: heavy
+    "ties-14-workgroups": lambda: _periodic_rows(14 * WG_ROWS),   # 14 candidates > 12: heavy
+    "ties-12-workgroups": lambda: _periodic_rows(12 * WG_ROWS),   # 12 candidates, full rescans
+    "descending-minimum": _descending_rows,                       # stale list entries dropped
 }
 
 
@@ -280,6 +284,27 @@ def test_column_merge_ties_and_list_overflow(case, precision):
     _check_chamfer(g, o)
     if case.startswith("ties"):
         assert np.all(g["idx_b"] < 37)
+
+
+@pytest.mark.parametrize("scale", [1e-12, 1e-6, 1e6, 1e12])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_coordinate_scales(scale, precision):
+    """The screen's certificate scales with the points' norms and its column partials are coded
+    over 32 binades placed by each frame's largest norm: clouds at very small and very large
+    scales, next to a frame at unit scale and one at the square root of the scale in the same
+    call, give the exhaustive search's indices and distances in both directions."""
+    p = gpu()
+    say(f"[chamfer] scale {scale:g} precision={precision}")
+    r = np.random.default_rng(71)
+    A = r.uniform(-.5, .5, (3, 5000, 3))
+    B = r.uniform(-.5, .5, (3, 4100, 3))
+    B[:, :50] = A[:, :50] + r.normal(scale=1e-4, size=(3, 50, 3))  # near pairs
+    for t, f in enumerate((scale, 1.0, np.sqrt(scale))):
+        A[t] *= f
+        B[t] *= f
+    A, B = A.astype(np.float32), B.astype(np.float32)
+    g, o = _chamfer_both(p, A, B, precision=precision)
+    _check_chamfer(g, o)
 
 
 def _few_heavy(n, seed):
