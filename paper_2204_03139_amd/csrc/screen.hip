@@ -945,6 +945,35 @@ __device__ __forceinline__ void stage_queries(const int32_t *rec, const float *Q
     }
 }
 
+// The order in which the teams take the workgroup's queries: sorted by candidate count (a counting
+// sort in LDS), so the four teams of a wave, which loop together, get queries of equal count and
+// no lane idles through another team's longer list.  Each query's result does not depend on the
+// order (heavy queries, count -1, and the slots past the last query sort first).
+constexpr int RF_BINS = 16;  // counts -2 .. 13 and above
+static_assert(RF_QUERIES == RF_THREADS, "one staged query per thread");
+template <int INTS>
+__device__ __forceinline__ void order_queries(const int32_t *srec, int nq, int *bins,
+                                              int16_t *order) {
+    const int q = threadIdx.x;
+    const int n = q < nq ? srec[q * INTS] : -2;
+    const int key = min(n + 2, RF_BINS - 1);
+    if (q < RF_BINS) bins[q] = 0;
+    __syncthreads();
+    atomicAdd(&bins[key], 1);
+    __syncthreads();
+    if (q == 0) {
+        int sum = 0;
+        for (int k = 0; k < RF_BINS; ++k) {
+            const int c = bins[k];
+            bins[k] = sum;
+            sum += c;
+        }
+    }
+    __syncthreads();
+    order[atomicAdd(&bins[key], 1)] = (int16_t)q;
+    __syncthreads();
+}
+
 // Row refine (a -> b): candidate slot groups of light rows; heavy rows are left to the exact
 // kernel.  A team of 16 lanes takes one query; each 64-target step gives every lane one run of 4
 // consecutive targets (48 contiguous bytes).
@@ -971,13 +1000,16 @@ __device__ __forceinline__ void refine_body(const RefineParams &pr, const Blk &b
     __shared__ float sq[RF_QUERIES * 3];
     const int t = blk.y;
     if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+    __shared__ int bins[RF_BINS];
+    __shared__ int16_t order[RF_QUERIES];
     stage_queries<REC_INTS>(rec, Q, t, Nq, blk.x * RF_QUERIES, srec, sq);
     __syncthreads();
+    order_queries<REC_INTS>(srec, min(RF_QUERIES, Nq - blk.x * RF_QUERIES), bins, order);
     const int team = threadIdx.x / RF_TEAM, tl = threadIdx.x % RF_TEAM;
     const float *Pt = P + (size_t)t * Np * 3;
     unsigned my_cand = 0, my_heavy = 0;
     for (int qq = 0; qq < RF_QUERIES / RF_TEAMS; ++qq) {
-        const int li = qq * RF_TEAMS + team;
+        const int li = order[qq * RF_TEAMS + team];
         const int i = blk.x * RF_QUERIES + li;
         const int32_t *rr = srec + li * REC_INTS;
         const int n = (i < Nq) ? rr[0] : -2;
@@ -1034,13 +1066,16 @@ __device__ __forceinline__ void colrefine_body(const RefineParams &pr, const Blk
     __shared__ float sq[RF_QUERIES * 3];
     const int t = blk.y;
     if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+    __shared__ int bins[RF_BINS];
+    __shared__ int16_t order[RF_QUERIES];
     stage_queries<CREC_INTS>(crec, B, t, Nb, blk.x * RF_QUERIES, srec, sq);
     __syncthreads();
+    order_queries<CREC_INTS>(srec, min(RF_QUERIES, Nb - blk.x * RF_QUERIES), bins, order);
     const int team = threadIdx.x / RF_TEAM, tl = threadIdx.x % RF_TEAM;
     const float *At = A + (size_t)t * Na * 3;
     unsigned my_cand = 0, my_heavy = 0;
     for (int qq = 0; qq < RF_QUERIES / RF_TEAMS; ++qq) {
-        const int lj = qq * RF_TEAMS + team;
+        const int lj = order[qq * RF_TEAMS + team];
         const int j = blk.x * RF_QUERIES + lj;
         const int32_t *rr = srec + lj * CREC_INTS;
         const int n = (j < Nb) ? rr[0] : -2;
