@@ -93,21 +93,32 @@ __global__ __launch_bounds__(SB_THREADS) void k_ss_hist(SortPassParams p) {
     ss_hist_body(p, grid_blk_xcd());
 }
 
-// exclusive prefix over (digit, block) of one frame, in place: each thread sums a contiguous run,
-// the runs' totals are scanned across the workgroup (in-wave shuffles, then the 16 wave totals),
-// and each thread rewrites its run from its exclusive start
+// exclusive prefix over (digit, block) of one frame, in place: each thread sums a contiguous run
+// (a multiple of four entries, read and written as 16-byte vectors whose loads are issued
+// together), the runs' totals are scanned across the workgroup (in-wave shuffles, then the 16 wave
+// totals), and each thread rewrites its run from its exclusive start.  The counts of a frame start
+// at a multiple of 256 entries, so the vectors are aligned.
 constexpr int SCAN_THREADS = 1024;
+constexpr int SCAN_UNROLL = 4;  // 16-byte vectors per batch of loads
 __device__ __forceinline__ void ss_scan_body(const SortPassParams &pr, const Blk &b) {
     __shared__ int wsum[SCAN_THREADS / 64];
     const int nblk = pr.nblk;
     const int t = b.x;
     int32_t *c = pr.counts + (size_t)t * BINS * nblk;
-    const int n = BINS * nblk;
-    const int per = (n + SCAN_THREADS - 1) / SCAN_THREADS;
+    const int n = BINS * nblk;  // a multiple of 256, so of 4
+    const int per = ((n + SCAN_THREADS - 1) / SCAN_THREADS + 3) & ~3;
     const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int4 *c4 = reinterpret_cast<int4 *>(c);
+    const int lo4 = lo / 4, hi4 = hi / 4;  // lo and hi are multiples of 4
     int s = 0;
-    for (int k = lo; k < hi; ++k) s += c[k];
+    for (int k = lo4; k < hi4; k += SCAN_UNROLL) {
+        int4 v[SCAN_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SCAN_UNROLL; ++u) v[u] = (k + u < hi4) ? c4[k + u] : make_int4(0, 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < SCAN_UNROLL; ++u) s += v[u].x + v[u].y + v[u].z + v[u].w;
+    }
     int incl = s;  // inclusive scan of the run totals inside the wave
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -119,10 +130,24 @@ __device__ __forceinline__ void ss_scan_body(const SortPassParams &pr, const Blk
     int before = 0;
     for (int w = 0; w < wave; ++w) before += wsum[w];
     int acc = before + incl - s;
-    for (int k = lo; k < hi; ++k) {
-        const int v = c[k];
-        c[k] = acc;
-        acc += v;
+    for (int k = lo4; k < hi4; k += SCAN_UNROLL) {
+        int4 v[SCAN_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SCAN_UNROLL; ++u) v[u] = (k + u < hi4) ? c4[k + u] : make_int4(0, 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < SCAN_UNROLL; ++u) {
+            if (k + u >= hi4) break;
+            int4 o;
+            o.x = acc;
+            acc += v[u].x;
+            o.y = acc;
+            acc += v[u].y;
+            o.z = acc;
+            acc += v[u].z;
+            o.w = acc;
+            acc += v[u].w;
+            c4[k + u] = o;
+        }
     }
 }
 
