@@ -9,19 +9,6 @@ namespace {
 
 constexpr int BW_THREADS = 256;
 
-// first position p in sorted[0..n) with sorted[p] >= key
-__device__ __forceinline__ int lower_bound(const int32_t *sorted, int n, int key) {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (sorted[mid] < key)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 // g_x[t,i] = g_t w_t ( cs * (x_i - y_{nn_x[i]}) + cm * sum_{j: nn_y[j]=i} (x_i - y_j) )
 // for x = a (cs = 2 alpha, cm = 2 beta) or x = b (cs = 2 beta, cm = 2 alpha).
 struct ChamferBwdParams {
@@ -29,7 +16,7 @@ struct ChamferBwdParams {
     const float *X;
     const float *Y;
     const int32_t *nn_x;
-    const int32_t *ykeys_sorted;
+    const int32_t *ystart;        // [T][Nx + 1]: first sorted position of each neighbour in x
     const int32_t *yvals_sorted;
     const float *frame_w;
     float *gX;
@@ -42,7 +29,7 @@ __device__ __forceinline__ void chamfer_bwd_body(const ChamferBwdParams &pr, con
     const float *__restrict__ X = pr.X;
     const float *__restrict__ Y = pr.Y;
     const int32_t *__restrict__ nn_x = pr.nn_x;
-    const int32_t *__restrict__ ykeys_sorted = pr.ykeys_sorted;
+    const int32_t *__restrict__ ystart = pr.ystart;
     const int32_t *__restrict__ yvals_sorted = pr.yvals_sorted;
     const int Nx = pr.Nx, Ny = pr.Ny;
     const double cself = pr.cself, cmutual = pr.cmutual;
@@ -68,11 +55,11 @@ __device__ __forceinline__ void chamfer_bwd_body(const ChamferBwdParams &pr, con
         g2 = cs * (x2 - yt[3 * (size_t)j + 2]);
     }
     if (cm != 0.f) {
-        const int32_t *ks = ykeys_sorted + (size_t)t * Ny;
         const int32_t *vs = yvals_sorted + (size_t)t * Ny;
-        const int lo = lower_bound(ks, Ny, i);
+        const int32_t *st = ystart + (size_t)t * (Nx + 1);
+        const int lo = st[i], hi = st[i + 1];
         float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-        for (int p = lo; p < Ny && ks[p] == i; ++p) {
+        for (int p = lo; p < hi; ++p) {
             const int j = vs[p];
             s0 += x0 - yt[3 * (size_t)j];
             s1 += x1 - yt[3 * (size_t)j + 1];
@@ -92,7 +79,10 @@ __global__ __launch_bounds__(BW_THREADS) void k_chamfer_bwd(ChamferBwdParams p) 
     chamfer_bwd_body(p, grid_blk_xcd());
 }
 
-// face_start[t][f] = first sorted position whose face is >= f, for f in [0, F]
+// start[t][k] = first position of the sorted keys of frame t whose key is >= k, for k in [0, K]
+// (the sort clamps its keys into [0, K]).  The thread of position q in [0, N] writes the entries
+// of the keys in (key[q-1], key[q]] (key[-1] = -1, key[N] = K), so every entry is written exactly
+// once, by adjacent differences instead of a binary search per key.
 struct BoundsParams {
     const int32_t *sorted;
     int32_t *start;
@@ -101,9 +91,13 @@ struct BoundsParams {
 
 __device__ __forceinline__ void bounds_body(const BoundsParams &p, const Blk &blk) {
     const int t = blk.y;
-    const int f = blk.x * BW_THREADS + threadIdx.x;
-    if (f > p.K) return;
-    p.start[(size_t)t * (p.K + 1) + f] = lower_bound(p.sorted + (size_t)t * p.N, p.N, f);
+    const int q = blk.x * BW_THREADS + threadIdx.x;
+    if (q > p.N) return;
+    const int32_t *s = p.sorted + (size_t)t * p.N;
+    const int lo = q == 0 ? -1 : min(s[q - 1], p.K);
+    const int hi = q == p.N ? p.K : min(s[q], p.K);
+    int32_t *st = p.start + (size_t)t * (p.K + 1);
+    for (int k = lo + 1; k <= hi; ++k) st[k] = q;
 }
 
 __global__ __launch_bounds__(BW_THREADS) void k_bounds(BoundsParams p) { bounds_body(p, grid_blk()); }
@@ -195,8 +189,11 @@ __global__ __launch_bounds__(BW_THREADS) void k_vertex_grad(VertexGradParams p) 
 }  // namespace
 
 size_t chamfer_bwd_scratch_bytes(int T, int Na, int Nb, bool want_b) {
-    size_t s = 2 * Arena::need((size_t)T * Nb, 4) + segsort_scratch_bytes(T, Nb);
-    if (want_b) s += 2 * Arena::need((size_t)T * Na, 4) + segsort_scratch_bytes(T, Na);
+    size_t s = 2 * Arena::need((size_t)T * Nb, 4) + segsort_scratch_bytes(T, Nb) +
+               Arena::need((size_t)T * (Na + 1), 4);
+    if (want_b)
+        s += 2 * Arena::need((size_t)T * Na, 4) + segsort_scratch_bytes(T, Na) +
+             Arena::need((size_t)T * (Nb + 1), 4);
     return s;
 }
 
@@ -214,13 +211,22 @@ void launch_chamfer_bwd(const double *grad_loss, const float *a, const float *b,
     int32_t *kb = ar.take<int32_t>((size_t)T * Nb);
     int32_t *vb = ar.take<int32_t>((size_t)T * Nb);
     char *ssb = ar.take<char>(segsort_scratch_bytes(T, Nb));
-    if (beta != 0.0) launch_segsort(idx_b, T, Nb, Na, kb, vb, ssb, s);
+    int32_t *sb = ar.take<int32_t>((size_t)T * (Na + 1));
+    if (beta != 0.0) {
+        launch_segsort(idx_b, T, Nb, Na, kb, vb, ssb, s);
+        BoundsParams bp;
+        bp.sorted = kb;
+        bp.start = sb;
+        bp.N = Nb;
+        bp.K = Na;
+        dispatch(KT_BOUNDS, k_bounds, dim3((Nb + BW_THREADS) / BW_THREADS, T), BW_THREADS, bp, s);
+    }
     ChamferBwdParams cp;
     cp.grad_loss = grad_loss;
     cp.X = a;
     cp.Y = b;
     cp.nn_x = idx_a;
-    cp.ykeys_sorted = kb;
+    cp.ystart = sb;
     cp.yvals_sorted = vb;
     cp.frame_w = frame_w;
     cp.gX = grad_a;
@@ -234,13 +240,20 @@ void launch_chamfer_bwd(const double *grad_loss, const float *a, const float *b,
         int32_t *ka = ar.take<int32_t>((size_t)T * Na);
         int32_t *va = ar.take<int32_t>((size_t)T * Na);
         char *ssa = ar.take<char>(segsort_scratch_bytes(T, Na));
+        int32_t *sa = ar.take<int32_t>((size_t)T * (Nb + 1));
         launch_segsort(idx_a, T, Na, Nb, ka, va, ssa, s);
+        BoundsParams bq;
+        bq.sorted = ka;
+        bq.start = sa;
+        bq.N = Na;
+        bq.K = Nb;
+        dispatch(KT_BOUNDS, k_bounds, dim3((Na + BW_THREADS) / BW_THREADS, T), BW_THREADS, bq, s);
         ChamferBwdParams cq;
         cq.grad_loss = grad_loss;
         cq.X = b;
         cq.Y = a;
         cq.nn_x = idx_b;
-        cq.ykeys_sorted = ka;
+        cq.ystart = sa;
         cq.yvals_sorted = va;
         cq.frame_w = frame_w;
         cq.gX = grad_b;
@@ -282,14 +295,14 @@ void launch_sample_bwd(const float *grad_points, const int32_t *faces, const int
     bp.start = fstart;
     bp.N = N;
     bp.K = F;
-    dispatch(KT_BOUNDS, k_bounds, dim3((F + BW_THREADS) / BW_THREADS, T), BW_THREADS, bp, s);
+    dispatch(KT_BOUNDS, k_bounds, dim3((N + BW_THREADS) / BW_THREADS, T), BW_THREADS, bp, s);
     // (face, corner) slots grouped by vertex: the vertex-incidence CSR of the topology
     launch_segsort(faces, 1, 3 * F, V, ck, cv, ss2, s);
     bp.sorted = ck;
     bp.start = vstart;
     bp.N = 3 * F;
     bp.K = V;
-    dispatch(KT_BOUNDS, k_bounds, dim3((V + BW_THREADS) / BW_THREADS, 1), BW_THREADS, bp, s);
+    dispatch(KT_BOUNDS, k_bounds, dim3((3 * F + BW_THREADS) / BW_THREADS, 1), BW_THREADS, bp, s);
     FaceGradParams fp;
     fp.gpts = grad_points;
     fp.bary = bary;

@@ -112,7 +112,7 @@ const int PROGRAM[] = {
     KT_NN8,       KT_NN4,      KT_NN1,      KT_NN_MERGE,   // exact a -> b (or its heavy rows)
     KT_COLMERGE,  KT_COLREFINE,                            // screen, columns
     KT_NN8,       KT_NN4,      KT_NN1,      KT_NN_MERGE,   // exact b -> a (or its heavy columns)
-    KT_LOSS,      KT_FILL_F64, SORT_PASSES, KT_CHAMFER_BWD,                    // Chamfer bwd
+    KT_LOSS,      KT_FILL_F64, SORT_PASSES, KT_BOUNDS, KT_CHAMFER_BWD,         // Chamfer bwd
     SORT_PASSES,  KT_BOUNDS,   SORT_PASSES, KT_BOUNDS,  KT_FACE_GRAD, KT_VERTEX_GRAD};
 #undef SORT_PASSES
 constexpr int NPROG = (int)(sizeof(PROGRAM) / sizeof(PROGRAM[0]));
