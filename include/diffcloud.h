@@ -176,7 +176,8 @@ int dc_chamfer_fwd(dc_ctx *ctx, const float *a, const float *b, int T, int Na, i
  *   grad_a[t,i] = g_t w_t ( 2 alpha (a_i - b_{idx_a[i]}) + 2 beta sum_{j: idx_b[j]=i} (a_i - b_j) )
  *   grad_b[t,j] = g_t w_t ( 2 beta (b_j - a_{idx_b[j]}) + 2 alpha sum_{i: idx_a[i]=j} (b_j - a_i) )
  * The sums over j (resp. i) run in increasing index order after a stable, atomic-free sort by
- * neighbour index, so results are bitwise reproducible.
+ * neighbour index, so results are bitwise reproducible.  A neighbour index outside [0, Nb) (resp.
+ * [0, Na)) contributes nothing: neither its own term nor a term to the point it names.
  *   grad_loss device double [T]; a, b, idx_a, idx_b, frame_w as in dc_chamfer_fwd (idx_b is not
  *   read with DC_RED_SIM2REAL_SUM, where beta = 0, and may then be NULL);
  *   grad_a device float [T,Na,3] out (overwritten); grad_b device float [T,Nb,3] or NULL.

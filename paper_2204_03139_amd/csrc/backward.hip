@@ -61,6 +61,7 @@ __device__ __forceinline__ void chamfer_bwd_body(const ChamferBwdParams &pr, con
         float s0 = 0.f, s1 = 0.f, s2 = 0.f;
         for (int p = lo; p < hi; ++p) {
             const int j = vs[p];
+            if (j < 0) continue;  // a neighbour index outside [0, Nx): contributes nothing
             s0 += x0 - yt[3 * (size_t)j];
             s1 += x1 - yt[3 * (size_t)j + 1];
             s2 += x2 - yt[3 * (size_t)j + 2];
@@ -213,7 +214,8 @@ void launch_chamfer_bwd(const double *grad_loss, const float *a, const float *b,
     char *ssb = ar.take<char>(segsort_scratch_bytes(T, Nb));
     int32_t *sb = ar.take<int32_t>((size_t)T * (Na + 1));
     if (beta != 0.0) {
-        launch_segsort(idx_b, T, Nb, Na, kb, vb, ssb, s);
+        // valid neighbours lie in [0, Na): Na - 1 is the key limit, out-of-range ones are marked
+        launch_segsort(idx_b, T, Nb, Na - 1, kb, vb, ssb, s, true);
         BoundsParams bp;
         bp.sorted = kb;
         bp.start = sb;
@@ -241,7 +243,7 @@ void launch_chamfer_bwd(const double *grad_loss, const float *a, const float *b,
         int32_t *va = ar.take<int32_t>((size_t)T * Na);
         char *ssa = ar.take<char>(segsort_scratch_bytes(T, Na));
         int32_t *sa = ar.take<int32_t>((size_t)T * (Nb + 1));
-        launch_segsort(idx_a, T, Na, Nb, ka, va, ssa, s);
+        launch_segsort(idx_a, T, Na, Nb - 1, ka, va, ssa, s, true);
         BoundsParams bq;
         bq.sorted = ka;
         bq.start = sa;

@@ -155,10 +155,11 @@ void launch_loss(const float *dist_a, const float *dist_b, int T, int Na, int Nb
                  const float *frame_w, double *loss, hipStream_t s);
 
 // stable, atomic-free sort of per-frame keys in [0, key_limit]: out_keys/out_vals get the keys
-// and the original positions in (key, position) order.
+// and the original positions in (key, position) order.  Keys outside the range sort as key_limit;
+// with mark_invalid their value is the complement of their position (negative).
 size_t segsort_scratch_bytes(int T, int N);
 void launch_segsort(const int32_t *keys, int T, int N, int key_limit, int32_t *out_keys,
-                    int32_t *out_vals, char *scratch, hipStream_t s);
+                    int32_t *out_vals, char *scratch, hipStream_t s, bool mark_invalid = false);
 
 // Chamfer backward
 size_t chamfer_bwd_scratch_bytes(int T, int Na, int Nb, bool want_b);

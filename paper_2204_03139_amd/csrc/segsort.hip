@@ -11,7 +11,8 @@
 //                items, waves in order inside a round), and writes item e to
 //                offset[digit][block] + rank, which preserves the input order among equal keys.
 // No atomics anywhere, so the permutation is the same on every run.  Keys outside [0, limit] are
-// clamped to limit (they sort last).
+// clamped to limit (they sort last); with `mark_invalid` such an item also carries the complement
+// of its position (a negative value), so that a key range of exactly 2^k valid keys needs k bits.
 #include "batch.h"
 
 namespace dc {
@@ -22,11 +23,6 @@ constexpr int SB_WAVES = SB_THREADS / 64;
 constexpr int SB_ROUNDS = 4;
 constexpr int SB_ITEMS = SB_THREADS * SB_ROUNDS;  // items per block
 constexpr int BINS = 256;
-
-__device__ __forceinline__ int load_key(const int32_t *keys, size_t o, int limit) {
-    const int k = keys[o];
-    return (k < 0 || k > limit) ? limit : k;
-}
 
 // lanes of this wave whose `valid` item has the same digit as this lane
 __device__ __forceinline__ unsigned long long same_digit(bool valid, int d) {
@@ -45,11 +41,19 @@ struct SortIO {
     const int32_t *src_vals;
     const int32_t *keys;      // first pass input
     int limit;
+    int mark_invalid;         // first pass: an out-of-range key's value is ~position
 };
 
 __device__ __forceinline__ void read_item(const SortIO &io, size_t o, int e, int &key, int &val) {
-    key = io.src_keys ? io.src_keys[o] : load_key(io.keys, o, io.limit);
-    val = io.src_vals ? io.src_vals[o] : e;
+    if (io.src_keys) {
+        key = io.src_keys[o];
+        val = io.src_vals[o];
+        return;
+    }
+    const int k = io.keys[o];
+    const bool bad = k < 0 || k > io.limit;
+    key = bad ? io.limit : k;
+    val = (bad && io.mark_invalid) ? ~e : e;
 }
 
 struct SortPassParams {
@@ -219,7 +223,7 @@ size_t segsort_scratch_bytes(int T, int N) {
 }
 
 void launch_segsort(const int32_t *keys, int T, int N, int key_limit, int32_t *out_keys,
-                    int32_t *out_vals, char *scratch, hipStream_t s) {
+                    int32_t *out_vals, char *scratch, hipStream_t s, bool mark_invalid) {
     const size_t piece = Arena::need((size_t)T * N, 4);
     int32_t *tk[2] = {reinterpret_cast<int32_t *>(scratch),
                       reinterpret_cast<int32_t *>(scratch + 2 * piece)};
@@ -234,6 +238,7 @@ void launch_segsort(const int32_t *keys, int T, int N, int key_limit, int32_t *o
         SortIO io;
         io.keys = keys;
         io.limit = key_limit;
+        io.mark_invalid = mark_invalid ? 1 : 0;
         io.src_keys = p == 0 ? nullptr : tk[(p - 1) & 1];
         io.src_vals = p == 0 ? nullptr : tv[(p - 1) & 1];
         int32_t *dk = (p == passes - 1) ? out_keys : tk[p & 1];

@@ -307,6 +307,46 @@ def test_coordinate_scales(scale, precision):
     _check_chamfer(g, o)
 
 
+def test_chamfer_backward_ignores_out_of_range_neighbours():
+    """A neighbour index outside [0, N) contributes nothing to the Chamfer gradient (the
+    library's rule for indices it did not produce; the sort keeps such entries apart from the
+    last valid index).  Expected: the oracle's gradient for the valid indices, less the terms of
+    the entries made invalid, in double."""
+    p = gpu()
+    say("[chamfer] backward with out-of-range neighbour indices")
+    r = np.random.default_rng(81)
+    T, Na, Nb = 2, 3000, 2500
+    A = r.uniform(-.5, .5, (T, Na, 3)).astype(np.float32)
+    B = r.uniform(-.5, .5, (T, Nb, 3)).astype(np.float32)
+    o = oracle.chamfer(A, B)
+    ia, ib = o["idx_a"].copy(), o["idx_b"].copy()
+    alpha, beta = 1.0 / Na, 1.0 / Nb
+    bad_a = r.random((T, Na)) < 0.05
+    bad_b = r.random((T, Nb)) < 0.05
+    ib[:, -1] = Na - 1  # the largest valid key, next to the invalid ones
+    bad_b[:, -1] = False
+    og = oracle.chamfer_grad(A, B, ia, ib, want_b=True)
+    ga, gb, gaa, gba = og["ga"].copy(), og["gb"].copy(), og["ga_abs"], og["gb_abs"]
+    for t in range(T):
+        for i in np.nonzero(bad_a[t])[0]:
+            g = 2 * alpha * (A[t, i].astype(np.float64) - B[t, ia[t, i]])
+            ga[t, i] -= g
+            gb[t, ia[t, i]] += g
+        for j in np.nonzero(bad_b[t])[0]:
+            g = 2 * beta * (A[t, ib[t, j]].astype(np.float64) - B[t, j])
+            ga[t, ib[t, j]] -= g
+            gb[t, j] += g
+    vals_a = np.array([-1, Nb, 1 << 30], np.int32)
+    vals_b = np.array([-1, Na, 1 << 30], np.int32)
+    ia[bad_a] = vals_a[r.integers(0, 3, bad_a.sum())]
+    ib[bad_b] = vals_b[r.integers(0, 3, bad_b.sum())]
+    gA, gB = p.chamfer_bwd(torch.ones(T, dtype=torch.float64, device="cuda"), dev(A), dev(B),
+                           dev(ia), dev(ib), want_b=True)
+    torch.cuda.synchronize()
+    assert_grad(host(gA), ga, gaa, 1e-5, "grad_a")
+    assert_grad(host(gB), gb, gba, 1e-5, "grad_b")
+
+
 def _few_heavy(n, seed):
     """n x n points with a few queries the screen cannot settle in either direction: one row
     point repeated in every 256-row workgroup (so the targets near it tie across all of them)
