@@ -598,6 +598,38 @@ def test_backward_parity(cfg, T, reduction):
     assert_grad(host(gv), ogv, ogva, what="grad_verts")
 
 
+def _segment_cases():
+    """Shapes at the edges of the backward's segments: one row (every target's neighbour is
+    row 0: one segment holds every key), one target, all targets at one point (one segment of
+    the whole frame, the other keys empty at both ends), and a ragged size."""
+    r = np.random.default_rng(91)
+    u = lambda *s: r.uniform(-.5, .5, s).astype(np.float32)  # noqa: E731
+    same = np.repeat(u(2, 1, 3), 700, axis=1)
+    return {"one-row": (u(2, 1, 3), u(2, 7, 3)), "one-target": (u(1, 300, 3), u(1, 1, 3)),
+            "one-point-targets": (u(2, 900, 3), same), "ragged": (u(3, 1001, 3), u(3, 777, 3))}
+
+
+@pytest.mark.parametrize("case", ["one-row", "one-target", "one-point-targets", "ragged"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_backward_segment_edges(case, precision):
+    """The Chamfer backward at the edges of its neighbour segments, in both directions, against
+    the oracle's double gradient (indices from the forward equal the oracle's)."""
+    p = gpu()
+    say(f"[backward] segments {case} precision={precision}")
+    A, B = _segment_cases()[case]
+    T = A.shape[0]
+    gl = np.linspace(1.0, 0.25, T)
+    o = oracle.chamfer(A, B)
+    og = oracle.chamfer_grad(A, B, o["idx_a"], o["idx_b"], 0, None, gl, want_b=True)
+    f = p.chamfer_fwd(dev(A), dev(B), precision=precision)
+    ga, gb = p.chamfer_bwd(dev(gl), dev(A), dev(B), f["idx_a"], f["idx_b"], want_b=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(f["idx_a"]), o["idx_a"])
+    assert np.array_equal(host(f["idx_b"]), o["idx_b"])
+    assert_grad(host(ga), og["ga"], og["ga_abs"], what="grad_a")
+    assert_grad(host(gb), og["gb"], og["gb_abs"], what="grad_b")
+
+
 def test_determinism():
     p = gpu()
     w = gen.workload(3)
