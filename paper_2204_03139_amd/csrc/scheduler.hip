@@ -24,6 +24,7 @@
 // dc_poll moves them into the caller's buffers.  An event marks the batch's completion.  Every
 // request executes exactly the launches of its direct calls, so its results do not depend on
 // what it is batched with.
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -371,6 +372,79 @@ struct BatchSlot {
 
 }  // namespace
 
+// Host copies between the caller's buffers and pinned staging (request inputs at submit, vertex
+// gradients at poll): a copy of COPY_SPLIT_MIN bytes or more is cut into pieces of at least
+// COPY_PIECE_MIN bytes that a few worker threads copy beside the calling thread, which takes the
+// first piece and waits for the rest.  One thread's memcpy would bound the serving loop's
+// capacity: a mix of requests carries about a gigabyte of inputs.
+constexpr size_t COPY_SPLIT_MIN = size_t(1) << 20;
+constexpr size_t COPY_PIECE_MIN = size_t(1) << 19;
+constexpr int COPY_WORKERS = 7;
+
+struct CopyPool {
+    struct Piece {
+        char *dst;
+        const char *src;
+        size_t n;
+        std::atomic<int> *left;
+    };
+    std::mutex mu;
+    std::condition_variable cv, done;
+    std::deque<Piece> q;
+    std::vector<std::thread> th;
+    bool stop = false;
+
+    void start() {
+        for (int k = 0; k < COPY_WORKERS; ++k) th.emplace_back([this] { work(); });
+    }
+    void finish() {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            stop = true;
+        }
+        cv.notify_all();
+        for (auto &t : th) t.join();
+        th.clear();
+    }
+    void work() {
+        for (;;) {
+            Piece p;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [this] { return stop || !q.empty(); });
+                if (q.empty()) return;
+                p = q.front();
+                q.pop_front();
+            }
+            std::memcpy(p.dst, p.src, p.n);
+            if (p.left->fetch_sub(1) == 1) {
+                std::lock_guard<std::mutex> g(mu);
+                done.notify_all();
+            }
+        }
+    }
+    void copy(void *dst, const void *src, size_t n) {
+        char *d = static_cast<char *>(dst);
+        const char *s = static_cast<const char *>(src);
+        if (n < COPY_SPLIT_MIN || th.empty()) {
+            std::memcpy(d, s, n);
+            return;
+        }
+        const size_t k = std::min<size_t>(th.size() + 1, n / COPY_PIECE_MIN);
+        const size_t per = (n + k - 1) / k;
+        std::atomic<int> left((int)k - 1);
+        {
+            std::lock_guard<std::mutex> g(mu);
+            for (size_t i = 1; i < k; ++i)
+                q.push_back({d + i * per, s + i * per, std::min(per, n - i * per), &left});
+        }
+        cv.notify_all();
+        std::memcpy(d, s, per);
+        std::unique_lock<std::mutex> lk(mu);
+        done.wait(lk, [&left] { return left.load() == 0; });
+    }
+};
+
 struct Scheduler {
     dc_ctx *ctx = nullptr;
     std::mutex mu;
@@ -383,6 +457,7 @@ struct Scheduler {
     BatchedKernel kern[KT_COUNT] = {};
     BatchSlot slots[NSLOTS];
     std::thread th;
+    CopyPool copies;  // host copies of request inputs and results
     // device memory of admitted requests (scheduler thread only)
     SegPool dpool;
     size_t dev_seg = DEV_SEG_MIN;
@@ -687,6 +762,7 @@ static int ensure_scheduler(dc_ctx *ctx) {
         delete S;
         return rc;
     }
+    S->copies.start();
     S->th = std::thread(loop, S);
     ctx->sched = S;
     return DC_OK;
@@ -750,9 +826,9 @@ int sched_submit(dc_ctx *ctx, const dc_request *q, dc_result *out, uint64_t *tic
         return rc;
     }
     char *h = r->h_in.p;
-    std::memcpy(h + map.verts, q->verts, (size_t)q->T * q->V * 3 * 4);
-    std::memcpy(h + map.faces, q->faces, (size_t)q->F * 3 * 4);
-    std::memcpy(h + map.obs, q->observed, (size_t)q->T * q->n_obs * 3 * 4);
+    S->copies.copy(h + map.verts, q->verts, (size_t)q->T * q->V * 3 * 4);
+    S->copies.copy(h + map.faces, q->faces, (size_t)q->F * 3 * 4);
+    S->copies.copy(h + map.obs, q->observed, (size_t)q->T * q->n_obs * 3 * 4);
     if (r->has_w) std::memcpy(h + map.fw, q->frame_w, (size_t)q->T * 4);
     out->t_submit = now_s();
     out->t_admit = 0;
@@ -792,8 +868,8 @@ int sched_poll(dc_ctx *ctx, uint64_t ticket) {
     if (r->status == DC_OK) {
         std::memcpy(r->out->loss, h + (r->map.loss - r->map.in_bytes), (size_t)r->T * 8);
         if (r->want_grad)
-            std::memcpy(r->out->grad_verts, h + (r->map.gverts - r->map.in_bytes),
-                        (size_t)r->T * r->V * 3 * 4);
+            S->copies.copy(r->out->grad_verts, h + (r->map.gverts - r->map.in_bytes),
+                           (size_t)r->T * r->V * 3 * 4);
     }
     const int st = r->status;
     r->out->status = st;
@@ -814,6 +890,7 @@ void sched_destroy(dc_ctx *ctx) {
     }
     S->cv.notify_one();
     S->th.join();
+    S->copies.finish();
     for (auto &kv : S->table) delete kv.second;
     for (auto &sl : S->slots) release_slot(ctx, sl);
     release_pools(S);
