@@ -121,6 +121,24 @@ int dc_sample_surface_masked(dc_ctx *ctx, const float *verts, const int32_t *fac
                              const uint8_t *face_mask, int mask_per_frame, float *points,
                              int32_t *face_idx, float *bary, void *stream);
 
+/* The first two steps of dc_sample_surface on their own: the face areas and their running sum,
+ * the inverse-CDF table that Eq. 3's area-weighted choice of a face is drawn from (Sec. III-B).
+ *   verts, faces, T, V, F   as dc_sample_surface
+ *   face_mask  device uint8 [F] (mask_per_frame = 0) or [T,F] (mask_per_frame = 1), or NULL (all
+ *              faces): as dc_sample_surface_masked, a face outside the subset has A_f = 0
+ *   cdf        device double [T,F] out: C_k = C_{k-1} + A_k, left to right from C_{-1} = 0, each
+ *              sum rounded to double - bit for bit the plain sequential sum of the A_f, which are
+ *              computed exactly as in dc_sample_surface
+ *   last_face  device int32 [T] or NULL; out: the last face with A_k > 0 (the face drawn when
+ *              rounding leaves no C_k above r*S), -1 for a frame whose total is zero or not
+ *              finite or whose faces name a vertex outside [0, V)
+ * Errors: DC_ERR_INVALID (argument, or mask_per_frame not 0/1), DC_ERR_HIP, DC_ERR_NOMEM,
+ * DC_ERR_BUDGET; zero or non-finite totals and bad face indices are reported by dc_sync(), as for
+ * dc_sample_surface. */
+int dc_area_cdf(dc_ctx *ctx, const float *verts, const int32_t *faces, int T, int V, int F,
+                const uint8_t *face_mask, int mask_per_frame, double *cdf, int32_t *last_face,
+                void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid allocation): dc_sample_surface with the same arguments, arithmetic,
  * results and errors, except that its scratch - the per-frame area CDF in double and the last

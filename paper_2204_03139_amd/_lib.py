@@ -34,7 +34,7 @@ STATUS_NAMES = {0: "DC_OK", 1: "DC_PENDING", -1: "DC_ERR_INVALID", -2: "DC_ERR_N
 
 # every symbol the public header declares
 EXPORTS = ["dc_create", "dc_destroy", "dc_last_error", "dc_sync", "dc_sample_surface",
-           "dc_sample_surface_masked", "dc_rigid_pose", "dc_rigid_pose_bwd",
+           "dc_sample_surface_masked", "dc_area_cdf", "dc_rigid_pose", "dc_rigid_pose_bwd",
            "dc_sample_surface_bwd", "dc_chamfer_fwd", "dc_chamfer_bwd", "dc_get_stats",
            "dc_submit", "dc_poll", "dc_version", "dc_debug_fail_allocs", "dc_profile",
            "dc_get_kernel_times", "dc_request_bytes", "dc_memory_held",
@@ -94,6 +94,7 @@ def load():
     L.dc_sample_surface.argtypes = [vp, vp, vp, i, i, i, i, u64, vp, vp, vp, vp, vp]
     L.dc_sample_surface_masked.argtypes = [vp, vp, vp, i, i, i, i, u64, vp, vp, i, vp, vp, vp, vp]
     L.dc_sample_surface_noalloc.argtypes = [vp, vp, vp, i, i, i, i, u64, vp, vp, vp, vp, vp]
+    L.dc_area_cdf.argtypes = [vp, vp, vp, i, i, i, vp, i, vp, vp, vp]
     L.dc_rigid_pose.argtypes = [vp, vp, vp, vp, i, i, i, vp, vp]
     L.dc_rigid_pose_bwd.argtypes = [vp, vp, vp, vp, vp, i, i, i, vp, vp]
     L.dc_sample_surface_bwd.argtypes = [vp, vp, vp, vp, vp, i, i, i, i, vp, vp]
@@ -236,6 +237,28 @@ def sample_surface(verts, faces, N: int, seed: int = 0, uniforms=None, out=None,
         rc = load().dc_sample_surface_masked(*ins, m, int(per_frame), *outs)
         _check(rc, "dc_sample_surface_masked")
     return points, face_idx, bary
+
+
+def area_cdf(verts, faces, face_mask=None, out=None, ctx=None, stream=None):
+    """dc_area_cdf: returns (cdf [T,F] float64, last_face [T] int32) of the mesh (verts [T,V,3],
+    faces [F,3]); face_mask (uint8 [F] or [T,F]) restricts the faces as in sample_surface."""
+    ctx = ctx or default_context(verts.device.index)
+    T, V, _ = verts.shape
+    F = faces.shape[0]
+    if out is None:
+        cdf = torch.empty((T, F), dtype=torch.float64, device=verts.device)
+        last = torch.empty((T,), dtype=torch.int32, device=verts.device)
+    else:
+        cdf, last = out
+    per_frame = face_mask is not None and face_mask.dim() == 2
+    m = None if face_mask is None else _ptr(face_mask, torch.uint8, (T, F) if per_frame else (F,),
+                                            "face_mask")
+    rc = load().dc_area_cdf(ctx.handle, _ptr(verts, torch.float32, (T, V, 3), "verts"),
+                            _ptr(faces, torch.int32, (F, 3), "faces"), T, V, F, m, int(per_frame),
+                            _ptr(cdf, torch.float64, (T, F), "cdf"),
+                            _ptr(last, torch.int32, (T,), "last_face"), _stream(stream))
+    _check(rc, "dc_area_cdf")
+    return cdf, last
 
 
 def sample_surface_noalloc(verts, faces, N: int, out, seed: int = 0, uniforms=None, ctx=None,

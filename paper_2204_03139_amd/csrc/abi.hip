@@ -400,6 +400,29 @@ int dc_sample_surface_masked(dc_ctx *ctx, const float *verts, const int32_t *fac
                                mask_per_frame, points, face_idx, bary, stream);
 }
 
+int dc_area_cdf(dc_ctx *ctx, const float *verts, const int32_t *faces, int T, int V, int F,
+                const uint8_t *face_mask, int mask_per_frame, double *cdf, int32_t *last_face,
+                void *stream) {
+    clear_error();
+    if (!ctx || !verts || !faces || !cdf || (mask_per_frame != 0 && mask_per_frame != 1)) {
+        set_error("dc_area_cdf: NULL argument or mask_per_frame not 0/1");
+        return DC_ERR_INVALID;
+    }
+    int rc = check_dims(T, {V, F});
+    if (rc) return rc;
+    DC_HIP(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> g(ctx->mu);
+    // the kernel always writes the last faces: to scratch when the caller does not want them
+    rc = arena_reserve(ctx, sizeof(int32_t) * (size_t)T, static_cast<hipStream_t>(stream));
+    if (rc) return rc;
+    ArenaUse use{ctx, static_cast<hipStream_t>(stream)};
+    int32_t *lastpos = last_face ? last_face : ctx->arena.take<int32_t>((size_t)T);
+    ProfScope ps(ctx, 2, static_cast<hipStream_t>(stream));
+    launch_area_cdf(verts, faces, T, V, F, face_mask, face_mask ? mask_per_frame : 0, cdf,
+                    lastpos, ctx->d_status, static_cast<hipStream_t>(stream));
+    return launched("area_cdf launch");
+}
+
 int dc_sample_surface_bwd(dc_ctx *ctx, const float *grad_points, const int32_t *faces,
                           const int32_t *face_idx, const float *bary, int T, int V, int F, int N,
                           float *grad_verts, void *stream) {

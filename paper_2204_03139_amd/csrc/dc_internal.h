@@ -122,6 +122,11 @@ struct ProfScope {
 // ---------------------------------------------------------------- launchers (async, on `s`)
 // sampling
 size_t sample_scratch_bytes(int T, int F);
+// the per-frame face areas and their running sum (cdf [T,F] double, lastpos [T]: last face of
+// positive area, -1 for a degenerate frame or one with an invalid face)
+void launch_area_cdf(const float *verts, const int32_t *faces, int T, int V, int F,
+                     const uint8_t *mask, int mask_per_frame, double *cdf, int32_t *lastpos,
+                     unsigned *status, hipStream_t s);
 void launch_sample(const float *verts, const int32_t *faces, int T, int V, int F, int N,
                    uint64_t seed, const uint32_t *uniforms, const uint8_t *mask, int mask_per_frame,
                    float *points, int32_t *face_idx, float *bary, double *cdf_scratch,
