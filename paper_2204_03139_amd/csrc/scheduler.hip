@@ -365,6 +365,7 @@ struct BatchSlot {
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t nodes[MAX_STAGES] = {};
     bool enabled[MAX_STAGES] = {};
+    int grid[MAX_STAGES] = {};  // workgroups each node launches now
     hipEvent_t ev = nullptr;
     std::vector<Req *> reqs;
     bool busy = false;
@@ -571,6 +572,37 @@ static void finish_req(Scheduler *S, Req *r, bool on_device) {
     std::vector<OpRec>().swap(r->ops);
 }
 
+// workgroups of a stage's node: its persistent grid, or fewer when the batch has less work
+static int stage_grid(const BatchedKernel &k, int total) {
+    int g = 1;
+    while (g < total && g < k.blocks) g <<= 1;
+    return std::min(g, k.blocks);
+}
+
+// stage `st` of the slot's graph as a kernel node of `blocks` workgroups: added to the graph
+// (building it) or set in the executable graph (the slot idle)
+static int set_stage_params(Scheduler *S, BatchSlot &sl, int st, int blocks, bool exec) {
+    const BatchedKernel &k = S->kern[PROGRAM[st]];
+    const BatchDesc *desc = sl.d_desc;
+    int stage = st;
+    void *args[2] = {&desc, &stage};
+    hipKernelNodeParams kp;
+    std::memset(&kp, 0, sizeof(kp));
+    kp.func = const_cast<void *>(k.func);
+    kp.gridDim = dim3(blocks);
+    kp.blockDim = dim3(k.threads);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    if (exec)
+        DC_HIP(hipGraphExecKernelNodeSetParams(sl.exec, sl.nodes[st], &kp));
+    else
+        DC_HIP(hipGraphAddKernelNode(&sl.nodes[st], sl.graph, st ? &sl.nodes[st - 1] : nullptr,
+                                     st ? 1 : 0, &kp));
+    sl.grid[st] = blocks;
+    return DC_OK;
+}
+
 // upload, replay and download one batch on slot `sl`; on failure every request of the batch
 // fails with the returned status
 static int run_batch(Scheduler *S, BatchSlot &sl) {
@@ -598,13 +630,22 @@ static int run_batch(Scheduler *S, BatchSlot &sl) {
                               hipMemcpyHostToDevice, s));
     const size_t dsz = sizeof(D->stage) + (size_t)nops * sizeof(OpRec);
     DC_HIP(hipMemcpyAsync(sl.d_desc, D, dsz, hipMemcpyHostToDevice, s));
-    // stages without work in this batch are switched off (the slot is idle, so its executable
-    // graph may be updated)
+    // stages without work in this batch are switched off, and the others launch no more
+    // workgroups than the power of two at or above their logical workgroups (every persistent
+    // workgroup costs launch time even when it finds nothing to do); the slot is idle, so its
+    // executable graph may be updated
     for (int st = 0; st < NPROG; ++st) {
-        const bool on = D->stage[st].total > 0;
+        const int total = D->stage[st].total;
+        const bool on = total > 0;
         if (on != sl.enabled[st]) {
             DC_HIP(hipGraphNodeSetEnabled(sl.exec, sl.nodes[st], on ? 1u : 0u));
             sl.enabled[st] = on;
+        }
+        if (!on) continue;
+        const int want = stage_grid(S->kern[PROGRAM[st]], total);
+        if (want != sl.grid[st]) {
+            const int rc = set_stage_params(S, sl, st, want, true);
+            if (rc != DC_OK) return rc;
         }
     }
     DC_HIP(hipGraphLaunch(sl.exec, s));
@@ -700,20 +741,8 @@ static int init_slot(Scheduler *S, BatchSlot &sl) {
     // the program as a chain of kernel nodes over the slot's descriptor
     DC_HIP(hipGraphCreate(&sl.graph, 0));
     for (int st = 0; st < NPROG; ++st) {
-        const BatchedKernel &k = S->kern[PROGRAM[st]];
-        const BatchDesc *desc = sl.d_desc;
-        int stage = st;
-        void *args[2] = {&desc, &stage};
-        hipKernelNodeParams kp;
-        std::memset(&kp, 0, sizeof(kp));
-        kp.func = const_cast<void *>(k.func);
-        kp.gridDim = dim3(k.blocks);
-        kp.blockDim = dim3(k.threads);
-        kp.sharedMemBytes = 0;
-        kp.kernelParams = args;
-        kp.extra = nullptr;
-        DC_HIP(hipGraphAddKernelNode(&sl.nodes[st], sl.graph, st ? &sl.nodes[st - 1] : nullptr,
-                                     st ? 1 : 0, &kp));
+        const int rc = set_stage_params(S, sl, st, S->kern[PROGRAM[st]].blocks, false);
+        if (rc != DC_OK) return rc;
         sl.enabled[st] = true;
     }
     DC_HIP(hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0));
