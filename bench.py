@@ -341,10 +341,21 @@ def run_serving(p, torch, rate_hz=None, n_requests=None, budget_bytes=64 << 30, 
             raise RuntimeError("a warm-up request failed")
 
     def drive(times):
+        # one client thread: submits each request at its arrival time and collects results; it
+        # sleeps in dc_wait on the oldest request in flight (until the next arrival is due, or
+        # 100 us at a time while several are in flight), and in time.sleep while none is
         pending = {}
         done = {}
         t0 = time.monotonic()
         k = 0
+
+        def collect(tk, st):
+            kk = pending.pop(tk)
+            status, loss, grad, tm = srv.take(tk, st)
+            if status != 0:
+                raise RuntimeError(f"request {kk} failed with status {status}")
+            done[kk] = tm["done"] - (t0 + times[kk])
+
         while k < len(reqs) or pending:
             now = time.monotonic() - t0
             while k < len(reqs) and times[k] <= now:
@@ -354,12 +365,16 @@ def run_serving(p, torch, rate_hz=None, n_requests=None, budget_bytes=64 << 30, 
             for tk in list(pending):
                 st = srv.poll(tk)
                 if st != 1:
-                    kk = pending.pop(tk)
-                    status, loss, grad, tm = srv.take(tk, st)
-                    if status != 0:
-                        raise RuntimeError(f"request {kk} failed with status {status}")
-                    done[kk] = tm["done"] - (t0 + times[kk])
-            time.sleep(5e-5)
+                    collect(tk, st)
+            gap = times[k] - (time.monotonic() - t0) if k < len(reqs) else 1.0
+            if pending:
+                cap = 1e-4 if len(pending) > 1 else gap - 5e-5
+                tk = next(iter(pending))
+                st = srv.wait_us(tk, int(max(0.0, min(cap, gap - 5e-5)) * 1e6))
+                if st != 1:
+                    collect(tk, st)
+            elif gap > 3e-4:
+                time.sleep(gap - 2e-4)
         span = max(done[kk] + times[kk] for kk in done)
         return np.array([done[kk] for kk in sorted(done)]), span
 

@@ -307,6 +307,14 @@ int dc_request_bytes(const dc_request *req, int want_grad, size_t *bytes);
  * Thread-safe. */
 int dc_poll(dc_ctx *ctx, uint64_t ticket);
 
+/* dc_poll that first waits for the request to finish: up to timeout_us microseconds (a negative
+ * value: without limit), sleeping until the serving loop marks a request done rather than
+ * polling.  Returns DC_PENDING if the request is still queued or running when the time is up;
+ * otherwise exactly what dc_poll returns, with the results handed over in the same way.  One
+ * thread should wait on or poll a given ticket; any number of threads may wait on different
+ * tickets.  Thread-safe. */
+int dc_wait(dc_ctx *ctx, uint64_t ticket, int64_t timeout_us);
+
 /* Device bytes the context holds against its budget now (*held), and the budget (*budget, may be
  * NULL).  Errors: DC_ERR_INVALID. */
 int dc_memory_held(dc_ctx *ctx, size_t *held, size_t *budget);

@@ -36,7 +36,7 @@ STATUS_NAMES = {0: "DC_OK", 1: "DC_PENDING", -1: "DC_ERR_INVALID", -2: "DC_ERR_N
 EXPORTS = ["dc_create", "dc_destroy", "dc_last_error", "dc_sync", "dc_sample_surface",
            "dc_sample_surface_masked", "dc_area_cdf", "dc_rigid_pose", "dc_rigid_pose_bwd",
            "dc_sample_surface_bwd", "dc_chamfer_fwd", "dc_chamfer_bwd", "dc_get_stats",
-           "dc_submit", "dc_poll", "dc_version", "dc_debug_fail_allocs", "dc_profile",
+           "dc_submit", "dc_poll", "dc_wait", "dc_version", "dc_debug_fail_allocs", "dc_profile",
            "dc_get_kernel_times", "dc_request_bytes", "dc_memory_held",
            "dc_sample_surface_noalloc"]
 
@@ -104,6 +104,7 @@ def load():
     L.dc_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(Result),
                             ctypes.POINTER(u64)]
     L.dc_poll.argtypes = [vp, u64]
+    L.dc_wait.argtypes = [vp, u64, ctypes.c_int64]
     L.dc_request_bytes.argtypes = [ctypes.POINTER(Request), i, ctypes.POINTER(ctypes.c_size_t)]
     L.dc_debug_fail_allocs.argtypes = [vp, i]
     L.dc_memory_held.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t),

@@ -572,4 +572,10 @@ int dc_poll(dc_ctx *ctx, uint64_t ticket) {
     return sched_poll(ctx, ticket);
 }
 
+int dc_wait(dc_ctx *ctx, uint64_t ticket, int64_t timeout_us) {
+    clear_error();
+    if (!ctx) return DC_ERR_INVALID;
+    return sched_wait(ctx, ticket, (long long)timeout_us);
+}
+
 }  // extern "C"

@@ -1,4 +1,4 @@
-// Serving loop of libdiffcloud: dc_submit / dc_poll.
+// Serving loop of libdiffcloud: dc_submit / dc_poll / dc_wait.
 #pragma once
 
 #include "dc_internal.h"
@@ -7,6 +7,7 @@ namespace dc {
 
 int sched_submit(dc_ctx *ctx, const dc_request *req, dc_result *out, uint64_t *ticket);
 int sched_poll(dc_ctx *ctx, uint64_t ticket);
+int sched_wait(dc_ctx *ctx, uint64_t ticket, long long timeout_us);
 void sched_destroy(dc_ctx *ctx);
 
 // device bytes a request holds while admitted (inputs, intermediates, outputs, scratch)

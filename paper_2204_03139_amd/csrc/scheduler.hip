@@ -450,6 +450,7 @@ struct Scheduler {
     dc_ctx *ctx = nullptr;
     std::mutex mu;
     std::condition_variable cv;
+    std::condition_variable finished;  // a request reached Q_DONE (dc_wait sleeps on it)
     std::deque<Req *> queue;
     std::unordered_map<uint64_t, Req *> table;
     uint64_t next_ticket = 1;
@@ -570,6 +571,7 @@ static void finish_req(Scheduler *S, Req *r, bool on_device) {
     }
     r->state = Q_DONE;
     std::vector<OpRec>().swap(r->ops);
+    S->finished.notify_all();
 }
 
 // workgroups of a stage's node: its persistent grid, or fewer when the batch has less work
@@ -723,7 +725,18 @@ static void loop(Scheduler *S) {
             lk.lock();
             if (rc != DC_OK) fail_batch(S, sl, rc);
         }
-        if (!progressed) S->cv.wait_for(lk, std::chrono::microseconds(50));
+        if (progressed) continue;
+        bool busy = false;
+        for (auto &sl : S->slots) busy |= sl.busy;
+        if (busy) {
+            // a batch is on the device: look at its event again at once (a timed wait would add
+            // its wake-up delay to every request's latency)
+            lk.unlock();
+            std::this_thread::yield();
+            lk.lock();
+        } else {
+            S->cv.wait_for(lk, std::chrono::microseconds(50));
+        }
     }
 }
 
@@ -874,25 +887,8 @@ int sched_submit(dc_ctx *ctx, const dc_request *q, dc_result *out, uint64_t *tic
     return DC_OK;
 }
 
-int sched_poll(dc_ctx *ctx, uint64_t ticket) {
-    Scheduler *S = ctx->sched;
-    if (!S) {
-        set_error("dc_poll: unknown ticket");
-        return DC_ERR_INVALID;
-    }
-    Req *r = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(S->mu);
-        auto it = S->table.find(ticket);
-        if (it == S->table.end()) {
-            set_error("dc_poll: unknown ticket");
-            return DC_ERR_INVALID;
-        }
-        if (it->second->state != Q_DONE) return DC_PENDING;
-        r = it->second;
-        S->table.erase(it);
-    }
-    // the request now belongs to this thread: hand its results over outside the scheduler's lock
+// the results of a finished request (removed from the table) into the caller's buffers
+static int hand_over(Scheduler *S, Req *r, const char *who) {
     const char *h = r->h_out.p;
     if (r->status == DC_OK) {
         std::memcpy(r->out->loss, h + (r->map.loss - r->map.in_bytes), (size_t)r->T * 8);
@@ -906,8 +902,50 @@ int sched_poll(dc_ctx *ctx, uint64_t ticket) {
     host_release(S, &r->h_in);
     host_release(S, &r->h_out);
     delete r;
-    if (st != DC_OK) set_error("dc_poll: the request failed");
+    if (st != DC_OK) set_error(std::string(who) + ": the request failed");
     return st;
+}
+
+// wait up to timeout_us (< 0: without limit, 0: not at all) for the ticket's request, then hand
+// its results over
+static int wait_for_ticket(dc_ctx *ctx, uint64_t ticket, long long timeout_us, const char *who) {
+    Scheduler *S = ctx->sched;
+    if (!S) {
+        set_error(std::string(who) + ": unknown ticket");
+        return DC_ERR_INVALID;
+    }
+    Req *r = nullptr;
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        const auto deadline =
+            std::chrono::steady_clock::now() + std::chrono::microseconds(std::max(timeout_us, 0LL));
+        for (;;) {
+            auto it = S->table.find(ticket);
+            if (it == S->table.end()) {
+                set_error(std::string(who) + ": unknown ticket");
+                return DC_ERR_INVALID;
+            }
+            if (it->second->state == Q_DONE) {
+                r = it->second;
+                S->table.erase(it);
+                break;
+            }
+            if (timeout_us == 0) return DC_PENDING;
+            if (timeout_us < 0)
+                S->finished.wait(lk);
+            else if (S->finished.wait_until(lk, deadline) == std::cv_status::timeout &&
+                     S->table.count(ticket) && S->table[ticket]->state != Q_DONE)
+                return DC_PENDING;
+        }
+    }
+    // the request now belongs to this thread: hand its results over outside the scheduler's lock
+    return hand_over(S, r, who);
+}
+
+int sched_poll(dc_ctx *ctx, uint64_t ticket) { return wait_for_ticket(ctx, ticket, 0, "dc_poll"); }
+
+int sched_wait(dc_ctx *ctx, uint64_t ticket, long long timeout_us) {
+    return wait_for_ticket(ctx, ticket, timeout_us, "dc_wait");
 }
 
 void sched_destroy(dc_ctx *ctx) {

@@ -1,4 +1,5 @@
-"""Python handle on the library's serving loop (dc_submit / dc_poll): argument marshalling only.
+"""Python handle on the library's serving loop (dc_submit / dc_poll / dc_wait): argument
+marshalling only.
 
 Requests carry host arrays; the library copies them at submit time, admits the request when its
 device memory fits the context's budget, runs sampling, Chamfer forward and backward for every
@@ -7,7 +8,6 @@ frame on the GPU, and returns the per-frame loss and (optionally) the vertex gra
 from __future__ import annotations
 
 import ctypes
-import time
 
 import numpy as np
 
@@ -61,16 +61,17 @@ class Server:
         """DC_PENDING (1) while running; then the final status (0 or a negative code)."""
         return _lib.load().dc_poll(self.ctx.handle, ticket)
 
-    def wait(self, ticket: int, timeout: float = 120.0, sleep: float = 2e-4):
+    def wait_us(self, ticket: int, timeout_us: int) -> int:
+        """dc_wait: sleep in the library until the request finishes or timeout_us passes
+        (negative: no limit); DC_PENDING (1) if it is still running, else its final status."""
+        return _lib.load().dc_wait(self.ctx.handle, ticket, int(timeout_us))
+
+    def wait(self, ticket: int, timeout: float = 120.0):
         """Block until the request finishes; returns (status, loss, grad, times)."""
-        t0 = time.monotonic()
-        while True:
-            st = self.poll(ticket)
-            if st != _lib.DC_PENDING:
-                return self.take(ticket, st)
-            if time.monotonic() - t0 > timeout:
-                raise TimeoutError(f"request {ticket} still pending after {timeout} s")
-            time.sleep(sleep)
+        st = self.wait_us(ticket, int(timeout * 1e6))
+        if st == _lib.DC_PENDING:
+            raise TimeoutError(f"request {ticket} still pending after {timeout} s")
+        return self.take(ticket, st)
 
     def take(self, ticket: int, status: int):
         res, loss, grad = self._live.pop(ticket)

@@ -297,3 +297,30 @@ def test_served_results_match_the_oracle():
             if want:
                 assert_grad(grad[t], ogv, ogva, what="served grad_verts")
     srv.close()
+
+
+def test_wait_blocks_until_done_and_matches_poll():
+    """dc_wait: a zero timeout is a poll, a short one on a large request returns DC_PENDING, an
+    unlimited one returns the final status with the same results as polling; unknown tickets
+    are rejected."""
+    p = gpu()
+    from paper_2204_03139_amd.serving import Server
+    say("[serving] dc_wait")
+    srv = Server(hbm_budget_bytes=1 << 30)
+    big = _request(40, n=60, T=24, Na=16384, Nb=16384)
+    small = _request(41)
+    tb = srv.submit(big["verts"], big["faces"], big["obs"], big["Na"], big["seed"], 1)
+    ts = srv.submit(small["verts"], small["faces"], small["obs"], small["Na"], small["seed"], 1)
+    assert srv.wait_us(tb, 0) == 1          # queued or running: a zero timeout does not wait
+    assert srv.wait_us(tb, 10) == 1         # 24 frames of 16,384^2 pairs take far longer
+    st, loss, grad, times = srv.take(tb, srv.wait_us(tb, -1))
+    assert st == 0 and times["submit"] <= times["admit"] <= times["done"]
+    dl, dg = _direct(p, big, 1)
+    assert np.array_equal(loss.view(np.uint64), dl.view(np.uint64))
+    assert np.array_equal(grad.view(np.uint32), dg.view(np.uint32))
+    st, loss, grad, _ = srv.wait(ts)
+    dl, dg = _direct(p, small, 1)
+    assert st == 0 and np.array_equal(loss.view(np.uint64), dl.view(np.uint64))
+    assert srv.wait_us(ts, -1) == -1        # a finished ticket is forgotten
+    assert srv.wait_us(12345678, 0) == -1   # never issued
+    srv.close()
