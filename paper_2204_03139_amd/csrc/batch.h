@@ -85,6 +85,7 @@ enum KernelType : int {
     KT_BIDIR8,
     KT_BIDIR4,
     KT_BIDIR_MERGE,
+    KT_SS_SMALL,
     KT_COUNT
 };
 

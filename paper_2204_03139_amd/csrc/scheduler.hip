@@ -101,11 +101,11 @@ void fill_f64(double *p, int n, double v, hipStream_t s) {
 }
 
 // The serving program: every request's recorded launches form a subsequence of it.  Exact
-// searches may use any of the three queries-per-lane variants; each sort has room for four
-// 8-bit digit passes (keys below 2^32).
-#define SORT_PASSES                                                                           \
-    KT_SS_HIST, KT_SS_SCAN, KT_SS_SCATTER, KT_SS_HIST, KT_SS_SCAN, KT_SS_SCATTER, KT_SS_HIST, \
-        KT_SS_SCAN, KT_SS_SCATTER, KT_SS_HIST, KT_SS_SCAN, KT_SS_SCATTER
+// searches may use any of the three queries-per-lane variants; each sort is either the one-launch
+// sort of small segments or up to four 8-bit digit passes (keys below 2^32).
+#define SORT_PASSES                                                                          \
+    KT_SS_SMALL, KT_SS_HIST, KT_SS_SCAN, KT_SS_SCATTER, KT_SS_HIST, KT_SS_SCAN, KT_SS_SCATTER, \
+        KT_SS_HIST, KT_SS_SCAN, KT_SS_SCATTER, KT_SS_HIST, KT_SS_SCAN, KT_SS_SCATTER
 const int PROGRAM[] = {
     KT_FILL_U32,  KT_AREA_CDF, KT_SAMPLE,                                      // sampling
     KT_NORM_MAX,  KT_NORM_MAX, KT_PACK,     KT_SCREEN, KT_SCREEN_ROWS, KT_REFINE,  // screen

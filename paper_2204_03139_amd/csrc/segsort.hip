@@ -1,6 +1,7 @@
 // Stable, atomic-free sort of per-frame integer keys (LSD radix, 8-bit digits).
 //
-// Each digit pass is three launches over blocks of 1024 items (many blocks per frame):
+// Each digit pass is three launches over blocks of 1024 items (many blocks per frame; a frame
+// small enough for one workgroup's LDS is sorted in one launch instead, see k_ss_small):
 //   k_ss_hist    each block counts its digits: within a wave, lanes holding the same digit are
 //                found with eight ballots, the group's lowest lane records the group size in a
 //                per-wave LDS row (distinct digits, so no two writers collide); the block sums the
@@ -208,6 +209,113 @@ __global__ __launch_bounds__(SB_THREADS) void k_ss_scatter(SortPassParams p) {
 
 static_assert(SB_THREADS == BINS, "one thread per digit bin");
 
+// A segment of at most SM_MAX items whose keys need at most two digit passes is sorted by one
+// workgroup in LDS (k_ss_small), in place of the six launches of two passes.  The segment is
+// loaded once, every item packed into one word (its 16-bit key, its 14-bit position and a flag for
+// an out-of-range key whose value is the complement of the position), and the passes move the words
+// between two LDS buffers; the last one writes keys and values out.  Wave w takes the items
+// [w P, (w + 1) P) of a pass, P a multiple of 64, in rounds of 64 (item w P + 64 r + lane), so
+// (wave, round, lane) is the item order.  Each pass counts the digits per wave (the same
+// eight-ballot grouping as above), turns the counts into offsets in (digit, wave) order, and writes
+// each item to its wave's running offset for its digit plus its rank among the earlier lanes of
+// its round with the same digit: equal keys keep their order.
+constexpr int SM_THREADS = 1024;
+constexpr int SM_WAVES = SM_THREADS / 64;
+// items: two buffers of one word each, 32 KB of LDS.  One workgroup takes about 0.8 us per round
+// of its 16 waves (the ballots dominate), so past about 4,096 items the launches of the block
+// passes, spread over the chip, are as fast or faster.
+constexpr int SM_MAX = 4096;
+
+struct SortSmallParams {
+    SortIO io;  // the input keys (src_keys unused)
+    int32_t *dst_keys;
+    int32_t *dst_vals;
+    int N, passes;
+};
+
+__device__ __forceinline__ void ss_small_body(const SortSmallParams &pr, const Blk &b) {
+    __shared__ unsigned buf[2][SM_MAX];
+    __shared__ int wcnt[SM_WAVES][BINS];
+    __shared__ int dsum[BINS / 64];
+    const int t = b.x;
+    const int N = pr.N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int per = (N + SM_THREADS - 1) / SM_THREADS * 64;  // items per wave
+    const int rounds = per / 64;
+    const int w0 = wave * per;
+    // key << 16 | flag << 14 | position (keys are below 2^16 when two passes suffice)
+    for (int e = threadIdx.x; e < N; e += SM_THREADS) {
+        int key, val;
+        read_item(pr.io, (size_t)t * N + e, e, key, val);
+        buf[0][e] = ((unsigned)key << 16) | (val < 0 ? 1u << 14 : 0u) | (unsigned)e;
+    }
+    for (int p = 0; p < pr.passes; ++p) {
+        const unsigned *src = buf[p & 1];
+        unsigned *dst = buf[(p + 1) & 1];
+        const int shift = 16 + 8 * p;
+        const bool last = p == pr.passes - 1;
+        for (int k = threadIdx.x; k < SM_WAVES * BINS; k += SM_THREADS) (&wcnt[0][0])[k] = 0;
+        __syncthreads();
+        for (int r = 0; r < rounds; ++r) {
+            const int e = w0 + 64 * r + lane;
+            const bool valid = e < N;
+            const int d = valid ? (int)(src[e] >> shift) & (BINS - 1) : 0;
+            const unsigned long long m = same_digit(valid, d);
+            if (valid && __popcll(m & below) == 0) wcnt[wave][d] += __popcll(m);
+        }
+        __syncthreads();
+        // offsets in (digit, wave) order: the digit totals scanned by threads 0..255, then each
+        // digit's waves in order
+        int s = 0, incl = 0;
+        if (threadIdx.x < BINS) {
+            for (int w = 0; w < SM_WAVES; ++w) s += wcnt[w][threadIdx.x];
+            incl = s;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int o = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += o;
+            }
+            if (lane == 63) dsum[wave] = incl;
+        }
+        __syncthreads();
+        if (threadIdx.x < BINS) {
+            int base = incl - s;
+            for (int w = 0; w < wave; ++w) base += dsum[w];
+            for (int w = 0; w < SM_WAVES; ++w) {
+                const int c = wcnt[w][threadIdx.x];
+                wcnt[w][threadIdx.x] = base;
+                base += c;
+            }
+        }
+        __syncthreads();
+        for (int r = 0; r < rounds; ++r) {
+            const int e = w0 + 64 * r + lane;
+            const bool valid = e < N;
+            const unsigned word = valid ? src[e] : 0u;
+            const int d = (int)(word >> shift) & (BINS - 1);
+            const unsigned long long m = same_digit(valid, d);
+            const int rank = __popcll(m & below);
+            const int pos = wcnt[wave][d] + rank;
+            if (valid && rank == 0) wcnt[wave][d] = pos + __popcll(m);
+            if (valid) {
+                if (last) {
+                    const int pe = (int)(word & 0x3FFFu);
+                    pr.dst_keys[(size_t)t * N + pos] = (int)(word >> 16);
+                    pr.dst_vals[(size_t)t * N + pos] = (word & (1u << 14)) ? ~pe : pe;
+                } else {
+                    dst[pos] = word;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(SM_THREADS) void k_ss_small(SortSmallParams p) {
+    ss_small_body(p, grid_blk());
+}
+
 }  // namespace
 
 static int ss_passes(int key_limit) {
@@ -233,6 +341,20 @@ void launch_segsort(const int32_t *keys, int T, int N, int key_limit, int32_t *o
     if (T <= 0 || N <= 0) return;
     const int nblk = ss_blocks(N);
     const int passes = ss_passes(key_limit);
+    if (N <= SM_MAX && passes <= 2) {  // one workgroup per segment, in LDS
+        SortSmallParams sp;
+        sp.io.keys = keys;
+        sp.io.src_keys = nullptr;
+        sp.io.src_vals = nullptr;
+        sp.io.limit = key_limit;
+        sp.io.mark_invalid = mark_invalid ? 1 : 0;
+        sp.dst_keys = out_keys;
+        sp.dst_vals = out_vals;
+        sp.N = N;
+        sp.passes = passes;
+        dispatch(KT_SS_SMALL, k_ss_small, dim3(T), SM_THREADS, sp, s);
+        return;
+    }
     const dim3 grid(nblk, T);
     for (int p = 0; p < passes; ++p) {
         SortIO io;
@@ -261,6 +383,7 @@ void register_sort_kernels(BatchedKernel *table) {
     table[KT_SS_HIST] = batched_kernel<SortPassParams, ss_hist_body, SB_THREADS, 1024>();
     table[KT_SS_SCAN] = batched_kernel<SortPassParams, ss_scan_body, SCAN_THREADS, 256>();
     table[KT_SS_SCATTER] = batched_kernel<SortPassParams, ss_scatter_body, SB_THREADS, 1024>();
+    table[KT_SS_SMALL] = batched_kernel<SortSmallParams, ss_small_body, SM_THREADS, 256>();
 }
 
 }  // namespace dc
