@@ -161,27 +161,31 @@ __device__ void running_sum(double *cur, int n, double &run, int lane) {
             const int sh = 1075 - eb;                  // the spacing of s's binade is 2^-sh
             const double ms = __builtin_ldexp(s, sh);  // s / u: an integer in [2^52, 2^53)
             double pre[RS_PER];
-            unsigned ties = 0;
+            int tie = RS_PER;  // the lane's first tie
             double acc = 0.0;
 #pragma unroll
             for (int i = 0; i < RS_PER; ++i) {
                 const double raw = cur[k + base + i];  // past the chunk: the buffer's padding
                 const double a = base + i < avail ? raw : 0.0;
-                const double x = __builtin_ldexp(a, sh);  // A / u, exact down to far below 1/2
-                const bool in = x < LIM;                  // false when A leaves the binade, or NaN
-                const double q = __builtin_floor(x);
-                const double f = x - q;
-                if (in && f == 0.5) ties |= 1u << i;
-                const double d = in ? (f > 0.5 ? q + 1.0 : q) : LIM;
-                acc = acc + d;
+                // A / u + 1/2 is exact while A / u < 2^52, and an area whose A / u is larger
+                // leaves the binade whatever its rounding: floor gives q + [f >= 1/2], and the
+                // sum is exactly an integer when f is exactly 1/2 (a tie, which stops the window,
+                // so that it rounds up here does not matter)
+                const double y = __builtin_ldexp(a, sh) + 0.5;
+                const double d = __builtin_floor(y);
+                if (d == y && tie == RS_PER) tie = i;
+                acc = acc + d;  // NaN and infinite areas make the sums leave the binade
                 pre[i] = acc;
             }
             const double incl = wave_prefix(acc, lane);
             const double ex = lane_before(incl);  // wave_shr:1
             int inside = 0;  // positions whose sum stays in the binade (sums never decrease)
 #pragma unroll
-            for (int i = 0; i < RS_PER; ++i) inside += ms + (ex + pre[i]) < LIM ? 1 : 0;
-            const int first = min(inside, ties ? __builtin_ctz(ties) : RS_PER);
+            for (int i = 0; i < RS_PER; ++i) {
+                pre[i] = ms + (ex + pre[i]);  // m of position i, in units of u
+                inside += pre[i] < LIM ? 1 : 0;
+            }
+            const int first = min(inside, tie);
             const unsigned long long bal = __ballot(first < RS_PER);
             if (bal) {
                 const int l = __ffsll((long long)bal) - 1;
@@ -193,7 +197,7 @@ __device__ void running_sum(double *cur, int n, double &run, int lane) {
 #pragma unroll
             for (int i = 0; i < RS_PER; ++i)
                 cur[base + i < stop ? k + base + i : AC_CHUNK + RS_WIN + lane] =
-                    __builtin_ldexp(ms + (ex + pre[i]), -sh);
+                    __builtin_ldexp(pre[i], -sh);
             if (stop == RS_WIN && avail >= RS_WIN) {  // the whole window stayed in the binade
                 run = __builtin_ldexp(ms + lane_value(incl, 63), -sh);
                 k += RS_WIN;
