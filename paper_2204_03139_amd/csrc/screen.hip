@@ -307,11 +307,6 @@ __device__ __forceinline__ int part_code(float v, int bias) {
     return min(max(hb - bias, 0), PC_MAX);
 }
 
-// the smallest value a code can stand for (0 for code 0, whose values may even be negative)
-__device__ __forceinline__ float part_lo(int c, int bias) {
-    return c <= 0 ? 0.f : __uint_as_float((unsigned)(c + bias) << 16);
-}
-
 // a value above everything a code can stand for (infinite for the saturated code)
 __device__ __forceinline__ float part_hi(int c, int bias) {
     return c >= PC_MAX ? __builtin_inff() : __uint_as_float((unsigned)(c + 1 + bias) << 16);
@@ -361,7 +356,7 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
     const float *__restrict__ Q = pr.Q;
     const bf16x8 *__restrict__ packed = pr.packed;
     const float *__restrict__ slack = pr.slack;
-    const int Nq = pr.Nq, Np = pr.Np, Np_pad = pr.Np_pad;
+    const int Nq = pr.Nq, Np_pad = pr.Np_pad;
     int32_t *__restrict__ rec = pr.rec;
     int32_t *__restrict__ heavy_cnt = pr.heavy_cnt;
     int32_t *__restrict__ heavy_list = pr.heavy_list;
