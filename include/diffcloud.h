@@ -68,7 +68,9 @@ typedef struct dc_ctx dc_ctx;
  * bytes). */
 int dc_create(dc_ctx **out, int device, size_t hbm_budget_bytes, int max_slots);
 
-/* Wait for the serving loop to drain, free everything the context owns, destroy it. */
+/* Wait for the serving loop to drain, free everything the context owns, destroy it.  No other
+ * call on the context may be in progress (a thread blocked in dc_wait included) or follow: the
+ * caller collects its requests' results first. */
 int dc_destroy(dc_ctx *ctx);
 
 /* Text of the calling thread's last error ("" if none); valid until the thread's next call into
