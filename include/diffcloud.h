@@ -160,7 +160,8 @@ int dc_sample_surface_noalloc(dc_ctx *ctx, const float *verts, const int32_t *fa
  *   grad_verts[t,v] = sum over points i of frame t and corners c with faces[face_idx[t,i]][c]==v
  *                     of bary[t,i,c] * grad_points[t,i].
  * No gradient flows through the face choice or the areas.  Sums run in a fixed order (by vertex
- * incidence, then by point index), so the result is bitwise reproducible; no atomics are used.
+ * incidence, then by point index) and in double (each (face, corner) sum and each output rounded
+ * once to float), so the result is bitwise reproducible; no atomics are used.
  *   grad_points device float [T,N,3]; faces, face_idx, bary as produced by dc_sample_surface;
  *   grad_verts  device float [T,V,3], overwritten.
  * Points whose face_idx is -1 (degenerate frame) contribute nothing.
@@ -196,7 +197,8 @@ int dc_chamfer_fwd(dc_ctx *ctx, const float *a, const float *b, int T, int Na, i
  *   grad_a[t,i] = g_t w_t ( 2 alpha (a_i - b_{idx_a[i]}) + 2 beta sum_{j: idx_b[j]=i} (a_i - b_j) )
  *   grad_b[t,j] = g_t w_t ( 2 beta (b_j - a_{idx_b[j]}) + 2 alpha sum_{i: idx_a[i]=j} (b_j - a_i) )
  * The sums over j (resp. i) run in increasing index order after a stable, atomic-free sort by
- * neighbour index, so results are bitwise reproducible.  A neighbour index outside [0, Nb) (resp.
+ * neighbour index, in double (each output rounded once to float), so results are bitwise
+ * reproducible.  A neighbour index outside [0, Nb) (resp.
  * [0, Na)) contributes nothing: neither its own term nor a term to the point it names.
  *   grad_loss device double [T]; a, b, idx_a, idx_b, frame_w as in dc_chamfer_fwd (idx_b is not
  *   read with DC_RED_SIM2REAL_SUM, where beta = 0, and may then be NULL);

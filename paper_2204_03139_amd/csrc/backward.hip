@@ -1,7 +1,8 @@
 // Backward passes: the Chamfer gradient through the saved neighbours (Sec. III-A, Eq. 1/2) and
 // the sampling gradient through Eq. 4 (Sec. III-B).  Both are gathers over segments built by the
-// stable atomic-free sort, summed in increasing index order, so every result is bitwise
-// reproducible and independent of scheduling.
+// stable atomic-free sort, summed in increasing index order and in double (each output rounded
+// once to float), so every result is bitwise reproducible, independent of scheduling, and within a
+// few units of 2^-24 of the sum of its terms' magnitudes however long a segment is.
 #include "batch.h"
 
 namespace dc {
@@ -39,41 +40,44 @@ __device__ __forceinline__ void chamfer_bwd_body(const ChamferBwdParams &pr, con
     const int i = blk.x * BW_THREADS + threadIdx.x;
     if (i >= Nx) return;
     const double g = grad_loss[t] * (frame_w ? (double)frame_w[t] : 1.0);
-    const float cs = (float)(cself * g);
-    const float cm = (float)(cmutual * g);
+    const double cs = cself * g;
+    const double cm = cmutual * g;
     const float *xt = X + (size_t)t * Nx * 3;
     const float *yt = Y + (size_t)t * Ny * 3;
-    const float x0 = xt[3 * (size_t)i], x1 = xt[3 * (size_t)i + 1], x2 = xt[3 * (size_t)i + 2];
-    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+    // in double (each difference of two floats is exact there) and rounded once to float: the
+    // result stays within a few units of 2^-24 of the sum of the terms' magnitudes however many
+    // points share this neighbour
+    const double x0 = xt[3 * (size_t)i], x1 = xt[3 * (size_t)i + 1], x2 = xt[3 * (size_t)i + 2];
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
     // the own-neighbour term exists only when cs != 0 (nn_x may be NULL otherwise: the b side of
     // the unidirectional loss has no neighbour indices)
-    const int jn = (cs != 0.f) ? nn_x[(size_t)t * Nx + i] : -1;
+    const int jn = (cs != 0.0) ? nn_x[(size_t)t * Nx + i] : -1;
     if ((unsigned)jn < (unsigned)Ny) {  // indices outside [0, Ny) contribute nothing
         const int j = jn;
-        g0 = cs * (x0 - yt[3 * (size_t)j]);
-        g1 = cs * (x1 - yt[3 * (size_t)j + 1]);
-        g2 = cs * (x2 - yt[3 * (size_t)j + 2]);
+        g0 = cs * (x0 - (double)yt[3 * (size_t)j]);
+        g1 = cs * (x1 - (double)yt[3 * (size_t)j + 1]);
+        g2 = cs * (x2 - (double)yt[3 * (size_t)j + 2]);
     }
-    if (cm != 0.f) {
+    if (cm != 0.0) {
         const int32_t *vs = yvals_sorted + (size_t)t * Ny;
         const int32_t *st = ystart + (size_t)t * (Nx + 1);
         const int lo = st[i], hi = st[i + 1];
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         for (int p = lo; p < hi; ++p) {
             const int j = vs[p];
             if (j < 0) continue;  // a neighbour index outside [0, Nx): contributes nothing
-            s0 += x0 - yt[3 * (size_t)j];
-            s1 += x1 - yt[3 * (size_t)j + 1];
-            s2 += x2 - yt[3 * (size_t)j + 2];
+            s0 += x0 - (double)yt[3 * (size_t)j];
+            s1 += x1 - (double)yt[3 * (size_t)j + 1];
+            s2 += x2 - (double)yt[3 * (size_t)j + 2];
         }
-        g0 = __builtin_fmaf(cm, s0, g0);
-        g1 = __builtin_fmaf(cm, s1, g1);
-        g2 = __builtin_fmaf(cm, s2, g2);
+        g0 += cm * s0;
+        g1 += cm * s1;
+        g2 += cm * s2;
     }
     float *o = gX + ((size_t)t * Nx + i) * 3;
-    o[0] = g0;
-    o[1] = g1;
-    o[2] = g2;
+    o[0] = (float)g0;
+    o[1] = (float)g1;
+    o[2] = (float)g2;
 }
 
 __global__ __launch_bounds__(BW_THREADS) void k_chamfer_bwd(ChamferBwdParams p) {
@@ -128,23 +132,24 @@ __device__ __forceinline__ void face_grad_body(const FaceGradParams &pr, const B
     const int32_t *pf = pts_by_face + (size_t)t * N;
     const float *gt = gpts + (size_t)t * N * 3;
     const float *bt = bary + (size_t)t * N * 3;
-    float acc[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    // in double (a product of two floats is exact there), rounded once to float per (face, corner)
+    double acc[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     for (int p = fs[f]; p < fs[f + 1]; ++p) {
         const int i = pf[p];
-        const float g0 = gt[3 * (size_t)i], g1 = gt[3 * (size_t)i + 1], g2 = gt[3 * (size_t)i + 2];
+        const double g0 = gt[3 * (size_t)i], g1 = gt[3 * (size_t)i + 1], g2 = gt[3 * (size_t)i + 2];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const float w = bt[3 * (size_t)i + c];
-            acc[c][0] = __builtin_fmaf(w, g0, acc[c][0]);
-            acc[c][1] = __builtin_fmaf(w, g1, acc[c][1]);
-            acc[c][2] = __builtin_fmaf(w, g2, acc[c][2]);
+            const double w = bt[3 * (size_t)i + c];
+            acc[c][0] = __builtin_fma(w, g0, acc[c][0]);
+            acc[c][1] = __builtin_fma(w, g1, acc[c][1]);
+            acc[c][2] = __builtin_fma(w, g2, acc[c][2]);
         }
     }
     float *o = fg + ((size_t)t * F + f) * 9;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) o[3 * c + d] = acc[c][d];
+        for (int d = 0; d < 3; ++d) o[3 * c + d] = (float)acc[c][d];
 }
 
 __global__ __launch_bounds__(BW_THREADS) void k_face_grad(FaceGradParams p) {
@@ -170,7 +175,7 @@ __device__ __forceinline__ void vertex_grad_body(const VertexGradParams &pr, con
     const int v = blk.x * BW_THREADS + threadIdx.x;
     if (v >= V) return;
     const float *ft = fg + (size_t)t * F * 9;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;  // in double, rounded once to float
     for (int q = vert_start[v]; q < vert_start[v + 1]; ++q) {
         const int fc = corners_by_vertex[q];  // 3 f + c
         a0 += ft[3 * (size_t)fc];
@@ -178,9 +183,9 @@ __device__ __forceinline__ void vertex_grad_body(const VertexGradParams &pr, con
         a2 += ft[3 * (size_t)fc + 2];
     }
     float *o = gverts + ((size_t)t * V + v) * 3;
-    o[0] = a0;
-    o[1] = a1;
-    o[2] = a2;
+    o[0] = (float)a0;
+    o[1] = (float)a1;
+    o[2] = (float)a2;
 }
 
 __global__ __launch_bounds__(BW_THREADS) void k_vertex_grad(VertexGradParams p) {

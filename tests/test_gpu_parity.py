@@ -605,11 +605,16 @@ def _segment_cases():
     r = np.random.default_rng(91)
     u = lambda *s: r.uniform(-.5, .5, s).astype(np.float32)  # noqa: E731
     same = np.repeat(u(2, 1, 3), 700, axis=1)
+    # the neighbour sorts either side of the one-workgroup sort's limit of 4,096 keys: idx_b
+    # (4,096 keys) in one workgroup, idx_a (4,097) in the block passes
+    cut = (u(2, 4097, 3), u(2, 4096, 3))
     return {"one-row": (u(2, 1, 3), u(2, 7, 3)), "one-target": (u(1, 300, 3), u(1, 1, 3)),
-            "one-point-targets": (u(2, 900, 3), same), "ragged": (u(3, 1001, 3), u(3, 777, 3))}
+            "one-point-targets": (u(2, 900, 3), same), "ragged": (u(3, 1001, 3), u(3, 777, 3)),
+            "sort-cutover": cut}
 
 
-@pytest.mark.parametrize("case", ["one-row", "one-target", "one-point-targets", "ragged"])
+@pytest.mark.parametrize("case", ["one-row", "one-target", "one-point-targets", "ragged",
+                                  "sort-cutover"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_backward_segment_edges(case, precision):
     """The Chamfer backward at the edges of its neighbour segments, in both directions, against
@@ -628,6 +633,25 @@ def test_backward_segment_edges(case, precision):
     assert np.array_equal(host(f["idx_b"]), o["idx_b"])
     assert_grad(host(ga), og["ga"], og["ga_abs"], what="grad_a")
     assert_grad(host(gb), og["gb"], og["gb_abs"], what="grad_b")
+
+
+@pytest.mark.parametrize("N", [4096, 4097])
+def test_sampling_backward_at_sort_cutover(N):
+    """Eq. 4 with the points-by-face sort (two digit passes over 1,682 faces) on either side of
+    the one-workgroup sort's limit: 4,096 points per frame in one workgroup, 4,097 in the block
+    passes; vertex gradients against the oracle's double sums."""
+    p = gpu()
+    say(f"[backward] sampling sort cutover N={N}")
+    verts, faces = gen.trajectory(30, 2, 4)
+    T, V = verts.shape[:2]
+    r = np.random.default_rng(N)
+    words = r.integers(0, 2**32, size=(T, N, 4), dtype=np.uint64).astype(np.uint32)
+    gp = r.standard_normal((T, N, 3)).astype(np.float32)
+    _, fi, ba = p.sample_surface(dev(verts), dev(faces), N, uniforms=dev(words.view(np.int32)))
+    gv = p.sample_surface_bwd(dev(gp), dev(faces), fi, ba, V)
+    torch.cuda.synchronize()
+    ogv, ogva = oracle.sample_grad(gp, faces, host(fi), host(ba), V, np.abs(gp))
+    assert_grad(host(gv), ogv, ogva, what="grad_verts")
 
 
 def test_determinism():
