@@ -146,6 +146,21 @@ def test_sizes_around_windows_and_chunks(F):
     _check(p, verts, faces, what=f"F={F}")
 
 
+def test_many_chunks():
+    """A frame of 1,000,003 faces (250 chunks of 4,000, the last one ragged) with areas over six
+    orders of magnitude, and a second frame with every tenth face masked."""
+    p = gpu()
+    rng = np.random.default_rng(11)
+    F = 1_000_003
+    scale = 10.0 ** rng.uniform(-3, 0, F)
+    base = rng.uniform(-1, 1, (F, 3, 3)) * scale[:, None, None]
+    verts = np.stack([base.reshape(3 * F, 3), base[::-1].reshape(3 * F, 3)]).astype(np.float32)
+    faces = np.arange(3 * F, dtype=np.int32).reshape(F, 3)
+    mask = np.ones((2, F), np.uint8)
+    mask[1, ::10] = 0
+    _check(p, verts, faces, mask=mask, what="many chunks")
+
+
 def test_bad_face_and_arguments():
     p = gpu()
     ctx = p.Context(0)
