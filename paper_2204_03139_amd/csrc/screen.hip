@@ -517,38 +517,30 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
                 N1 = sb[(bt + 3) * SC_ROWPAD];
             }
             float cm0 = inf, cm1 = inf;
-            if constexpr (COLS) {
-                // issue order of the two-direction screen, written out: each query tile's two
-                // MFMAs go two tiles ahead of the minima that read their results, so no minimum
-                // waits for the matrix unit (1.2% faster than the compiler's order steered by a
-                // one-tile scheduling hint; the one-direction screen keeps the compiler's order)
-                constexpr int LA = 2;
-                floatx4 d0[ATILES], d1[ATILES];
+            // issue order, written out: each query tile's two MFMAs go two tiles ahead of the
+            // minima that read their results, so no minimum waits for the matrix unit (measured
+            // 1.2% faster for both directions and 0.8% for the rows alone than the compiler's
+            // order, also when it was steered by a one-tile scheduling hint)
+            constexpr int LA = 2;
+            floatx4 d0[ATILES], d1[ATILES];
 #pragma unroll
-                for (int a = 0; a < LA; ++a) {
-                    d0[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B0, zero, 0, 0, 0);
-                    d1[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B1, zero, 0, 0, 0);
+            for (int a = 0; a < LA; ++a) {
+                d0[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B0, zero, 0, 0, 0);
+                d1[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B1, zero, 0, 0, 0);
+            }
+#pragma unroll
+            for (int a = 0; a < ATILES; ++a) {
+                if (a + LA < ATILES) {
+                    d0[a + LA] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a + LA], B0, zero, 0, 0, 0);
+                    d1[a + LA] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a + LA], B1, zero, 0, 0, 0);
                 }
 #pragma unroll
-                for (int a = 0; a < ATILES; ++a) {
-                    if (a + LA < ATILES) {
-                        d0[a + LA] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a + LA], B0, zero, 0, 0, 0);
-                        d1[a + LA] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a + LA], B1, zero, 0, 0, 0);
-                    }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) m[a][r] = fminf(fminf(m[a][r], d0[a][r]), d1[a][r]);
+                for (int r = 0; r < 4; ++r) m[a][r] = fminf(fminf(m[a][r], d0[a][r]), d1[a][r]);
+                if (COLS) {
                     cm0 = fminf(fminf(cm0, d0[a][0]), d0[a][1]);
                     cm0 = fminf(fminf(cm0, d0[a][2]), d0[a][3]);
                     cm1 = fminf(fminf(cm1, d1[a][0]), d1[a][1]);
                     cm1 = fminf(fminf(cm1, d1[a][2]), d1[a][3]);
-                }
-            } else {
-#pragma unroll
-                for (int a = 0; a < ATILES; ++a) {
-                    const floatx4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B0, zero, 0, 0, 0);
-                    const floatx4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B1, zero, 0, 0, 0);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) m[a][r] = fminf(fminf(m[a][r], d0[r]), d1[r]);
                 }
             }
             if (COLS) {
