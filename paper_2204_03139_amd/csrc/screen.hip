@@ -7,7 +7,7 @@
 // Each float coordinate is split exactly into three bf16 parts (x = h + m + l); the products
 // hH, hM, mH, hL, lH, mM per coordinate (18 K-slots) plus the two norms in three parts each (6
 // K-slots) fill 24 of the 32 K-slots, so the matrix unit produces the whole screened distance.
-// Rows a stay in registers (16-row tiles: six per wave for both directions, four for one); the
+// Rows a stay in registers (16-row tiles: seven per wave for both directions, four for one); the
 // b operands (packed once per frame) stream through a double-buffered LDS stage.  Every 16x16
 // result tile feeds both directions with v_min3 only:
 //   rows (a -> b): each (lane, row) folds its column of every tile into a running minimum;
@@ -51,11 +51,12 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int SC_WAVES = 4;
 constexpr int SC_THREADS = 64 * SC_WAVES;
 #ifndef DC_SCREEN_ATILES_COLS
-#define DC_SCREEN_ATILES_COLS 6
+#define DC_SCREEN_ATILES_COLS 7
 #endif
 // 16-row query tiles per wave: the one-direction screen keeps three workgroups per compute unit
-// with four; the two-direction screen amortises its per-stage column reduction over six tiles
-// (at two workgroups per compute unit), which measured faster for it and slower for the other
+// with four; the two-direction screen amortises its per-stage column reduction over seven tiles
+// (at two workgroups per compute unit, 239 registers; eight spill), which measured faster for it
+// and slower for the other
 template <bool COLS>
 constexpr int sc_atiles() { return COLS ? DC_SCREEN_ATILES_COLS : DC_SCREEN_ATILES; }
 template <bool COLS>
@@ -1047,8 +1048,8 @@ __global__ __launch_bounds__(RF_THREADS) void k_refine(RefineParams p) {
     refine_body(p, grid_blk_xcd());
 }
 
-// Column refine (b -> a): each candidate workgroup contributes its winning row group (48 rows:
-// 12 runs of 4) or, when flagged ambiguous, all of its rows.
+// Column refine (b -> a): each candidate workgroup contributes its winning row group (8 rows per
+// query tile: runs of 4, two per tile) or, when flagged ambiguous, all of its rows.
 __device__ __forceinline__ void colrefine_body(const RefineParams &pr, const Blk &blk) {
     const float *__restrict__ B = pr.Q;
     const float *__restrict__ A = pr.P;

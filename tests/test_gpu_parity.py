@@ -233,8 +233,9 @@ def test_chamfer_ties_and_identity(precision):
     _check_chamfer(g, o)
 
 
-# query rows per workgroup of the two-direction screen (the column partials are per workgroup)
-WG_ROWS = 384
+# query rows per workgroup of the two-direction screen (the column partials are per workgroup):
+# four waves of seven 16-row tiles
+WG_ROWS = 448
 
 
 def _periodic_rows(n_rows, period=37, seed=41):
