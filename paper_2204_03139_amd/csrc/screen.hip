@@ -7,7 +7,7 @@
 // Each float coordinate is split exactly into three bf16 parts (x = h + m + l); the products
 // hH, hM, mH, hL, lH, mM per coordinate (18 K-slots) plus the two norms in three parts each (6
 // K-slots) fill 24 of the 32 K-slots, so the matrix unit produces the whole screened distance.
-// Rows a stay in registers (16-row tiles: seven per wave for both directions, four for one); the
+// Rows a stay in registers (16-row tiles: seven per wave for both directions, six for one); the
 // b operands (packed once per frame) stream through a double-buffered LDS stage.  Every 16x16
 // result tile feeds both directions with v_min3 only:
 //   rows (a -> b): each (lane, row) folds its column of every tile into a running minimum;
@@ -40,7 +40,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // tiling (overridable at build time for tuning sweeps)
 #ifndef DC_SCREEN_ATILES
-#define DC_SCREEN_ATILES 4
+#define DC_SCREEN_ATILES 6
 #endif
 #ifndef DC_SCREEN_STAGE
 #define DC_SCREEN_STAGE 256
@@ -53,10 +53,10 @@ constexpr int SC_THREADS = 64 * SC_WAVES;
 #ifndef DC_SCREEN_ATILES_COLS
 #define DC_SCREEN_ATILES_COLS 7
 #endif
-// 16-row query tiles per wave: the one-direction screen keeps three workgroups per compute unit
-// with four; the two-direction screen amortises its per-stage column reduction over seven tiles
-// (at two workgroups per compute unit, 239 registers; eight spill), which measured faster for it
-// and slower for the other
+// 16-row query tiles per wave, both screens at two workgroups per compute unit: six for the
+// one-direction screen (197 registers; four tiles at three workgroups per compute unit, five
+// and seven measured slower), seven for the two-direction screen, which amortises its per-stage
+// column reduction over them (239 registers; six measured slower, eight spill)
 template <bool COLS>
 constexpr int sc_atiles() { return COLS ? DC_SCREEN_ATILES_COLS : DC_SCREEN_ATILES; }
 template <bool COLS>
@@ -1258,7 +1258,8 @@ void register_screen_kernels(BatchedKernel *table) {
     // the same register bounds as the direct kernels so that they all stay resident
     table[KT_SCREEN] = batched_kernel<ScreenParams, screen_body<true>, SC_THREADS, 512,
                                       sc_atiles<true>() <= 4 ? 3 : 2>();
-    table[KT_SCREEN_ROWS] = batched_kernel<ScreenParams, screen_body<false>, SC_THREADS, 768,
+    table[KT_SCREEN_ROWS] = batched_kernel<ScreenParams, screen_body<false>, SC_THREADS,
+                                           sc_atiles<false>() <= 4 ? 768 : 512,
                                            sc_atiles<false>() <= 4 ? 3 : 2>();
     // six waves per SIMD (at most 80 registers, which the refine bodies need without spilling):
     // 1,536 blocks

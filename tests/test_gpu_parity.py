@@ -350,7 +350,8 @@ def test_chamfer_backward_ignores_out_of_range_neighbours():
 
 def _few_heavy(n, seed):
     """n x n points with a few queries the screen cannot settle in either direction: one row
-    point repeated in every 256-row workgroup (so the targets near it tie across all of them)
+    point repeated every 256 rows, so every row workgroup of either screen holds it (and the
+    targets near it tie across all of them),
     and one target point repeated in 16 different slot groups (so the rows near it have more
     candidate groups than the screen keeps)."""
     r = np.random.default_rng(seed)
