@@ -36,8 +36,8 @@ SCREEN_ISSUE_CEILING = CUS * SIMDS_PER_CU * PEAK_CLOCK_HZ / (5 * 4) * 256
 # valid only for the machine code they were measured on (sha256 of the kernel's bytes in the
 # built library's gfx950 code object).
 SCREEN_SYMBOL = "_ZN2dc12_GLOBAL__N_18k_screenILb1EEEvNS0_12ScreenParamsE"
-SCREEN_TRAFFIC = dict(code_sha256="8ca024817c93aa5c2c07098d42269b0d29d77f098277248f56b296a2ce052d56",
-                      bytes=1007707 * 1024 * 2 + 2086474 * 1024)
+SCREEN_TRAFFIC = dict(code_sha256="2b2d09a4bc2301a1a06e3d30f06b82e43131df2b13699fd1d503161ed3a412ec",
+                      bytes=739720 * 1024 * 2 + 1843269 * 1024)
 LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2204_03139_amd",
                    "libdiffcloud.so")
 

@@ -234,8 +234,8 @@ def test_chamfer_ties_and_identity(precision):
 
 
 # query rows per workgroup of the two-direction screen (the column partials are per workgroup):
-# four waves of seven 16-row tiles
-WG_ROWS = 448
+# four waves of eight 16-row tiles
+WG_ROWS = 512
 
 
 def _periodic_rows(n_rows, period=37, seed=41):
