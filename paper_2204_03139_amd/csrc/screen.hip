@@ -7,7 +7,7 @@
 // Each float coordinate is split exactly into three bf16 parts (x = h + m + l); the products
 // hH, hM, mH, hL, lH, mM per coordinate (18 K-slots) plus the two norms in three parts each (6
 // K-slots) fill 24 of the 32 K-slots, so the matrix unit produces the whole screened distance.
-// Rows a stay in registers (16-row tiles: eight per wave for both directions, six for one); the
+// Rows a stay in registers (16-row tiles: eight per wave); the
 // b operands (packed once per frame) stream through a double-buffered LDS stage.  Every 16x16
 // result tile feeds both directions with v_min3 only:
 //   rows (a -> b): each (lane, row) folds its column of every tile into a running minimum;
@@ -40,7 +40,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // tiling (overridable at build time for tuning sweeps)
 #ifndef DC_SCREEN_ATILES
-#define DC_SCREEN_ATILES 6
+#define DC_SCREEN_ATILES 8
 #endif
 #ifndef DC_SCREEN_STAGE
 #define DC_SCREEN_STAGE 256
@@ -53,11 +53,9 @@ constexpr int SC_THREADS = 64 * SC_WAVES;
 #ifndef DC_SCREEN_ATILES_COLS
 #define DC_SCREEN_ATILES_COLS 8
 #endif
-// 16-row query tiles per wave, both screens at two workgroups per compute unit: six for the
-// one-direction screen (197 registers; four tiles at three workgroups per compute unit, five
-// and seven measured slower), eight for the two-direction screen, which amortises its per-stage
-// column reduction over them (255 registers with one tile of lookahead; six and seven measured
-// slower)
+// 16-row query tiles per wave: eight in both screens, at two workgroups per compute unit (232
+// registers for one direction, 255 for both; fewer tiles measured slower in both, and the
+// two-direction screen amortises its per-stage column reduction over them)
 template <bool COLS>
 constexpr int sc_atiles() { return COLS ? DC_SCREEN_ATILES_COLS : DC_SCREEN_ATILES; }
 template <bool COLS>
@@ -519,12 +517,11 @@ __device__ __forceinline__ void screen_body(const ScreenParams &pr, const Blk &b
                 N1 = sb[(bt + 3) * SC_ROWPAD];
             }
             float cm0 = inf, cm1 = inf;
-            // issue order, written out: each query tile's two MFMAs go LA tiles ahead of the
+            // issue order, written out: each query tile's two MFMAs go one tile ahead of the
             // minima that read their results, so no minimum waits for the matrix unit (measured
             // faster than the compiler's order, also when it was steered by a one-tile scheduling
-            // hint).  One tile for the two-direction screen, whose eight tiles per wave leave no
-            // registers for a second; two for the one-direction screen.
-            constexpr int LA = COLS ? 1 : 2;
+            // hint; eight tiles per wave leave no registers for a second tile of lookahead)
+            constexpr int LA = 1;
             floatx4 d0[ATILES], d1[ATILES];
 #pragma unroll
             for (int a = 0; a < LA; ++a) {
